@@ -1,0 +1,246 @@
+"""FP64 CPU oracle of the synchrotron sightline march -- test infrastructure.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never touches it, and it shares no code with that path.
+
+The arithmetic lives in ``sync_oracle.c`` (plain C, FP64, no fast-math); this
+module is ctypes marshalling plus ``build()``.  Each C function cites the
+passage of Diao et al. (arXiv:2410.01136) it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sync_oracle.c")
+_LIB = os.path.join(_HERE, "libsync_oracle.so")
+
+MODEL16, GRID, SPHERE = 0, 1, 2
+NPARAM = 16
+MAX_FREQ = 16
+
+
+def build(quiet: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+           "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=quiet)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("r_obs", ctypes.c_double * 3), ("r_max", ctypes.c_double),
+                ("box_lo", ctypes.c_double * 3), ("box_hi", ctypes.c_double * 3),
+                ("n_freq", ctypes.c_int32), ("freq_hz", ctypes.c_double * MAX_FREQ)]
+
+
+class _Field(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("theta", ctypes.c_double * NPARAM),
+                ("grid_n", ctypes.c_int32 * 3), ("grid_lo", ctypes.c_double * 3),
+                ("grid_hi", ctypes.c_double * 3),
+                ("grid_bn", ctypes.c_void_p), ("grid_c", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    gp, fp = ctypes.POINTER(_Geom), ctypes.POINTER(_Field)
+    lib.or_forward.argtypes = [gp, fp, dp]
+    lib.or_forward_pixels.argtypes = [gp, fp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                      dp, dp]
+    lib.or_adjoint.argtypes = [gp, fp, dp, dp, dp, dp]
+    lib.or_pix2zphi_ring.argtypes = [ctypes.c_int32, ctypes.c_int64, dp, dp]
+    lib.or_zphi2pix_ring.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double]
+    lib.or_zphi2pix_ring.restype = ctypes.c_int64
+    lib.or_path_length.argtypes = [gp, dp]
+    lib.or_path_length.restype = ctypes.c_double
+    for name in ("or_j_I", "or_j_P"):
+        getattr(lib, name).argtypes = [ctypes.c_double] * 4
+        getattr(lib, name).restype = ctypes.c_double
+    lib.or_digamma.argtypes = [ctypes.c_double]
+    lib.or_digamma.restype = ctypes.c_double
+    lib.or_k_rm.restype = ctypes.c_double
+    lib.or_rj.argtypes = [ctypes.c_double]
+    lib.or_rj.restype = ctypes.c_double
+    lib.or_fields.argtypes = [fp, dp, dp, dp, dp]
+    lib.or_sample_model16.argtypes = [dp, ctypes.POINTER(ctypes.c_int32), dp, dp,
+                                      ctypes.c_void_p, ctypes.c_void_p]
+    lib.or_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_geom(nside, n_steps, freqs_hz, r_obs=(-8.5, 0.0, 0.0), r_max=math.inf,
+              box_lo=(-math.inf,) * 3, box_hi=(math.inf,) * 3) -> _Geom:
+    g = _Geom()
+    g.nside, g.n_steps = int(nside), int(n_steps)
+    g.r_obs[:] = [float(v) for v in r_obs]
+    g.r_max = float(r_max)
+    g.box_lo[:] = [float(v) for v in box_lo]
+    g.box_hi[:] = [float(v) for v in box_hi]
+    freqs = [float(v) for v in freqs_hz]
+    if not 1 <= len(freqs) <= MAX_FREQ:
+        raise ValueError("1..16 frequencies")
+    g.n_freq = len(freqs)
+    g.freq_hz[:len(freqs)] = freqs
+    return g
+
+
+class Field:
+    """Field description; keeps the grid arrays alive while in use."""
+
+    def __init__(self, kind, theta, grid_bn=None, grid_c=None, grid_lo=None, grid_hi=None):
+        self.s = _Field()
+        self.s.kind = int(kind)
+        th = np.asarray(theta, dtype=np.float64)
+        if th.shape != (NPARAM,):
+            raise ValueError("theta must have 16 entries")
+        self.s.theta[:] = th.tolist()
+        self.grid_bn = self.grid_c = None
+        if kind == GRID:
+            self.grid_bn = np.ascontiguousarray(grid_bn, dtype=np.float32)
+            if self.grid_bn.ndim != 4 or self.grid_bn.shape[3] != 4:
+                raise ValueError("grid_bn must be [nz][ny][nx][4]")
+            nz, ny, nx, _ = self.grid_bn.shape
+            self.s.grid_n[:] = [nx, ny, nz]
+            self.s.grid_lo[:] = [float(v) for v in grid_lo]
+            self.s.grid_hi[:] = [float(v) for v in grid_hi]
+            self.s.grid_bn = self.grid_bn.ctypes.data
+            if grid_c is not None:
+                self.grid_c = np.ascontiguousarray(grid_c, dtype=np.float32)
+                if self.grid_c.shape != (nz, ny, nx):
+                    raise ValueError("grid_c must be [nz][ny][nx]")
+                self.s.grid_c = self.grid_c.ctypes.data
+
+
+def forward(geom: _Geom, field: Field) -> np.ndarray:
+    """Full RING map [n_freq][3][npix] of (T_I, T_Q, T_U) in K, FP64."""
+    lib = _load()
+    npix = 12 * geom.nside ** 2
+    maps = np.zeros((geom.n_freq, 3, npix), dtype=np.float64)
+    if lib.or_forward(ctypes.byref(geom), ctypes.byref(field.s), _dptr(maps)) != 0:
+        raise ValueError("oracle rejected the geometry or field")
+    return maps
+
+
+def forward_pixels(geom: _Geom, field: Field, pix, want_phi=False):
+    """Selected pixels: [n][n_freq][3] in K (and the end Faraday depth)."""
+    lib = _load()
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    out = np.zeros((pix.size, geom.n_freq, 3), dtype=np.float64)
+    phi = np.zeros(pix.size, dtype=np.float64)
+    rc = lib.or_forward_pixels(ctypes.byref(geom), ctypes.byref(field.s),
+                               pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), pix.size,
+                               _dptr(out), _dptr(phi))
+    if rc != 0:
+        raise ValueError("oracle rejected the request")
+    return (out, phi) if want_phi else out
+
+
+def adjoint(geom: _Geom, field: Field, dmaps, want_grid=False):
+    """Gradient of sum(dmaps * maps): (dtheta[16], dgrid_bn, dgrid_c)."""
+    lib = _load()
+    dm = np.ascontiguousarray(dmaps, dtype=np.float64)
+    npix = 12 * geom.nside ** 2
+    if dm.shape != (geom.n_freq, 3, npix):
+        raise ValueError("dmaps must be [n_freq][3][npix]")
+    dth = np.zeros(NPARAM)
+    gbn = gc = None
+    nul = ctypes.POINTER(ctypes.c_double)()
+    if want_grid and field.s.kind == GRID:
+        nz, ny, nx, _ = field.grid_bn.shape
+        gbn = np.zeros((nz, ny, nx, 4))
+        gc = np.zeros((nz, ny, nx)) if field.grid_c is not None else None
+    rc = lib.or_adjoint(ctypes.byref(geom), ctypes.byref(field.s), _dptr(dm), _dptr(dth),
+                        _dptr(gbn) if gbn is not None else nul,
+                        _dptr(gc) if gc is not None else nul)
+    if rc != 0:
+        raise ValueError("oracle rejected the request")
+    return dth, gbn, gc
+
+
+def sample_model16(theta, n_xyz, lo, hi):
+    """Analytic 16-parameter model on a node-centred grid: (bn [nz][ny][nx][4], c)."""
+    lib = _load()
+    nx, ny, nz = (int(v) for v in n_xyz)
+    bn = np.zeros((nz, ny, nx, 4), dtype=np.float32)
+    c = np.zeros((nz, ny, nx), dtype=np.float32)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    n = (ctypes.c_int32 * 3)(nx, ny, nz)
+    lo_a = np.ascontiguousarray(lo, dtype=np.float64)
+    hi_a = np.ascontiguousarray(hi, dtype=np.float64)
+    if lib.or_sample_model16(_dptr(th), n, _dptr(lo_a), _dptr(hi_a), bn.ctypes.data,
+                             c.ctypes.data) != 0:
+        raise ValueError("bad grid shape")
+    return bn, c
+
+
+def pix2zphi(nside: int, p: int):
+    lib = _load()
+    z, phi = ctypes.c_double(), ctypes.c_double()
+    lib.or_pix2zphi_ring(int(nside), int(p), ctypes.byref(z), ctypes.byref(phi))
+    return z.value, phi.value
+
+
+def zphi2pix(nside: int, z: float, phi: float) -> int:
+    return int(_load().or_zphi2pix_ring(int(nside), float(z), float(phi)))
+
+
+def fields_at(field: Field, r):
+    lib = _load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    B = np.zeros(3)
+    ne, n0 = ctypes.c_double(), ctypes.c_double()
+    lib.or_fields(ctypes.byref(field.s), _dptr(r), _dptr(B),
+                  ctypes.cast(ctypes.byref(ne), ctypes.POINTER(ctypes.c_double)),
+                  ctypes.cast(ctypes.byref(n0), ctypes.POINTER(ctypes.c_double)))
+    return B, ne.value, n0.value
+
+
+def path_length(geom: _Geom, nhat) -> float:
+    n = np.ascontiguousarray(nhat, dtype=np.float64)
+    return _load().or_path_length(ctypes.byref(geom), _dptr(n))
+
+
+def j_I(alpha, nu, bt_gauss, n0):
+    return _load().or_j_I(alpha, nu, bt_gauss, n0)
+
+
+def j_P(alpha, nu, bt_gauss, n0):
+    return _load().or_j_P(alpha, nu, bt_gauss, n0)
+
+
+def digamma(x):
+    return _load().or_digamma(x)
+
+
+def k_rm():
+    return _load().or_k_rm()
+
+
+def rayleigh_jeans(nu):
+    return _load().or_rj(nu)
+
+
+def num_threads():
+    return _load().or_num_threads()

@@ -1,0 +1,725 @@
+/*
+ * FP64 CPU oracle of the synchrotron sightline march -- TEST INFRASTRUCTURE.
+ *
+ * This file is the plain, slow, obviously-correct reference that the GPU path
+ * is checked against.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it; the product path never does.  It
+ * shares no source, header, table or constant with the HIP library: every
+ * constant below is typed here on purpose.
+ *
+ * What it computes (Diao et al., "synax", arXiv:2410.01136):
+ *   - pixel centres of a HEALPix RING map (Gorski et al. 2005, the pixelisation
+ *     the paper uses through healpy; Sec. 2.3),
+ *   - the sightline from the observer to the box boundary split into N equal
+ *     segments sampled at their midpoints (Sec. 2.3, the integration-point
+ *     construction),
+ *   - the fields B, n_e, N0 at each midpoint (analytic model or trilinear
+ *     interpolation over a regular grid, Sec. 2.3),
+ *   - the emissivities j_I and j_P (Eqs. ji and jp, Sec. 2.1-2.2),
+ *   - the rotation measure as a running integral (Eq. rm) and the angle
+ *     chi = RM lambda^2 + chi_0 with chi_0 from Eq. chi (Sec. 2.2),
+ *   - the Riemann sums of Eq. int, then the Rayleigh-Jeans brightness
+ *     temperature (maps are in Kelvin, Fig. acc_func caption).
+ *   - the hand-derived reverse pass (gradient of sum(dmaps * maps) with
+ *     respect to the 16 analytic parameters and to grid voxels), which the
+ *     tests pin against central finite differences of this same forward.
+ *
+ * Readings of passages the paper leaves open (each is listed in the design doc):
+ *   - B_LOS is signed, B_par = -B.n (positive toward the observer); the paper
+ *     writes an absolute value, which would stop field reversals cancelling.
+ *   - The denominator of Eq. chi is read as -B.e_l = B_x sin l - B_y cos l
+ *     (the printed form is not a sky-plane component); the numerator is B.e_b.
+ *   - The RM at a midpoint is the sum of all earlier segments plus half of its
+ *     own segment (second-order midpoint prefix).
+ *   - Units: cgs inside the physics (B in gauss, lengths in cm, N0 and n_e in
+ *     cm^-3), positions in kpc, fields handed in as micro-gauss.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- physical constants, cgs, CODATA 2018 -------------------------------- */
+static const double OR_QE = 4.80320471e-10;      /* electron charge [esu]   */
+static const double OR_ME = 9.1093837015e-28;    /* electron mass [g]       */
+static const double OR_C = 2.99792458e10;        /* speed of light [cm/s]   */
+static const double OR_KB = 1.380649e-16;        /* Boltzmann [erg/K]       */
+static const double OR_PC = 3.0856775814913673e18; /* parsec [cm]           */
+static const double OR_PI = 3.14159265358979323846;
+
+#define OR_NPARAM 16
+#define OR_MAX_FREQ 16
+
+enum { OR_MODEL16 = 0, OR_GRID = 1, OR_SPHERE = 2 };
+
+/* Geometry and step schedule. */
+typedef struct {
+  int32_t nside;
+  int32_t n_steps;
+  double r_obs[3];     /* observer [kpc], Galactocentric Cartesian          */
+  double r_max;        /* cap on the sightline length [kpc]; may be +inf    */
+  double box_lo[3];    /* box faces [kpc]; +-inf allowed                    */
+  double box_hi[3];
+  int32_t n_freq;
+  double freq_hz[OR_MAX_FREQ];
+} or_geom;
+
+/* Field description. */
+typedef struct {
+  int32_t kind;
+  double theta[OR_NPARAM];
+  int32_t grid_n[3];   /* nx, ny, nz nodes                                  */
+  double grid_lo[3];   /* node-centred: first node on lo, last node on hi   */
+  double grid_hi[3];
+  const float* grid_bn; /* [nz][ny][nx][4] = Bx, By, Bz [uG], n_e [cm^-3]   */
+  const float* grid_c;  /* [nz][ny][nx] N0 [cm^-3], or NULL -> analytic N0  */
+} or_field;
+
+/* ========================================================================== */
+/* HEALPix RING pixel centres (Gorski et al. 2005)                           */
+/* ========================================================================== */
+
+/* Largest integer i with i*i <= v, for v >= 0. */
+static int64_t or_isqrt(int64_t v) {
+  int64_t r = (int64_t)sqrt((double)v);
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+/* Pixel p of a RING map -> (z = cos(colatitude), phi = longitude). */
+void or_pix2zphi_ring(int32_t nside, int64_t p, double* z, double* phi) {
+  const int64_t N = nside;
+  const int64_t npix = 12 * N * N;
+  const int64_t ncap = 2 * N * (N - 1);
+  if (p < ncap) {
+    /* north polar cap: ring i holds 4i pixels, 2i(i-1) pixels before it */
+    int64_t i = (1 + or_isqrt(1 + 2 * p)) / 2;
+    while (2 * i * (i - 1) > p) --i;
+    while (2 * (i + 1) * i <= p) ++i;
+    int64_t j = p - 2 * i * (i - 1) + 1;
+    *z = 1.0 - (double)(i * i) / (3.0 * (double)(N * N));
+    *phi = OR_PI / (2.0 * (double)i) * ((double)j - 0.5);
+  } else if (p < npix - ncap) {
+    /* equatorial belt: rings N..3N, 4N pixels each; rings alternate between
+       a pixel centred on phi = 0 and a half-pixel offset */
+    int64_t q = p - ncap;
+    int64_t i = q / (4 * N) + N;
+    int64_t j = q % (4 * N) + 1;
+    double shift = ((i + N) & 1) ? 1.0 : 0.5;
+    *z = 4.0 / 3.0 - 2.0 * (double)i / (3.0 * (double)N);
+    *phi = OR_PI / (2.0 * (double)N) * ((double)j - shift);
+  } else {
+    /* south polar cap, mirror of the north cap */
+    int64_t q = npix - p; /* 1-based count from the south pole end */
+    int64_t i = (1 + or_isqrt(2 * q - 1)) / 2;
+    while (2 * i * (i - 1) >= q) --i;
+    while (2 * (i + 1) * i < q) ++i;
+    int64_t j = 4 * i + 1 - (q - 2 * i * (i - 1));
+    *z = -(1.0 - (double)(i * i) / (3.0 * (double)(N * N)));
+    *phi = OR_PI / (2.0 * (double)i) * ((double)j - 0.5);
+  }
+}
+
+/* Inverse map (z, phi) -> RING pixel, written from the zone geometry of the
+   same paper; used only to pin pix2zphi by a round trip. */
+int64_t or_zphi2pix_ring(int32_t nside, double z, double phi) {
+  const int64_t N = nside;
+  const double twopi = 2.0 * OR_PI;
+  phi = fmod(phi, twopi);
+  if (phi < 0) phi += twopi;
+  double t = phi / (0.5 * OR_PI); /* in [0, 4) */
+  double za = fabs(z);
+  if (za <= 2.0 / 3.0) {
+    /* belt: two families of lines of constant jp, jm cut the zone */
+    int64_t jp = (int64_t)floor((double)N * (0.5 + t - 0.75 * z));
+    int64_t jm = (int64_t)floor((double)N * (0.5 + t + 0.75 * z));
+    int64_t ir = N + 1 + jp - jm; /* 1 .. 2N+1, counted from z = 2/3 */
+    int64_t kshift = 1 - (ir & 1);
+    int64_t ip = (jp + jm - N + kshift + 1) / 2;
+    ip = ((ip % (4 * N)) + 4 * N) % (4 * N);
+    return 2 * N * (N - 1) + (ir - 1) * 4 * N + ip;
+  } else {
+    double tp = t - floor(t);
+    double tmp = (double)N * sqrt(3.0 * (1.0 - za));
+    int64_t jp = (int64_t)floor(tp * tmp);
+    int64_t jm = (int64_t)floor((1.0 - tp) * tmp);
+    int64_t ir = jp + jm + 1; /* ring counted from the nearer pole */
+    int64_t ip = (int64_t)floor(t * (double)ir);
+    ip = ((ip % (4 * ir)) + 4 * ir) % (4 * ir);
+    if (z > 0) return 2 * ir * (ir - 1) + ip;
+    return 12 * N * N - 2 * ir * (ir + 1) + ip;
+  }
+}
+
+/* Galactic longitude l and latitude b of a pixel centre; the sightline unit
+   vector n = (cos b cos l, cos b sin l, sin b) with x from the Sun toward the
+   Galactic centre (Sec. 2.3: pixel coordinates {l_i, b_i}). */
+void or_pixel_lb(int32_t nside, int64_t p, double* l, double* b) {
+  double z, phi;
+  or_pix2zphi_ring(nside, p, &z, &phi);
+  *l = phi;
+  *b = asin(z);
+}
+
+/* ========================================================================== */
+/* Sightline construction (Sec. 2.3)                                         */
+/* ========================================================================== */
+
+/* Distance from the observer to the box boundary along n, capped at r_max. */
+double or_path_length(const or_geom* g, const double n[3]) {
+  double t = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    if (n[k] > 0.0 && isfinite(g->box_hi[k])) {
+      double tk = (g->box_hi[k] - g->r_obs[k]) / n[k];
+      if (tk < t) t = tk;
+    } else if (n[k] < 0.0 && isfinite(g->box_lo[k])) {
+      double tk = (g->box_lo[k] - g->r_obs[k]) / n[k];
+      if (tk < t) t = tk;
+    }
+  }
+  return (g->r_max < t) ? g->r_max : t;
+}
+
+/* ========================================================================== */
+/* Field models (Sec. 2.3: analytic callables or gridded interpolation)       */
+/* ========================================================================== */
+
+/*
+ * The 16-parameter axisymmetric model of the spiral-disk test configuration.
+ * theta: 0 B0[uG] 1 psi0 2 psi1 3 chiB0 4 R_B 5 z_B 6 BH0[uG] 7 z_H 8 R_H
+ *        9 C0[cm^-3] 10 hr_CR 11 hz_CR 12 alpha 13 n0[cm^-3] 14 hz_ne 15 kappa_ne
+ * Sun at R = 8.5 kpc.  The pitch psi is measured from the azimuthal direction,
+ * tan(psi) = B_rho / B_phi; the psi1 log-radius term and the tanh(z / 1 kpc)
+ * out-of-plane tilt take the forms of the paper's WMAP field (Sec. 3.1).
+ */
+static const double OR_RSUN = 8.5;
+static const double OR_RHO_MIN = 1e-3;
+
+void or_model16(const double* th, const double r[3], double B[3], double* ne, double* n0) {
+  const double x = r[0], y = r[1], z = r[2];
+  const double rho = sqrt(x * x + y * y);
+  const double rg = rho > OR_RHO_MIN ? rho : OR_RHO_MIN;
+  const double rhat[3] = {x / rg, y / rg, 0.0};
+  const double fhat[3] = {-y / rg, x / rg, 0.0};
+  const double az = fabs(z);
+
+  const double Ed = exp(-(rho - OR_RSUN) / th[4] - az / th[5]);
+  const double psi = th[1] + th[2] * log(rg / OR_RSUN);
+  const double chiB = th[3] * tanh(z);
+  const double sp = sin(psi), cp = cos(psi), sc = sin(chiB), cc = cos(chiB);
+  const double Eh = exp(-az / th[7] - (rho - OR_RSUN) / th[8]);
+  const double bh = th[6] * (z / th[7]) * Eh;
+  for (int k = 0; k < 3; ++k)
+    B[k] = th[0] * Ed * (sp * cc * rhat[k] + cp * cc * fhat[k]) + bh * fhat[k];
+  B[2] += th[0] * Ed * sc;
+  *n0 = th[9] * exp(-(rho - OR_RSUN) / th[10] - az / th[11]);
+  *ne = th[13] * exp(-az / th[14] - th[15] * (rho - OR_RSUN));
+}
+
+/* Vector-Jacobian product of or_model16 with respect to theta (adds into tb). */
+static void or_model16_vjp(const double* th, const double r[3], const double Bb[3], double neb,
+                           double n0b, double* tb) {
+  const double x = r[0], y = r[1], z = r[2];
+  const double rho = sqrt(x * x + y * y);
+  const double rg = rho > OR_RHO_MIN ? rho : OR_RHO_MIN;
+  const double rhat[3] = {x / rg, y / rg, 0.0};
+  const double fhat[3] = {-y / rg, x / rg, 0.0};
+  const double zhat[3] = {0.0, 0.0, 1.0};
+  const double az = fabs(z);
+  const double dR = rho - OR_RSUN;
+
+  const double Ed = exp(-dR / th[4] - az / th[5]);
+  const double lnr = log(rg / OR_RSUN);
+  const double psi = th[1] + th[2] * lnr;
+  const double tz = tanh(z);
+  const double chiB = th[3] * tz;
+  const double sp = sin(psi), cp = cos(psi), sc = sin(chiB), cc = cos(chiB);
+  const double Eh = exp(-az / th[7] - dR / th[8]);
+
+  double dir[3], dpsi[3], dchi[3];
+  for (int k = 0; k < 3; ++k) {
+    dir[k] = sp * cc * rhat[k] + cp * cc * fhat[k] + sc * zhat[k];
+    dpsi[k] = cp * cc * rhat[k] - sp * cc * fhat[k];
+    dchi[k] = -sp * sc * rhat[k] - cp * sc * fhat[k] + cc * zhat[k];
+  }
+  double bd = 0, bp = 0, bc = 0, bf = 0;
+  for (int k = 0; k < 3; ++k) {
+    bd += Bb[k] * dir[k];
+    bp += Bb[k] * dpsi[k];
+    bc += Bb[k] * dchi[k];
+    bf += Bb[k] * fhat[k];
+  }
+  const double disk = th[0] * Ed * bd; /* = Bbar . B_disk */
+  tb[0] += Ed * bd;
+  tb[1] += th[0] * Ed * bp;
+  tb[2] += th[0] * Ed * bp * lnr;
+  tb[3] += th[0] * Ed * bc * tz;
+  tb[4] += disk * dR / (th[4] * th[4]);
+  tb[5] += disk * az / (th[5] * th[5]);
+  /* halo: B_H0 (z / z_H) Eh fhat */
+  const double hal = th[6] * (z / th[7]) * Eh * bf; /* = Bbar . B_halo */
+  tb[6] += (z / th[7]) * Eh * bf;
+  tb[7] += th[6] * Eh * bf * (-z / (th[7] * th[7]) + (z / th[7]) * az / (th[7] * th[7]));
+  tb[8] += hal * dR / (th[8] * th[8]);
+  /* cosmic-ray normalisation */
+  const double Ec = exp(-dR / th[10] - az / th[11]);
+  const double n0 = th[9] * Ec;
+  tb[9] += n0b * Ec;
+  tb[10] += n0b * n0 * dR / (th[10] * th[10]);
+  tb[11] += n0b * n0 * az / (th[11] * th[11]);
+  /* thermal electrons */
+  const double En = exp(-az / th[14] - th[15] * dR);
+  const double ne = th[13] * En;
+  tb[13] += neb * En;
+  tb[14] += neb * ne * az / (th[14] * th[14]);
+  tb[15] += neb * (-ne * dR);
+}
+
+/* Homogeneous sphere (Sec. 2.4 test): uniform fields within radius R0 of a
+   centre, zero outside.  theta: 0-2 B [uG], 3 n_e, 4 N0, 5 R0 [kpc] (<= 0 means
+   everywhere), 6-8 centre [kpc], 12 alpha. */
+static void or_sphere(const double* th, const double r[3], double B[3], double* ne, double* n0) {
+  int inside = 1;
+  if (th[5] > 0.0) {
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) d2 += (r[k] - th[6 + k]) * (r[k] - th[6 + k]);
+    inside = d2 < th[5] * th[5];
+  }
+  for (int k = 0; k < 3; ++k) B[k] = inside ? th[k] : 0.0;
+  *ne = inside ? th[3] : 0.0;
+  *n0 = inside ? th[4] : 0.0;
+}
+
+/* Trilinear cell lookup on a node-centred grid.  Returns 0 outside the grid
+   box (fields are zero there), else fills the base node index and the eight
+   corner weights in the order (dx, dy, dz) = bit (0, 1, 2) of the corner. */
+static int or_grid_cell(const or_field* f, const double r[3], int64_t* base, int64_t stride[3],
+                        double w[8]) {
+  double t[3];
+  int64_t i[3];
+  for (int k = 0; k < 3; ++k) {
+    if (!(r[k] >= f->grid_lo[k] && r[k] <= f->grid_hi[k])) return 0;
+    const int64_t n = f->grid_n[k];
+    const double u = (r[k] - f->grid_lo[k]) / (f->grid_hi[k] - f->grid_lo[k]) * (double)(n - 1);
+    int64_t i0 = (int64_t)floor(u);
+    if (i0 < 0) i0 = 0;
+    if (i0 > n - 2) i0 = n - 2;
+    i[k] = i0;
+    t[k] = u - (double)i0;
+  }
+  stride[0] = 1;
+  stride[1] = f->grid_n[0];
+  stride[2] = (int64_t)f->grid_n[0] * f->grid_n[1];
+  *base = i[0] + i[1] * stride[1] + i[2] * stride[2];
+  for (int c = 0; c < 8; ++c) {
+    double wc = 1.0;
+    for (int k = 0; k < 3; ++k) wc *= ((c >> k) & 1) ? t[k] : 1.0 - t[k];
+    w[c] = wc;
+  }
+  return 1;
+}
+
+static int64_t or_corner(int64_t base, const int64_t s[3], int c) {
+  return base + ((c & 1) ? s[0] : 0) + ((c & 2) ? s[1] : 0) + ((c & 4) ? s[2] : 0);
+}
+
+/* Field values at r: B [uG], n_e and N0 [cm^-3]. */
+void or_fields(const or_field* f, const double r[3], double B[3], double* ne, double* n0) {
+  if (f->kind == OR_MODEL16) {
+    or_model16(f->theta, r, B, ne, n0);
+  } else if (f->kind == OR_SPHERE) {
+    or_sphere(f->theta, r, B, ne, n0);
+  } else {
+    int64_t base, s[3];
+    double w[8];
+    B[0] = B[1] = B[2] = 0.0;
+    *ne = 0.0;
+    *n0 = 0.0;
+    double Bm[3], nem, n0m;
+    if (f->grid_c == NULL) { /* analytic cosmic-ray normalisation */
+      or_model16(f->theta, r, Bm, &nem, &n0m);
+      *n0 = n0m;
+    }
+    if (!or_grid_cell(f, r, &base, s, w)) {
+      if (f->grid_c != NULL) *n0 = 0.0;
+      return;
+    }
+    for (int c = 0; c < 8; ++c) {
+      const int64_t v = or_corner(base, s, c);
+      for (int k = 0; k < 3; ++k) B[k] += w[c] * (double)f->grid_bn[4 * v + k];
+      *ne += w[c] * (double)f->grid_bn[4 * v + 3];
+      if (f->grid_c != NULL) *n0 += w[c] * (double)f->grid_c[v];
+    }
+  }
+}
+
+/* ========================================================================== */
+/* Emissivities (Sec. 2.1 Eq. ji, Sec. 2.2 Eq. jp)                           */
+/* ========================================================================== */
+
+/* Eq. ji, literally, in cgs: B_trans [gauss], N0 [cm^-3], nu [Hz]. */
+double or_j_I(double alpha, double nu, double bt, double n0) {
+  if (bt <= 0.0) return 0.0;
+  const double pre = sqrt(3.0) * pow(OR_QE, 3) * bt * n0 / (8.0 * OR_PI * OR_ME * OR_C * OR_C);
+  const double brk = pow(4.0 * OR_PI * nu * OR_ME * OR_C / (3.0 * OR_QE * bt), (1.0 - alpha) / 2.0);
+  return pre * brk * pow(2.0, (alpha + 1.0) / 2.0) / (alpha + 1.0) *
+         tgamma(alpha / 4.0 - 1.0 / 12.0) * tgamma(alpha / 4.0 + 19.0 / 12.0);
+}
+
+/* Eq. jp, literally. */
+double or_j_P(double alpha, double nu, double bt, double n0) {
+  if (bt <= 0.0) return 0.0;
+  const double pre = sqrt(3.0) * pow(OR_QE, 3) * bt * n0 / (8.0 * OR_PI * OR_ME * OR_C * OR_C);
+  const double brk = pow(4.0 * OR_PI * nu * OR_ME * OR_C / (3.0 * OR_QE * bt), (1.0 - alpha) / 2.0);
+  return pre * brk * pow(2.0, (alpha - 3.0) / 2.0) * tgamma(alpha / 4.0 - 1.0 / 12.0) *
+         tgamma(alpha / 4.0 + 7.0 / 12.0);
+}
+
+/* Digamma by upward recurrence to x >= 12 and the asymptotic series
+   psi(x) = ln x - 1/(2x) - sum_k B_2k / (2k x^2k) (Abramowitz & Stegun 6.3.18). */
+double or_digamma(double x) {
+  double acc = 0.0;
+  while (x < 12.0) {
+    acc -= 1.0 / x;
+    x += 1.0;
+  }
+  const double x2 = 1.0 / (x * x);
+  const double series =
+      x2 * (1.0 / 12.0 - x2 * (1.0 / 120.0 - x2 * (1.0 / 252.0 - x2 * (1.0 / 240.0 - x2 * (1.0 / 132.0)))));
+  return acc + log(x) - 0.5 / x - series;
+}
+
+/* d ln j_I / d alpha and d ln j_P / d alpha at fixed B_trans [gauss]; the
+   bracket of Eqs. ji/jp already holds B_trans, so no separate ln B term. */
+static void or_dlnj_dalpha(double alpha, double nu, double bt, double* dI, double* dP) {
+  const double lb = log(4.0 * OR_PI * nu * OR_ME * OR_C / (3.0 * OR_QE * bt));
+  const double common = -0.5 * lb + 0.25 * or_digamma(alpha / 4.0 - 1.0 / 12.0);
+  *dI = common + 0.5 * log(2.0) - 1.0 / (alpha + 1.0) + 0.25 * or_digamma(alpha / 4.0 + 19.0 / 12.0);
+  *dP = common + 0.5 * log(2.0) + 0.25 * or_digamma(alpha / 4.0 + 7.0 / 12.0);
+}
+
+/* Rotation-measure constant of Eq. rm, q^3 / (2 pi m^2 c^4), cgs. */
+double or_k_rm(void) { return pow(OR_QE, 3) / (2.0 * OR_PI * OR_ME * OR_ME * pow(OR_C, 4)); }
+
+/* Rayleigh-Jeans conversion of a specific intensity to Kelvin. */
+double or_rj(double nu) { return OR_C * OR_C / (2.0 * OR_KB * nu * nu); }
+
+/* ========================================================================== */
+/* One sightline                                                              */
+/* ========================================================================== */
+
+typedef struct {
+  double nhat[3], el[3], eb[3];
+  double L, dkpc, dcm;
+} or_ray;
+
+static void or_make_ray(const or_geom* g, int64_t p, or_ray* ray) {
+  double l, b;
+  or_pixel_lb(g->nside, p, &l, &b);
+  ray->nhat[0] = cos(b) * cos(l);
+  ray->nhat[1] = cos(b) * sin(l);
+  ray->nhat[2] = sin(b);
+  ray->el[0] = -sin(l);
+  ray->el[1] = cos(l);
+  ray->el[2] = 0.0;
+  ray->eb[0] = -sin(b) * cos(l);
+  ray->eb[1] = -sin(b) * sin(l);
+  ray->eb[2] = cos(b);
+  ray->L = or_path_length(g, ray->nhat);
+  ray->dkpc = ray->L / (double)g->n_steps;
+  ray->dcm = ray->dkpc * 1e3 * OR_PC;
+}
+
+static void or_midpoint(const or_geom* g, const or_ray* ray, int n, double r[3]) {
+  const double s = ((double)n + 0.5) * ray->dkpc; /* n is 0-based here */
+  for (int k = 0; k < 3; ++k) r[k] = g->r_obs[k] + s * ray->nhat[k];
+}
+
+/* Per-step local quantities the sums need. */
+typedef struct {
+  double Bt;     /* |B_trans| [gauss]                      */
+  double num;    /* B . e_b [gauss]  (numerator of Eq. chi) */
+  double den;    /* -B . e_l [gauss] (denominator, reading) */
+  double blos;   /* -B . n [gauss]                          */
+  double ne, n0; /* [cm^-3]                                 */
+  double chi0;
+} or_local;
+
+static void or_local_eval(const or_field* f, const or_ray* ray, const double r[3], or_local* q) {
+  double B[3], ne, n0;
+  or_fields(f, r, B, &ne, &n0);
+  double bl = 0, bb = 0, bn = 0;
+  for (int k = 0; k < 3; ++k) {
+    bl += B[k] * ray->el[k];
+    bb += B[k] * ray->eb[k];
+    bn += B[k] * ray->nhat[k];
+  }
+  q->num = 1e-6 * bb;
+  q->den = -1e-6 * bl;
+  q->blos = -1e-6 * bn;
+  q->Bt = sqrt(q->num * q->num + q->den * q->den);
+  q->ne = ne;
+  q->n0 = n0;
+  q->chi0 = atan2(q->num, q->den);
+}
+
+/* Forward march of one pixel: out[f][3] = T_I, T_Q, T_U [K]; returns the
+   total Faraday depth sum of the segment increments [rad cm^-2]. */
+static double or_march_pixel(const or_geom* g, const or_field* f, int64_t p, double* out) {
+  or_ray ray;
+  or_make_ray(g, p, &ray);
+  const double alpha = f->theta[12];
+  const double krm = or_k_rm();
+  double I[OR_MAX_FREQ] = {0}, Q[OR_MAX_FREQ] = {0}, U[OR_MAX_FREQ] = {0};
+  double rm_before = 0.0; /* integral of n_e B_LOS over all earlier segments */
+  for (int n = 0; n < g->n_steps; ++n) {
+    double r[3];
+    or_midpoint(g, &ray, n, r);
+    or_local q;
+    or_local_eval(f, &ray, r, &q);
+    const double seg = q.ne * q.blos * ray.dcm;
+    const double RM = krm * (rm_before + 0.5 * seg);
+    rm_before += seg;
+    for (int k = 0; k < g->n_freq; ++k) {
+      const double nu = g->freq_hz[k];
+      const double lam = OR_C / nu;
+      const double jI = or_j_I(alpha, nu, q.Bt, q.n0);
+      const double jP = or_j_P(alpha, nu, q.Bt, q.n0);
+      const double chi = RM * lam * lam + q.chi0;
+      I[k] += jI * ray.dcm;
+      Q[k] += jP * cos(2.0 * chi) * ray.dcm;
+      U[k] += jP * sin(2.0 * chi) * ray.dcm;
+    }
+  }
+  for (int k = 0; k < g->n_freq; ++k) {
+    const double rj = or_rj(g->freq_hz[k]);
+    out[3 * k + 0] = rj * I[k];
+    out[3 * k + 1] = rj * Q[k];
+    out[3 * k + 2] = rj * U[k];
+  }
+  return krm * rm_before;
+}
+
+static int or_check(const or_geom* g, const or_field* f) {
+  if (g->nside < 1 || g->n_steps < 1 || g->n_freq < 1 || g->n_freq > OR_MAX_FREQ) return -1;
+  if (f->kind != OR_MODEL16 && f->kind != OR_GRID && f->kind != OR_SPHERE) return -1;
+  if (f->kind == OR_GRID && (f->grid_bn == NULL || f->grid_n[0] < 2 || f->grid_n[1] < 2 ||
+                             f->grid_n[2] < 2))
+    return -1;
+  return 0;
+}
+
+/* Full RING map: maps[f][3][npix] in K (double). */
+int or_forward(const or_geom* g, const or_field* f, double* maps) {
+  if (or_check(g, f)) return -1;
+  const int64_t npix = 12LL * g->nside * g->nside;
+  const int nf = g->n_freq;
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < npix; ++p) {
+    double out[3 * OR_MAX_FREQ];
+    or_march_pixel(g, f, p, out);
+    for (int k = 0; k < nf; ++k)
+      for (int s = 0; s < 3; ++s) maps[((int64_t)k * 3 + s) * npix + p] = out[3 * k + s];
+  }
+  return 0;
+}
+
+/* Selected pixels: out[i][f][3] for pixel pix[i]; phi_end[i] may be NULL. */
+int or_forward_pixels(const or_geom* g, const or_field* f, const int64_t* pix, int64_t n,
+                      double* out, double* phi_end) {
+  if (or_check(g, f)) return -1;
+  const int64_t npix = 12LL * g->nside * g->nside;
+  for (int64_t i = 0; i < n; ++i)
+    if (pix[i] < 0 || pix[i] >= npix) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; ++i) {
+    double ph = or_march_pixel(g, f, pix[i], out + i * 3 * g->n_freq);
+    if (phi_end) phi_end[i] = ph;
+  }
+  return 0;
+}
+
+/* ========================================================================== */
+/* Reverse pass: gradient of L = sum(dmaps * maps)                           */
+/* ========================================================================== */
+
+/* Adds the gradient of one pixel's contribution.  dm[f][3] are the cotangents
+   of (T_I, T_Q, T_U) at this pixel.  Grid gradients go to gbn ([v][4]) and gc
+   ([v]) when non-NULL; theta gradients to tb[16]. */
+static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, const double* dm,
+                             double* tb, double* gbn, double* gc) {
+  or_ray ray;
+  or_make_ray(g, p, &ray);
+  const int N = g->n_steps;
+  const double alpha = f->theta[12];
+  const double krm = or_k_rm();
+  or_local* q = (or_local*)malloc(sizeof(or_local) * (size_t)N);
+  double* RM = (double*)malloc(sizeof(double) * (size_t)N);
+  double* rmb = (double*)malloc(sizeof(double) * (size_t)N); /* dL/dRM_n */
+  /* forward sweep, keeping the per-step quantities */
+  double before = 0.0;
+  for (int n = 0; n < N; ++n) {
+    double r[3];
+    or_midpoint(g, &ray, n, r);
+    or_local_eval(f, &ray, r, &q[n]);
+    const double seg = q[n].ne * q[n].blos * ray.dcm;
+    RM[n] = krm * (before + 0.5 * seg);
+    before += seg;
+  }
+  /* local cotangents of j_I, j_P, chi at every step; dL/dRM_n */
+  double* jIb = (double*)calloc((size_t)N * OR_MAX_FREQ, sizeof(double));
+  double* jPb = (double*)calloc((size_t)N * OR_MAX_FREQ, sizeof(double));
+  double* chi0b = (double*)calloc((size_t)N, sizeof(double));
+  for (int n = 0; n < N; ++n) {
+    rmb[n] = 0.0;
+    for (int k = 0; k < g->n_freq; ++k) {
+      const double nu = g->freq_hz[k];
+      const double lam = OR_C / nu;
+      const double rj = or_rj(nu);
+      const double jP = or_j_P(alpha, nu, q[n].Bt, q[n].n0);
+      const double chi = RM[n] * lam * lam + q[n].chi0;
+      const double gI = dm[3 * k + 0] * rj * ray.dcm;
+      const double gQ = dm[3 * k + 1] * rj * ray.dcm;
+      const double gU = dm[3 * k + 2] * rj * ray.dcm;
+      jIb[n * OR_MAX_FREQ + k] = gI;
+      jPb[n * OR_MAX_FREQ + k] = gQ * cos(2.0 * chi) + gU * sin(2.0 * chi);
+      const double chib = jP * (-2.0 * gQ * sin(2.0 * chi) + 2.0 * gU * cos(2.0 * chi));
+      chi0b[n] += chib;
+      rmb[n] += chib * lam * lam;
+    }
+  }
+  /* RM_n = krm (sum_{m<n} seg_m + seg_n / 2): dL/dseg_m */
+  double suffix = 0.0; /* sum over n > m of dL/dRM_n */
+  for (int n = N - 1; n >= 0; --n) {
+    const double segb = krm * (suffix + 0.5 * rmb[n]);
+    suffix += rmb[n];
+    /* seg = ne * blos * dcm */
+    const double neb_seg = segb * q[n].blos * ray.dcm;
+    const double blosb = segb * q[n].ne * ray.dcm;
+    /* j_I, j_P depend on Bt, n0 (and alpha); chi0 = atan2(num, den) */
+    double Btb = 0.0, n0b = 0.0, ab = 0.0;
+    for (int k = 0; k < g->n_freq; ++k) {
+      const double nu = g->freq_hz[k];
+      if (q[n].Bt <= 0.0) continue;
+      const double jI = or_j_I(alpha, nu, q[n].Bt, q[n].n0);
+      const double jP = or_j_P(alpha, nu, q[n].Bt, q[n].n0);
+      const double gI = jIb[n * OR_MAX_FREQ + k], gP = jPb[n * OR_MAX_FREQ + k];
+      /* j ~ Bt^{(alpha+1)/2} n0 */
+      Btb += (gI * jI + gP * jP) * (alpha + 1.0) / (2.0 * q[n].Bt);
+      if (q[n].n0 != 0.0) {
+        n0b += (gI * jI + gP * jP) / q[n].n0;
+      } else {
+        n0b += gI * or_j_I(alpha, nu, q[n].Bt, 1.0) + gP * or_j_P(alpha, nu, q[n].Bt, 1.0);
+      }
+      double dI, dP;
+      or_dlnj_dalpha(alpha, nu, q[n].Bt, &dI, &dP);
+      ab += gI * jI * dI + gP * jP * dP;
+    }
+    double numb = 0.0, denb = 0.0;
+    if (q[n].Bt > 0.0) {
+      const double bt2 = q[n].Bt * q[n].Bt;
+      numb = Btb * q[n].num / q[n].Bt + chi0b[n] * q[n].den / bt2;
+      denb = Btb * q[n].den / q[n].Bt - chi0b[n] * q[n].num / bt2;
+    }
+    tb[12] += ab;
+    /* num = 1e-6 B.e_b, den = -1e-6 B.e_l, blos = -1e-6 B.n  (B in uG) */
+    double Bb[3];
+    for (int k = 0; k < 3; ++k)
+      Bb[k] = 1e-6 * (numb * ray.eb[k] - denb * ray.el[k] - blosb * ray.nhat[k]);
+    double r[3];
+    or_midpoint(g, &ray, n, r);
+    if (f->kind == OR_MODEL16) {
+      or_model16_vjp(f->theta, r, Bb, neb_seg, n0b, tb);
+    } else if (f->kind == OR_GRID) {
+      if (f->grid_c == NULL) {
+        const double zero3[3] = {0, 0, 0};
+        or_model16_vjp(f->theta, r, zero3, 0.0, n0b, tb);
+      }
+      int64_t base, s[3];
+      double w[8];
+      if (or_grid_cell(f, r, &base, s, w)) {
+        for (int c = 0; c < 8; ++c) {
+          const int64_t v = or_corner(base, s, c);
+          if (gbn) {
+            for (int k = 0; k < 3; ++k) gbn[4 * v + k] += w[c] * Bb[k];
+            gbn[4 * v + 3] += w[c] * neb_seg;
+          }
+          if (gc && f->grid_c != NULL) gc[v] += w[c] * n0b;
+        }
+      }
+    }
+  }
+  free(q);
+  free(RM);
+  free(rmb);
+  free(jIb);
+  free(jPb);
+  free(chi0b);
+}
+
+/*
+ * Gradient of L = sum_{f,s,p} dmaps[f][s][p] * maps[f][s][p] (maps from
+ * or_forward) with respect to theta (dtheta[16], may be NULL) and, for grid
+ * fields, the grid values (dgrid_bn [nz][ny][nx][4], dgrid_c [nz][ny][nx]; each
+ * may be NULL).  Serial over pixels so that the sums are in a fixed order.
+ */
+int or_adjoint(const or_geom* g, const or_field* f, const double* dmaps, double* dtheta,
+               double* dgrid_bn, double* dgrid_c) {
+  if (or_check(g, f)) return -1;
+  const int64_t npix = 12LL * g->nside * g->nside;
+  const int nf = g->n_freq;
+  double tb[OR_NPARAM] = {0};
+  int64_t nv = 0;
+  if (f->kind == OR_GRID) nv = (int64_t)f->grid_n[0] * f->grid_n[1] * f->grid_n[2];
+  if (dgrid_bn) memset(dgrid_bn, 0, sizeof(double) * 4 * (size_t)nv);
+  if (dgrid_c) memset(dgrid_c, 0, sizeof(double) * (size_t)nv);
+  for (int64_t p = 0; p < npix; ++p) {
+    double dm[3 * OR_MAX_FREQ];
+    int any = 0;
+    for (int k = 0; k < nf; ++k)
+      for (int s = 0; s < 3; ++s) {
+        dm[3 * k + s] = dmaps[((int64_t)k * 3 + s) * npix + p];
+        any |= dm[3 * k + s] != 0.0;
+      }
+    if (any) or_adjoint_pixel(g, f, p, dm, tb, dgrid_bn, dgrid_c);
+  }
+  if (dtheta)
+    for (int k = 0; k < OR_NPARAM; ++k) dtheta[k] = tb[k];
+  return 0;
+}
+
+/* The analytic 16-parameter model sampled on the nodes of a grid:
+   out_bn [nz][ny][nx][4], out_c [nz][ny][nx] (either may be NULL). */
+int or_sample_model16(const double* theta, const int32_t n[3], const double lo[3],
+                      const double hi[3], float* out_bn, float* out_c) {
+  if (n[0] < 2 || n[1] < 2 || n[2] < 2) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t iz = 0; iz < n[2]; ++iz)
+    for (int64_t iy = 0; iy < n[1]; ++iy)
+      for (int64_t ix = 0; ix < n[0]; ++ix) {
+        const double r[3] = {lo[0] + (hi[0] - lo[0]) * (double)ix / (double)(n[0] - 1),
+                             lo[1] + (hi[1] - lo[1]) * (double)iy / (double)(n[1] - 1),
+                             lo[2] + (hi[2] - lo[2]) * (double)iz / (double)(n[2] - 1)};
+        double B[3], ne, n0;
+        or_model16(theta, r, B, &ne, &n0);
+        const int64_t v = ix + n[0] * (iy + n[1] * iz);
+        if (out_bn) {
+          for (int k = 0; k < 3; ++k) out_bn[4 * v + k] = (float)B[k];
+          out_bn[4 * v + 3] = (float)ne;
+        }
+        if (out_c) out_c[v] = (float)n0;
+      }
+  return 0;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

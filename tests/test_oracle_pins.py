@@ -1,0 +1,409 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Every test here checks the oracle against something other than itself: values
+the paper prints (tests/golden), closed forms of special cases, invariants,
+and textbook functions (mpmath).  A plausible slip anywhere in the oracle --
+a dropped factor, a sign, a transposed index -- fails at least one of them.
+"""
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+from paper_2410_01136_amd import inputs as I
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+QE, ME, C, KB, PC = 4.80320471e-10, 9.1093837015e-28, 2.99792458e10, 1.380649e-16, 3.0856775814913673e18
+
+
+def geom(orc, g: I.Geometry):
+    return orc.make_geom(g.nside, g.n_steps, g.freqs_hz, g.r_obs, g.r_max, g.box_lo, g.box_hi)
+
+
+def unit_vectors(orc, nside, p):
+    z, phi = orc.pix2zphi(nside, p)
+    l, b = phi, math.asin(z)
+    n = np.array([math.cos(b) * math.cos(l), math.cos(b) * math.sin(l), math.sin(b)])
+    el = np.array([-math.sin(l), math.cos(l), 0.0])
+    eb = np.array([-math.sin(b) * math.cos(l), -math.sin(b) * math.sin(l), math.cos(b)])
+    return n, el, eb
+
+
+# --------------------------------------------------------------------------- HEALPix
+
+def test_healpix_nside1_golden(orc):
+    rows = np.loadtxt(os.path.join(GOLD, "healpix_nside1.txt"))
+    for p, z, phi_pi in rows:
+        z2, phi2 = orc.pix2zphi(1, int(p))
+        assert z2 == pytest.approx(z, abs=1e-15)
+        assert phi2 / math.pi == pytest.approx(phi_pi, abs=1e-15)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 8, 16, 32])
+def test_healpix_structure(orc, nside):
+    npix = 12 * nside * nside
+    zphi = np.array([orc.pix2zphi(nside, p) for p in range(npix)])
+    # round trip through the independently written inverse
+    back = [orc.zphi2pix(nside, z, ph) for z, ph in zphi]
+    assert back == list(range(npix))
+    # 4N-1 rings, 4i / 4N pixels per ring, ring z-values of the zone formulas
+    zs, counts = np.unique(np.round(zphi[:, 0], 13), return_counts=True)
+    assert len(zs) == 4 * nside - 1
+    zs = zs[::-1]  # north to south
+    for i, (zv, cnt) in enumerate(zip(zs, counts[::-1]), start=1):
+        if i < nside:
+            assert cnt == 4 * i and zv == pytest.approx(1 - i * i / (3 * nside * nside), abs=1e-12)
+        elif i <= 3 * nside:
+            assert cnt == 4 * nside and zv == pytest.approx(4 / 3 - 2 * i / (3 * nside), abs=1e-12)
+        else:
+            j = 4 * nside - i
+            assert cnt == 4 * j and zv == pytest.approx(-(1 - j * j / (3 * nside * nside)), abs=1e-12)
+    # equal-area pixels on a sphere: the centres balance, sum of n = 0
+    st = np.sqrt(1 - zphi[:, 0] ** 2)
+    v = np.stack([st * np.cos(zphi[:, 1]), st * np.sin(zphi[:, 1]), zphi[:, 0]], 1)
+    assert np.abs(v.sum(0)).max() < 1e-10 * npix
+    # mirror bijections b -> -b and l -> -l
+    north_south = sorted(orc.zphi2pix(nside, -z, ph) for z, ph in zphi)
+    east_west = sorted(orc.zphi2pix(nside, z, -ph) for z, ph in zphi)
+    assert north_south == list(range(npix)) and east_west == list(range(npix))
+
+
+# --------------------------------------------------------------------------- constants
+
+def test_rm_constant_golden(orc):
+    gold = json.load(open(os.path.join(GOLD, "constants.json")))
+    k_si = orc.k_rm() * 1e-6 * PC * 1e4  # rad cm^-2 per (cm^-3 G cm) -> rad m^-2 per (cm^-3 uG pc)
+    assert k_si == pytest.approx(gold["k_rm_rad_m2_per_cm3_uG_pc"], abs=5e-4)
+    assert k_si == pytest.approx(0.8119012, rel=1e-6)
+
+
+def test_emissivity_alpha3_closed_form(orc):
+    # at alpha = 3 Eq. ji reduces to 3 sqrt3 q^4 B^2 N0 Gamma(2/3) Gamma(7/3) / (32 pi^2 m^2 c^3 nu)
+    for B, n0, nu in [(6e-6, 4e-5, 1e9), (3e-6, 1e-5, 2.4e9), (1e-5, 2e-5, 4.08e8)]:
+        ref = (3 * mpmath.sqrt(3) * mpmath.mpf(QE) ** 4 * mpmath.mpf(B) ** 2 * n0 *
+               mpmath.gamma(mpmath.mpf(2) / 3) * mpmath.gamma(mpmath.mpf(7) / 3) /
+               (32 * mpmath.pi ** 2 * mpmath.mpf(ME) ** 2 * mpmath.mpf(C) ** 3 * nu))
+        assert orc.j_I(3.0, nu, B, n0) == pytest.approx(float(ref), rel=1e-13)
+
+
+@pytest.mark.parametrize("alpha", [2.2, 2.5, 3.0, 3.5, 4.1])
+def test_polarisation_fraction_identity(orc, alpha):
+    # Gamma(x + 1) = x Gamma(x) turns Eq. jp / Eq. ji into (alpha + 1) / (alpha + 7/3)
+    r = orc.j_P(alpha, 1.4e9, 5e-6, 3e-5) / orc.j_I(alpha, 1.4e9, 5e-6, 3e-5)
+    assert r == pytest.approx((alpha + 1) / (alpha + 7 / 3), rel=1e-13)
+    gold = json.load(open(os.path.join(GOLD, "constants.json")))
+    if alpha == 3.0:
+        assert r == pytest.approx(gold["pol_fraction_alpha3"], rel=1e-13)
+
+
+def test_emissivity_power_laws(orc):
+    # j ~ B^{(alpha+1)/2} nu^{(1-alpha)/2} N0, from Eq. ji
+    a = 2.7
+    base = orc.j_I(a, 1e9, 4e-6, 3e-5)
+    assert orc.j_I(a, 1e9, 8e-6, 3e-5) / base == pytest.approx(2 ** ((a + 1) / 2), rel=1e-13)
+    assert orc.j_I(a, 3e9, 4e-6, 3e-5) / base == pytest.approx(3 ** ((1 - a) / 2), rel=1e-13)
+    assert orc.j_I(a, 1e9, 4e-6, 6e-5) / base == pytest.approx(2.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("x", [0.1, 0.5, 0.6666, 1.0, 1.75, 3.3, 13.0, 40.0])
+def test_digamma(orc, x):
+    assert orc.digamma(x) == pytest.approx(float(mpmath.digamma(x)), rel=1e-13, abs=1e-14)
+
+
+def test_rayleigh_jeans(orc):
+    assert orc.rayleigh_jeans(1e9) == pytest.approx(C * C / (2 * KB * 1e18), rel=1e-15)
+
+
+def test_e1_intensity_value(orc):
+    # B_perp = 6 uG sightlines of the sphere test: T_I = RJ * j_I * R0 = 0.2649 K at 2.4 GHz
+    t = orc.rayleigh_jeans(2.4e9) * orc.j_I(3.0, 2.4e9, 6e-6, 4.01e-5) * 4e3 * PC
+    assert t == pytest.approx(0.26491, rel=1e-4)
+
+
+# --------------------------------------------------------------------------- geometry
+
+def test_path_length_box_and_cap(orc):
+    g = orc.make_geom(4, 8, [1e9], r_obs=(-8.5, 0, 0), r_max=math.inf,
+                      box_lo=(-20, -20, -4), box_hi=(20, 20, 4))
+    assert orc.path_length(g, [1, 0, 0]) == pytest.approx(28.5)
+    assert orc.path_length(g, [-1, 0, 0]) == pytest.approx(11.5)
+    assert orc.path_length(g, [0, 0, 1]) == pytest.approx(4.0)
+    d = np.array([1.0, 1.0, 0.0]) / math.sqrt(2)
+    assert orc.path_length(g, d) == pytest.approx(20 * math.sqrt(2))
+    g2 = orc.make_geom(4, 8, [1e9], r_obs=(-8.5, 0, 0), r_max=20.0)
+    assert orc.path_length(g2, [0, 0, 1]) == 20.0
+
+
+# --------------------------------------------------------------------------- closed forms
+
+def uniform_field(orc, B, ne, n0, alpha=3.0):
+    return orc.Field(orc.SPHERE, I.sphere_theta(B_uG=B, ne=ne, n0=n0, R0_kpc=0.0, alpha=alpha))
+
+
+def test_uniform_slab_intensity(orc):
+    # uniform fields, fixed length L: I = j_I L exactly (Eq. int with constant j)
+    B = np.array([3.0, -2.0, 1.5])
+    g = orc.make_geom(4, 37, [1e9, 3e9], r_max=7.0)
+    m = orc.forward(g, uniform_field(orc, B, 0.02, 3e-5, alpha=2.6))
+    for p in range(0, 192, 7):
+        n, el, eb = unit_vectors(orc, 4, p)
+        bt = math.hypot(B @ el, B @ eb) * 1e-6
+        for k, nu in enumerate([1e9, 3e9]):
+            ref = orc.rayleigh_jeans(nu) * orc.j_I(2.6, nu, bt, 3e-5) * 7.0 * 1e3 * PC
+            assert m[k, 0, p] == pytest.approx(ref, rel=1e-13)
+
+
+def test_no_faraday_polarisation_fraction(orc):
+    # n_e = 0, uniform B: PI / I = (alpha + 1)/(alpha + 7/3) = 0.75 at alpha = 3 and the
+    # angle is chi_0 of Eq. chi: tan(chi0) = B.e_b / (-B.e_l)
+    B = np.array([2.0, 5.0, -3.0])
+    g = orc.make_geom(8, 16, [1e9], r_max=5.0)
+    m = orc.forward(g, uniform_field(orc, B, 0.0, 4e-5))[0]
+    pi = np.hypot(m[1], m[2])
+    assert np.allclose(pi / m[0], 0.75, rtol=1e-13)
+    for p in range(0, 768, 11):
+        n, el, eb = unit_vectors(orc, 8, p)
+        chi0 = math.atan2(B @ eb, -(B @ el))
+        assert math.atan2(m[2, p], m[1, p]) == pytest.approx(
+            math.remainder(2 * chi0, 2 * math.pi), abs=1e-12)
+
+
+def test_polarised_fraction_bound_any_field(orc):
+    th = I.THETA0.copy()
+    th[13] = 0.0  # no thermal electrons
+    th[2], th[3], th[6] = 0.3, 0.4, 2.0
+    g = orc.make_geom(8, 64, [1e9], r_max=20.0)
+    m = orc.forward(g, orc.Field(orc.MODEL16, th))[0]
+    assert np.all(np.hypot(m[1], m[2]) <= 0.75 * m[0] * (1 + 1e-13))
+
+
+def test_discrete_burn_slab(orc):
+    # uniform B and n_e: phi_n = (n + 1/2) a, so the sum of Eq. int is a geometric series:
+    # P = j_P dr e^{2 i chi0} (e^{2i Phi} - 1) / (2 i sin(Phi / N)), Phi = lambda^2 RM_total
+    B = np.array([1.0, 4.0, 2.0])
+    ne, n0, L, N, nu = 0.03, 4e-5, 6.0, 64, 1.0e9
+    g = orc.make_geom(4, N, [nu], r_max=L)
+    m = orc.forward(g, uniform_field(orc, B, ne, n0))[0]
+    lam2 = (C / nu) ** 2
+    for p in range(0, 192, 5):
+        n, el, eb = unit_vectors(orc, 4, p)
+        blos = -(B @ n) * 1e-6
+        bt = math.hypot(B @ el, B @ eb) * 1e-6
+        chi0 = math.atan2(B @ eb, -(B @ el))
+        dr = L / N * 1e3 * PC
+        Phi = lam2 * orc.k_rm() * ne * blos * L * 1e3 * PC
+        s = (np.exp(2j * Phi) - 1) / (2j * math.sin(Phi / N)) if abs(Phi) > 1e-12 else N
+        P = orc.j_P(3.0, nu, bt, n0) * dr * np.exp(2j * chi0) * s * orc.rayleigh_jeans(nu)
+        assert m[1, p] == pytest.approx(P.real, abs=1e-12 * abs(P) + 1e-300)
+        assert m[2, p] == pytest.approx(P.imag, abs=1e-12 * abs(P) + 1e-300)
+
+
+@pytest.mark.slow
+def test_e1_sphere_discrete_and_paper_residuals(orc):
+    """Sec. 2.4 sphere: exact discrete sums, and residual std vs the analytic maps."""
+    gold = json.load(open(os.path.join(GOLD, "e1_sphere_residual_std.json")))
+    gI = I.geometry("E1")
+    g = geom(orc, gI)
+    th = I.sphere_theta()
+    m = orc.forward(g, orc.Field(orc.SPHERE, th))[0]
+    nu = gI.freqs_hz[0]
+    lam2 = (C / nu) ** 2
+    rj = orc.rayleigh_jeans(nu)
+    B = th[0:3]
+    R0 = th[5]
+    ana = np.zeros_like(m)
+    for p in range(gI.npix):
+        n, el, eb = unit_vectors(orc, gI.nside, p)
+        L = orc.path_length(g, n)
+        dkpc = L / gI.n_steps
+        k = int(np.sum((np.arange(gI.n_steps) + 0.5) * dkpc < R0))  # midpoints inside
+        blos = -(B @ n) * 1e-6
+        bt = math.hypot(B @ el, B @ eb) * 1e-6
+        chi0 = math.atan2(B @ eb, -(B @ el))
+        jI, jP = orc.j_I(3.0, nu, bt, th[4]), orc.j_P(3.0, nu, bt, th[4])
+        a = lam2 * orc.k_rm() * th[3] * blos * dkpc * 1e3 * PC
+        disc = np.exp(2j * chi0) * np.exp(2j * a * (np.arange(k) + 0.5)).sum() * dkpc * 1e3 * PC * jP
+        assert m[0, p] == pytest.approx(rj * jI * k * dkpc * 1e3 * PC, rel=1e-12)
+        assert abs(m[1, p] + 1j * m[2, p] - rj * disc) <= 1e-11 * abs(disc) * rj + 1e-18
+        Phi = lam2 * orc.k_rm() * th[3] * blos * R0 * 1e3 * PC
+        fac = (np.exp(2j * Phi) - 1) / (2j * Phi) if Phi != 0 else 1.0
+        P = rj * jP * R0 * 1e3 * PC * np.exp(2j * chi0) * fac
+        ana[:, p] = [rj * jI * R0 * 1e3 * PC, P.real, P.imag]
+    std = (m - ana).std(axis=1)
+    # I: the paper's residual is the sphere-edge discretisation, reproduced to 10%
+    assert std[0] == pytest.approx(gold["std_I_K"], rel=0.10)
+    # Q, U: same order as the paper's (its RM discretisation is not stated)
+    assert gold["std_Q_K"] / 3 < std[1] < gold["std_Q_K"] * 1.5
+    assert gold["std_U_K"] / 3 < std[2] < gold["std_U_K"] * 1.5
+    # residuals below 1% of the signal scale and below 1 mK (Sec. 2.4)
+    assert np.abs(m - ana).max() < 1e-3
+
+
+def test_spectrum_power_law(orc):
+    # without Faraday rotation T ~ nu^{(1-alpha)/2} / nu^2 = nu^{-(alpha+3)/2} on every pixel
+    th = I.THETA0.copy()
+    th[13] = 0.0
+    th[12] = 2.8
+    g = orc.make_geom(4, 48, [1e9, 2.3e9, 5e9], r_max=20.0)
+    m = orc.forward(g, orc.Field(orc.MODEL16, th))
+    for k, nu in enumerate([2.3e9, 5e9], start=1):
+        ratio = (nu / 1e9) ** (-(2.8 + 3) / 2)
+        for s in range(3):
+            assert np.allclose(m[k, s], m[0, s] * ratio, rtol=1e-12, atol=1e-30)
+
+
+def test_faraday_vanishes_at_high_frequency(orc):
+    th = I.THETA0.copy()
+    g_hi = orc.make_geom(4, 48, [1e15], r_max=20.0)  # lambda^2 phi ~ 3e-9 rad
+    m_rot = orc.forward(g_hi, orc.Field(orc.MODEL16, th))[0]
+    th0 = th.copy()
+    th0[13] = 0.0
+    m_free = orc.forward(g_hi, orc.Field(orc.MODEL16, th0))[0]
+    assert np.allclose(m_rot, m_free, rtol=1e-5, atol=1e-9 * np.abs(m_free).max())
+
+
+# --------------------------------------------------------------------------- symmetries
+
+def mirror_index(orc, nside, which):
+    out = []
+    for p in range(12 * nside * nside):
+        z, ph = orc.pix2zphi(nside, p)
+        out.append(orc.zphi2pix(nside, -z, ph) if which == "b" else orc.zphi2pix(nside, z, -ph))
+    return np.array(out)
+
+
+def test_mirror_l_with_pitch_flip(orc):
+    # the mirror y -> -y composed with B -> -B maps the model with (psi0, psi1, chiB0)
+    # onto the model with all three negated (the halo term is unchanged); B -> -B
+    # keeps I and chi_0 and flips RM, so I is equal and P -> conj(P) on l -> -l
+    # with Faraday rotation on
+    th = I.THETA0.copy()
+    th[2], th[3], th[6] = 0.2, 0.3, 1.0
+    thm = th.copy()
+    thm[1], thm[2], thm[3] = -th[1], -th[2], -th[3]
+    g = orc.make_geom(8, 64, [1e9], r_max=20.0)
+    a = orc.forward(g, orc.Field(orc.MODEL16, th))[0]
+    b = orc.forward(g, orc.Field(orc.MODEL16, thm))[0]
+    mi = mirror_index(orc, 8, "l")
+    scale = np.abs(a).max()
+    assert np.allclose(a[0], b[0][mi], rtol=1e-12, atol=1e-14 * scale)
+    assert np.allclose(a[1], b[1][mi], rtol=1e-12, atol=1e-12 * scale)
+    assert np.allclose(a[2], -b[2][mi], rtol=1e-12, atol=1e-12 * scale)
+
+
+def test_mirror_b_even_field_no_faraday(orc):
+    # z-even field with B_z = 0 and n_e = 0: b -> -b keeps I and conjugates P
+    th = I.THETA0.copy()
+    th[13] = 0.0
+    g = orc.make_geom(8, 64, [1e9], r_max=20.0)
+    a = orc.forward(g, orc.Field(orc.MODEL16, th))[0]
+    mi = mirror_index(orc, 8, "b")
+    scale = np.abs(a).max()
+    assert np.allclose(a[0], a[0][mi], rtol=1e-12, atol=1e-14 * scale)
+    assert np.allclose(a[1], a[1][mi], rtol=1e-12, atol=1e-12 * scale)
+    assert np.allclose(a[2], -a[2][mi], rtol=1e-12, atol=1e-12 * scale)
+    # with thermal electrons the even field breaks the symmetry (RM keeps its sign)
+    th[13] = 0.03
+    c = orc.forward(g, orc.Field(orc.MODEL16, th))[0]
+    assert not np.allclose(c[2], -c[2][mi], rtol=1e-6, atol=1e-6 * scale)
+
+
+def test_mirror_b_odd_field_with_faraday(orc):
+    # a purely z-odd field (halo only): b -> -b flips B_par and B.e_l, so chi -> -chi even with n_e
+    th = I.THETA0.copy()
+    th[0] = 0.0
+    th[6] = 3.0
+    g = orc.make_geom(8, 64, [1e9], r_max=20.0)
+    a = orc.forward(g, orc.Field(orc.MODEL16, th))[0]
+    mi = mirror_index(orc, 8, "b")
+    scale = np.abs(a).max()
+    assert np.allclose(a[0], a[0][mi], rtol=1e-12, atol=1e-14 * scale)
+    assert np.allclose(a[1], a[1][mi], rtol=1e-11, atol=1e-11 * scale)
+    assert np.allclose(a[2], -a[2][mi], rtol=1e-11, atol=1e-11 * scale)
+
+
+# --------------------------------------------------------------------------- convergence
+
+def test_step_convergence_second_order(orc):
+    # smooth integrands: the midpoint sums converge as N^-2, so the Richardson ratio
+    # (M_N - M_2N) / (M_2N - M_4N) tends to 4
+    th = I.THETA0.copy()
+    ms = []
+    for N in (256, 512, 1024):
+        g = orc.make_geom(4, N, [1e9], r_max=20.0)
+        ms.append(orc.forward(g, orc.Field(orc.MODEL16, th))[0])
+    d1, d2 = ms[0] - ms[1], ms[1] - ms[2]
+    big = np.abs(d2[0]) > 1e-6 * np.abs(ms[2][0]).max()
+    ratio = d1[0][big] / d2[0][big]
+    assert np.median(ratio) == pytest.approx(4.0, abs=0.3)
+    # Faraday-free polarisation converges the same way
+    th[13] = 0.0
+    ms = []
+    for N in (128, 256, 512):
+        g = orc.make_geom(4, N, [1e9], r_max=20.0)
+        ms.append(orc.forward(g, orc.Field(orc.MODEL16, th))[0])
+    d1, d2 = ms[0] - ms[1], ms[1] - ms[2]
+    big = np.abs(d2[1]) > 1e-6 * np.abs(ms[2][1]).max()
+    assert np.median(d1[1][big] / d2[1][big]) == pytest.approx(4.0, abs=0.3)
+
+
+# --------------------------------------------------------------------------- grids
+
+def test_trilinear_reproduces_linear_fields(orc):
+    # node values of a linear function are exact in float32 here, so trilinear
+    # interpolation must return the linear function itself
+    nx, ny, nz = 9, 5, 3
+    lo, hi = (0.0, 0.0, 0.0), (8.0, 4.0, 2.0)
+    xs, ys, zs = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="xy")
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+
+    def lin(x, y, z):
+        return np.stack([1 + 2 * x - y + 0.5 * z, -3 + 0.25 * x + y, 2 * z - x, 0.5 + 0.125 * x + 0.25 * y],
+                        -1)
+
+    bn = lin(xx.astype(float), yy.astype(float), zz.astype(float)).astype(np.float32)
+    c = (1.0 + xx + 2 * yy - zz).astype(np.float32)
+    f = orc.Field(orc.GRID, I.THETA0, grid_bn=bn, grid_c=c, grid_lo=lo, grid_hi=hi)
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        r = rng.uniform(lo, hi)
+        B, ne, n0 = orc.fields_at(f, r)
+        ref = lin(*r)
+        assert np.allclose(B, ref[:3], rtol=1e-13, atol=1e-13)
+        assert ne == pytest.approx(ref[3], rel=1e-13)
+        assert n0 == pytest.approx(1.0 + r[0] + 2 * r[1] - r[2], rel=1e-12, abs=1e-12)
+    # outside the box the fields vanish
+    B, ne, n0 = orc.fields_at(f, [8.5, 1.0, 1.0])
+    assert np.all(B == 0) and ne == 0 and n0 == 0
+
+
+def test_grid_map_converges_to_analytic(orc):
+    # Sec. 4.1: maps from a grid sampled from the analytic model approach the analytic
+    # map as the grid is refined (second order for trilinear interpolation)
+    g = orc.make_geom(4, 128, [1.4e9], box_lo=I.BOX_LO, box_hi=I.BOX_HI)
+    ana = orc.forward(g, orc.Field(orc.MODEL16, I.THETA0))[0]
+    errs = []
+    for n in (33, 65, 129):
+        nz = (n - 1) // 4 + 1
+        bn, c = orc.sample_model16(I.THETA0, (n, n, nz), I.BOX_LO, I.BOX_HI)
+        f = orc.Field(orc.GRID, I.THETA0, grid_bn=bn, grid_c=c, grid_lo=I.BOX_LO, grid_hi=I.BOX_HI)
+        errs.append(np.std(orc.forward(g, f)[0][0] - ana[0]))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] / errs[2] > 2.5  # close to 4 once the grid resolves the disk
+
+
+def test_grid_with_analytic_cr_matches_model(orc):
+    # a grid sampled from the model, with analytic N0, reproduces the model at the nodes
+    n = (9, 9, 5)
+    bn, c = orc.sample_model16(I.THETA0, n, I.BOX_LO, I.BOX_HI)
+    f = orc.Field(orc.GRID, I.THETA0, grid_bn=bn, grid_c=None, grid_lo=I.BOX_LO, grid_hi=I.BOX_HI)
+    fm = orc.Field(orc.MODEL16, I.THETA0)
+    for r in ([-5.0, 5.0, 0.0], [10.0, -15.0, 2.0], [0.0, 0.0, -4.0]):
+        B, ne, n0 = orc.fields_at(f, r)
+        Bm, nem, n0m = orc.fields_at(fm, r)
+        assert np.allclose(B, Bm, rtol=1e-6, atol=1e-6)
+        assert ne == pytest.approx(nem, rel=1e-6)
+        assert n0 == n0m
