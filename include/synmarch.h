@@ -1,0 +1,217 @@
+/*
+ * synmarch -- MI355X (gfx950) sightline march for Galactic synchrotron maps.
+ *
+ * C ABI of the hot path of Diao et al., "synax: a differentiable and
+ * GPU-accelerated synchrotron simulation package" (arXiv:2410.01136):
+ * for every HEALPix pixel a sightline from the observer is cut into N equal
+ * segments sampled at their midpoints (Sec. 2.3); the fields B, n_e and the
+ * cosmic-ray normalisation N0 are evaluated there, analytically or by trilinear
+ * interpolation of a regular grid (Sec. 2.3); the emissivities of Eqs. ji and
+ * jp (Sec. 2.1-2.2), the rotation measure of Eq. rm as a running sum and the
+ * angle chi = RM lambda^2 + chi_0 of Eq. chi give the sums of Eq. int, which
+ * are returned as Rayleigh-Jeans brightness temperatures in K.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked (device) are HIP device pointers; everything else is host.
+ *    The caller owns every buffer.  Only syn_batch_create allocates device
+ *    memory (freed by syn_batch_destroy).
+ *  - Calls are ordered on the given stream and return before the GPU work
+ *    ends.  All argument checks run on the host before any launch; on a
+ *    non-OK status nothing has been launched and no output was written.
+ *  - No C++ exception crosses the ABI.  syn_last_error() returns a
+ *    thread-local description of the last failing call.
+ *  - Positions are Galactocentric Cartesian in kpc: x from the Sun toward the
+ *    Galactic centre, y toward l = 90 deg, z toward b = 90 deg.  B is in
+ *    micro-gauss, n_e and N0 in cm^-3, frequencies in Hz.
+ *  - Maps are float [n_freq][3][npix], Stokes (I, Q, U) in K, HEALPix RING
+ *    order.  Q and U follow Eq. int with chi_0 measured from Galactic north
+ *    toward increasing l (tan chi_0 = B.e_b / (-B.e_l)); B_LOS is signed,
+ *    -B.n, positive toward the observer; the RM at a midpoint includes half of
+ *    its own segment.
+ */
+#ifndef SYNMARCH_H
+#define SYNMARCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SYN_OK = 0,
+  SYN_EINVAL = -1,        /* an argument failed validation                 */
+  SYN_EUNSUPPORTED = -2,  /* valid request the library does not implement  */
+  SYN_ENOMEM = -3,        /* device allocation failed (batch plans only)   */
+  SYN_EHIP = -4,          /* a HIP runtime call failed                     */
+  SYN_EWORKSPACE = -5     /* workspace missing or too small                */
+} syn_status;
+
+enum {
+  SYN_FIELD_MODEL16 = 0, /* 16-parameter analytic spiral-disk model         */
+  SYN_FIELD_GRID = 1,    /* trilinear interpolation of node-centred grids   */
+  SYN_FIELD_SPHERE = 2,  /* homogeneous sphere (Sec. 2.4 test)              */
+  SYN_FIELD_MLP = 3      /* coordinate-MLP surrogate of the fields          */
+};
+
+enum { SYN_NPARAM = 16, SYN_MAX_FREQ = 16, SYN_MAX_NSIDE = 8192 };
+
+/* Geometry and step schedule (Sec. 2.3).  The sightline of every pixel runs
+   from r_obs to the first box face it meets, capped at r_max, and is cut into
+   n_steps equal segments sampled at their midpoints. */
+typedef struct syn_geom {
+  int32_t nside;                /* power of two, 1 .. SYN_MAX_NSIDE          */
+  int32_t n_steps;              /* >= 1                                      */
+  double r_obs_kpc[3];          /* observer, strictly inside the box         */
+  double r_max_kpc;             /* > 0; +inf: box only                       */
+  double box_lo_kpc[3];         /* box faces; +-inf allowed, but every       */
+  double box_hi_kpc[3];         /* sightline must end at a finite length     */
+  int32_t n_freq;               /* 1 .. SYN_MAX_FREQ                         */
+  double freq_hz[SYN_MAX_FREQ]; /* > 0                                       */
+} syn_geom;
+
+/* Field-model descriptor (Sec. 2.3: a callable field generator, analytic or
+   gridded).  theta[12] is the CR power-law index alpha (> 1/3, the pole of
+   Gamma(alpha/4 - 1/12) in Eq. ji) for every kind.
+   MODEL16 theta: 0 B0[uG] 1 psi0 2 psi1 3 chiB0 [rad] 4 R_B 5 z_B [kpc]
+     6 BH0[uG] 7 z_H 8 R_H [kpc] 9 C0[cm^-3] 10 hr_CR 11 hz_CR [kpc] 12 alpha
+     13 n0[cm^-3] 14 hz_ne[kpc] 15 kappa_ne[1/kpc]; Sun at R = 8.5 kpc.
+       B = B0 e^{-(R-8.5)/R_B - |z|/z_B} (sin psi cos chi rho^ + cos psi cos chi
+           phi^ + sin chi z^), psi = psi0 + psi1 ln(R/8.5), chi = chiB0 tanh(z)
+         + BH0 (z/z_H) e^{-|z|/z_H - (R-8.5)/R_H} phi^,
+       N0 = C0 e^{-(R-8.5)/hr - |z|/hz},  n_e = n0 e^{-|z|/hz_ne - kappa (R-8.5)}.
+   GRID: grid_bn (device) float [nz][ny][nx][4] = (Bx, By, Bz, n_e); grid_c
+     (device) float [nz][ny][nx] = N0, or NULL for N0 from the MODEL16 formula
+     with theta[9..11].  Node i of an axis sits at lo + i (hi - lo) / (n - 1);
+     outside [lo, hi] every gridded field is zero.  At least 2 nodes per axis.
+   SPHERE theta: 0-2 B[uG] 3 n_e 4 N0 5 radius[kpc] (<= 0: everywhere)
+     6-8 centre[kpc]; fields are uniform inside, zero outside.
+   MLP: mlp (device) packed weights from syn_mlp_pack; grid_lo/hi give the box
+     the network's input coordinates are normalised to. */
+typedef struct syn_field {
+  int32_t kind;
+  double theta[SYN_NPARAM];
+  int32_t grid_n[3];            /* nx, ny, nz                                 */
+  double grid_lo_kpc[3];
+  double grid_hi_kpc[3];
+  const float* grid_bn;         /* (device)                                   */
+  const float* grid_c;          /* (device) or NULL                           */
+  const void* mlp;              /* (device)                                   */
+} syn_field;
+
+/* Bytes of workspace syn_forward needs; with_adjoint != 0 adds what the
+   matching syn_adjoint reads (the Faraday sum of every sightline, 8 B per
+   pixel, plus per-block gradient partials).  Returns 0 for invalid input. */
+size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t with_adjoint);
+
+/* Forward march: maps (device) float [n_freq][3][npix] in K.  ws (device) may
+   be NULL (ws_bytes 0) when no adjoint will follow; otherwise it must hold
+   syn_workspace_bytes(geom, field, 1) bytes and is read by syn_adjoint. */
+syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps, void* ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+/* Reverse pass of syn_forward: given dmaps (device) = dL/dmaps, float
+   [n_freq][3][npix], returns dL/dtheta in dtheta (device, double[16], written,
+   not accumulated; may be NULL) and, for GRID fields, ADDS dL/dgrid into
+   dgrid_bn (device, float [nz][ny][nx][4]) and dgrid_c (device, float
+   [nz][ny][nx]) when non-NULL (atomic float adds: bitwise order may vary).
+   ws must be the workspace of the syn_forward call with the same geom and
+   field.  Sightlines are recomputed in reverse step order; the Faraday sum is
+   rebuilt from its stored total, so no per-step state is stored. */
+syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float* dmaps,
+                       void* ws, size_t ws_bytes, double* dtheta, float* dgrid_bn,
+                       float* dgrid_c, hipStream_t stream);
+
+/* Gaussian chi^2 of Sec. 3.1 extended to I, Q and U:
+   chi2 = sum_m inv_sigma2[m] sum_p (maps[m][p] - target[m][p])^2 over n_maps
+   maps of n_pix values, and dmaps = d chi2 / d maps (device, float; may be
+   NULL).  chi2 is a device double[1], summed in FP64 in a fixed order.
+   inv_sigma2 is host, double[n_maps] (finite, >= 0).  ws (device) holds
+   syn_chi2_workspace_bytes(n_pix, n_maps) bytes of partial sums. */
+size_t syn_chi2_workspace_bytes(int64_t n_pix, int32_t n_maps);
+syn_status syn_chi2(int64_t n_pix, int32_t n_maps, const float* maps, const float* target,
+                    const double* inv_sigma2, float* dmaps, double* chi2, void* ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/* The MODEL16 fields sampled on the nodes of a grid: out_bn (device) float
+   [nz][ny][nx][4] = (Bx, By, Bz, n_e) and out_c (device) float [nz][ny][nx]
+   = N0 (either may be NULL).  n = (nx, ny, nz), each >= 2. */
+syn_status syn_sample_model16(const double* theta, const int32_t n[3], const double lo[3],
+                              const double hi[3], float* out_bn, float* out_c,
+                              hipStream_t stream);
+
+/* Field values at n points (device float [n][3], kpc): out (device) float
+   [n][5] = (Bx, By, Bz, n_e, N0).  Any field kind. */
+syn_status syn_eval_fields(const syn_field* field, int64_t n, const float* xyz, float* out,
+                           hipStream_t stream);
+
+/* ---- coordinate-MLP surrogate of the fields ------------------------------ */
+/* Network: x^ = 2 (r - lo) / (hi - lo) - 1; features sin(2 pi b_k . x^),
+   cos(2 pi b_k . x^) for 16 frequency vectors b_k; 4 hidden layers of width
+   128 with exact-erf GELU; a linear output of 5 = (Bx, By, Bz [uG],
+   ln n_e, ln N0).  Weights are BF16 with FP32 biases; products accumulate in
+   FP32 on the matrix cores.  syn_mlp_pack converts host FP32 arrays
+   (w_in [128][32], b_in [128], w_h [3][128][128], b_h [3][128], w_out
+   [5][128], b_out [5], fourier [16][3]) into the packed device layout;
+   syn_mlp_packed_bytes gives its size. */
+size_t syn_mlp_packed_bytes(void);
+syn_status syn_mlp_pack(const float* fourier, const float* w_in, const float* b_in,
+                        const float* w_h, const float* b_h, const float* w_out,
+                        const float* b_out, void* packed_host);
+
+/* ---- many parameter sets in one persistent launch ------------------------ */
+/* A batch is n_sets MODEL16 parameter vectors, each with its own N_side,
+   sharing one geometry (steps, observer, cap, box, frequency).  One plan runs
+   forward, chi^2 against per-set targets and the adjoint for every set in a
+   single captured HIP graph of persistent work-queue kernels. */
+typedef struct syn_batch_desc {
+  int32_t n_sets;
+  const int32_t* nside;        /* [n_sets], powers of two                       */
+  const double* theta;         /* [n_sets][16]                                  */
+  syn_geom geom;               /* nside ignored; one frequency                  */
+} syn_batch_desc;
+
+typedef struct syn_batch syn_batch;
+
+/* Creates a plan; allocates its device tables.  Pixel p of set s lives at
+   offset syn_batch_offset(plan, s) + p of the ragged map arrays, which hold
+   syn_batch_total_pixels(plan) pixels per Stokes map ([3][total]). */
+syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan);
+int64_t syn_batch_total_pixels(const syn_batch* plan);
+int64_t syn_batch_offset(const syn_batch* plan, int32_t set);
+/* Runs forward, chi^2 with inv_sigma2 (host double[3]) against target (device
+   float [3][total]) and the adjoint.  Outputs (device): maps float [3][total],
+   dmaps float [3][total], chi2 double [n_sets], dtheta double [n_sets][16].
+   The first call captures the graph on stream; later calls replay it and
+   must pass the same pointers. */
+syn_status syn_batch_run(syn_batch* plan, const float* target, const double* inv_sigma2,
+                         float* maps, float* dmaps, double* chi2, double* dtheta,
+                         hipStream_t stream);
+void syn_batch_destroy(syn_batch* plan);
+
+/* ---- launch shapes --------------------------------------------------------- */
+/* Kernel families tuned by the autotuner. */
+enum { SYN_KERNEL_FORWARD = 0, SYN_KERNEL_ADJOINT = 1, SYN_KERNEL_BATCH = 2 };
+
+/* Lanes per sightline S (1, 4, 16 or 64): consecutive steps of one sightline
+   are spread over S lanes and their Faraday sums are combined with a
+   wavefront prefix scan.  0 restores the built-in choice.  Applies to the
+   given (kernel, field kind) pair on the calling process. */
+syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lanes);
+int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix);
+
+const char* syn_last_error(void);
+int32_t syn_version(void);
+
+/* Host-side copy of the pixel ordering the kernels use, for checks without a
+   GPU: the RING index, z = cos(colatitude) and longitude of NESTED pixel q. */
+syn_status syn_host_nest_pixel(int32_t nside, int64_t q, int64_t* ring, double* z, double* phi);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYNMARCH_H */

@@ -645,10 +645,17 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
         for (int c = 0; c < 8; ++c) {
           const int64_t v = or_corner(base, s, c);
           if (gbn) {
-            for (int k = 0; k < 3; ++k) gbn[4 * v + k] += w[c] * Bb[k];
+            for (int k = 0; k < 3; ++k) {
+#pragma omp atomic
+              gbn[4 * v + k] += w[c] * Bb[k];
+            }
+#pragma omp atomic
             gbn[4 * v + 3] += w[c] * neb_seg;
           }
-          if (gc && f->grid_c != NULL) gc[v] += w[c] * n0b;
+          if (gc && f->grid_c != NULL) {
+#pragma omp atomic
+            gc[v] += w[c] * n0b;
+          }
         }
       }
     }
@@ -665,7 +672,8 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
  * Gradient of L = sum_{f,s,p} dmaps[f][s][p] * maps[f][s][p] (maps from
  * or_forward) with respect to theta (dtheta[16], may be NULL) and, for grid
  * fields, the grid values (dgrid_bn [nz][ny][nx][4], dgrid_c [nz][ny][nx]; each
- * may be NULL).  Serial over pixels so that the sums are in a fixed order.
+ * may be NULL).  Pixels run in parallel; each thread keeps its own theta sums
+ * and grid contributions are added atomically.
  */
 int or_adjoint(const or_geom* g, const or_field* f, const double* dmaps, double* dtheta,
                double* dgrid_bn, double* dgrid_c) {
@@ -677,15 +685,22 @@ int or_adjoint(const or_geom* g, const or_field* f, const double* dmaps, double*
   if (f->kind == OR_GRID) nv = (int64_t)f->grid_n[0] * f->grid_n[1] * f->grid_n[2];
   if (dgrid_bn) memset(dgrid_bn, 0, sizeof(double) * 4 * (size_t)nv);
   if (dgrid_c) memset(dgrid_c, 0, sizeof(double) * (size_t)nv);
-  for (int64_t p = 0; p < npix; ++p) {
-    double dm[3 * OR_MAX_FREQ];
-    int any = 0;
-    for (int k = 0; k < nf; ++k)
-      for (int s = 0; s < 3; ++s) {
-        dm[3 * k + s] = dmaps[((int64_t)k * 3 + s) * npix + p];
-        any |= dm[3 * k + s] != 0.0;
-      }
-    if (any) or_adjoint_pixel(g, f, p, dm, tb, dgrid_bn, dgrid_c);
+#pragma omp parallel
+  {
+    double tl[OR_NPARAM] = {0};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t p = 0; p < npix; ++p) {
+      double dm[3 * OR_MAX_FREQ];
+      int any = 0;
+      for (int k = 0; k < nf; ++k)
+        for (int s = 0; s < 3; ++s) {
+          dm[3 * k + s] = dmaps[((int64_t)k * 3 + s) * npix + p];
+          any |= dm[3 * k + s] != 0.0;
+        }
+      if (any) or_adjoint_pixel(g, f, p, dm, tl, dgrid_bn, dgrid_c);
+    }
+#pragma omp critical
+    for (int k = 0; k < OR_NPARAM; ++k) tb[k] += tl[k];
   }
   if (dtheta)
     for (int k = 0; k < OR_NPARAM; ++k) dtheta[k] = tb[k];

@@ -1,0 +1,402 @@
+// C ABI of the synchrotron march: argument checks, physical prefactors, launch
+// shapes and dispatch.  Every check runs on the host before anything is
+// launched; no exception crosses the ABI.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <atomic>
+#include <string>
+
+#include "../../include/synmarch.h"
+#include "sm_device.h"
+#include "sm_launch.h"
+
+namespace {
+
+// ---- physical constants (cgs, CODATA 2018) --------------------------------
+constexpr double kQe = 4.80320471e-10;        // esu
+constexpr double kMe = 9.1093837015e-28;      // g
+constexpr double kC = 2.99792458e10;          // cm s^-1
+constexpr double kKb = 1.380649e-16;          // erg K^-1
+constexpr double kKpcCm = 3.0856775814913673e21;
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_err;
+
+syn_status fail(syn_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+syn_status hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return SYN_EHIP;
+}
+
+bool finite3(const double* v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+int ilog2_pow2(int32_t v) {
+  if (v < 1 || (v & (v - 1)) != 0) return -1;
+  int o = 0;
+  while ((1 << o) < v) ++o;
+  return o;
+}
+
+// Digamma: upward recurrence to x >= 10, then the Stirling-type asymptotic
+// series in 1/x^2 (Abramowitz & Stegun 6.3.18).
+double digamma_host(double x) {
+  double r = 0.0;
+  while (x < 10.0) {
+    r -= 1.0 / x;
+    x += 1.0;
+  }
+  const double f = 1.0 / (x * x);
+  const double t = f * (-1.0 / 12 + f * (1.0 / 120 + f * (-1.0 / 252 + f * (1.0 / 240 + f * (-1.0 / 132 + f * (691.0 / 32760))))));
+  return r + log(x) - 0.5 / x + t;
+}
+
+// ---- launch shapes ----------------------------------------------------------
+std::atomic<int> g_lanes[3][4];  // [kernel family][field kind], 0 = default
+
+int default_lanes(int64_t npix) {
+  // enough lanes to give every SIMD of the 256 CUs several waves
+  const int64_t target = 1 << 19;
+  for (int S : {1, 4, 16}) {
+    if (npix * S >= target) return S;
+  }
+  return 64;
+}
+
+int lanes_for(int kernel, int kind, int64_t npix) {
+  const int s = (kernel >= 0 && kernel < 3 && kind >= 0 && kind < 4) ? g_lanes[kernel][kind].load()
+                                                                      : 0;
+  return s > 0 ? s : default_lanes(npix);
+}
+
+// ---- argument checks --------------------------------------------------------
+syn_status check_geom(const syn_geom* g, sm::GeomArgs* ga) {
+  if (g == nullptr) return fail(SYN_EINVAL, "geom is NULL");
+  const int order = ilog2_pow2(g->nside);
+  if (order < 0 || g->nside > SYN_MAX_NSIDE)
+    return fail(SYN_EINVAL, "nside must be a power of two in [1, 8192]");
+  if (g->n_steps < 1 || g->n_steps > (1 << 24)) return fail(SYN_EINVAL, "n_steps must be in [1, 2^24]");
+  if (g->n_freq < 1 || g->n_freq > SYN_MAX_FREQ) return fail(SYN_EINVAL, "n_freq must be in [1, 16]");
+  for (int f = 0; f < g->n_freq; ++f)
+    if (!(isfinite(g->freq_hz[f]) && g->freq_hz[f] > 0.0))
+      return fail(SYN_EINVAL, "frequencies must be finite and > 0");
+  if (!finite3(g->r_obs_kpc)) return fail(SYN_EINVAL, "observer must be finite");
+  if (!(g->r_max_kpc > 0.0)) return fail(SYN_EINVAL, "r_max must be > 0");
+  bool all_faces = true;
+  for (int k = 0; k < 3; ++k) {
+    const double lo = g->box_lo_kpc[k], hi = g->box_hi_kpc[k];
+    if (isnan(lo) || isnan(hi) || !(lo < hi)) return fail(SYN_EINVAL, "box needs lo < hi on every axis");
+    if (!(g->r_obs_kpc[k] > lo && g->r_obs_kpc[k] < hi))
+      return fail(SYN_EINVAL, "observer must lie strictly inside the box");
+    all_faces = all_faces && isfinite(lo) && isfinite(hi);
+  }
+  if (!isfinite(g->r_max_kpc) && !all_faces)
+    return fail(SYN_EINVAL, "an infinite r_max needs six finite box faces");
+  ga->nside = g->nside;
+  ga->order = order;
+  ga->n_steps = g->n_steps;
+  ga->npix = 12LL * g->nside * g->nside;
+  for (int k = 0; k < 3; ++k) {
+    ga->r_obs[k] = g->r_obs_kpc[k];
+    ga->box_lo[k] = g->box_lo_kpc[k];
+    ga->box_hi[k] = g->box_hi_kpc[k];
+  }
+  ga->r_max = g->r_max_kpc;
+  return SYN_OK;
+}
+
+sm::M16Args m16_args(const double* th) {
+  const double l2e = 1.4426950408889634;
+  sm::M16Args m{};
+  m.B0 = (float)th[0];
+  m.psi0 = (float)th[1];
+  m.psi1 = (float)th[2];
+  m.chiB0 = (float)th[3];
+  m.sin_psi0 = (float)sin(th[1]);
+  m.cos_psi0 = (float)cos(th[1]);
+  m.invRB = (float)(1.0 / th[4]);
+  m.invzB = (float)(1.0 / th[5]);
+  m.l2_invRB = (float)(l2e / th[4]);
+  m.l2_invzB = (float)(l2e / th[5]);
+  m.BH0 = (float)th[6];
+  m.invzH = (float)(1.0 / th[7]);
+  m.invRH = (float)(1.0 / th[8]);
+  m.l2_invzH = (float)(l2e / th[7]);
+  m.l2_invRH = (float)(l2e / th[8]);
+  m.C0 = (float)th[9];
+  m.invhr = (float)(1.0 / th[10]);
+  m.invhz = (float)(1.0 / th[11]);
+  m.l2_invhr = (float)(l2e / th[10]);
+  m.l2_invhz = (float)(l2e / th[11]);
+  m.n0 = (float)th[13];
+  m.invhne = (float)(1.0 / th[14]);
+  m.l2_invhne = (float)(l2e / th[14]);
+  m.l2_kappa = (float)(l2e * th[15]);
+  m.log2_rsun = (float)log2(8.5);
+  return m;
+}
+
+syn_status check_m16_theta(const double* th) {
+  for (int k : {4, 5, 7, 8, 10, 11, 14})
+    if (!(th[k] > 0.0)) return fail(SYN_EINVAL, "model16 scale lengths (theta 4,5,7,8,10,11,14) must be > 0");
+  return SYN_OK;
+}
+
+syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) {
+  if (f == nullptr) return fail(SYN_EINVAL, "field is NULL");
+  for (int k = 0; k < SYN_NPARAM; ++k)
+    if (!isfinite(f->theta[k])) return fail(SYN_EINVAL, "theta must be finite");
+  if (!(f->theta[12] > 1.0 / 3.0))
+    return fail(SYN_EINVAL, "alpha (theta[12]) must exceed 1/3, the pole of Gamma(alpha/4 - 1/12)");
+  memset(fp, 0, sizeof(*fp));
+  fp->kind = f->kind;
+  switch (f->kind) {
+    case SYN_FIELD_MODEL16: {
+      syn_status s = check_m16_theta(f->theta);
+      if (s != SYN_OK) return s;
+      fp->m16 = m16_args(f->theta);
+      return SYN_OK;
+    }
+    case SYN_FIELD_GRID: {
+      if (f->grid_bn == nullptr) return fail(SYN_EINVAL, "grid_bn is NULL");
+      if (((uintptr_t)f->grid_bn & 15) != 0) return fail(SYN_EINVAL, "grid_bn must be 16-byte aligned");
+      if (f->grid_c != nullptr && ((uintptr_t)f->grid_c & 3) != 0)
+        return fail(SYN_EINVAL, "grid_c must be 4-byte aligned");
+      for (int k = 0; k < 3; ++k) {
+        if (f->grid_n[k] < 2 || f->grid_n[k] > (1 << 16))
+          return fail(SYN_EINVAL, "grid_n must be in [2, 65536] on every axis");
+        if (!(isfinite(f->grid_lo_kpc[k]) && isfinite(f->grid_hi_kpc[k]) &&
+              f->grid_lo_kpc[k] < f->grid_hi_kpc[k]))
+          return fail(SYN_EINVAL, "grid box needs finite lo < hi");
+      }
+      if ((int64_t)f->grid_n[0] * f->grid_n[1] * f->grid_n[2] > (int64_t)1 << 34)
+        return fail(SYN_EINVAL, "grid too large");
+      if (f->grid_c == nullptr) {
+        syn_status s = check_m16_theta(f->theta);
+        if (s != SYN_OK) return s;
+      }
+      fp->m16 = m16_args(f->theta);
+      sm::GridArgs& ga = fp->grid;
+      ga.bn = reinterpret_cast<const float4*>(f->grid_bn);
+      ga.c = f->grid_c;
+      for (int k = 0; k < 3; ++k) {
+        ga.n[k] = f->grid_n[k];
+        ga.lo[k] = (float)f->grid_lo_kpc[k];
+        ga.hi[k] = (float)f->grid_hi_kpc[k];
+        ga.inv_h[k] = (float)((double)(f->grid_n[k] - 1) / (f->grid_hi_kpc[k] - f->grid_lo_kpc[k]));
+        ga.umax[k] = (float)(f->grid_n[k] - 1);
+      }
+      return SYN_OK;
+    }
+    case SYN_FIELD_SPHERE: {
+      if (for_adjoint) return fail(SYN_EUNSUPPORTED, "the sphere field has no adjoint");
+      sm::SphereArgs& s = fp->sph;
+      for (int k = 0; k < 3; ++k) {
+        s.b[k] = (float)f->theta[k];
+        s.c[k] = (float)f->theta[6 + k];
+      }
+      s.ne = (float)f->theta[3];
+      s.n0 = (float)f->theta[4];
+      s.r2 = f->theta[5] > 0.0 ? (float)(f->theta[5] * f->theta[5]) : 0.0f;
+      return SYN_OK;
+    }
+    case SYN_FIELD_MLP:
+      return fail(SYN_EUNSUPPORTED, "MLP fields are not available in this build");
+    default:
+      return fail(SYN_EINVAL, "unknown field kind");
+  }
+}
+
+// Per-frequency prefactors of the sums (Eqs. ji, jp, rm and Rayleigh-Jeans).
+void freq_args(const syn_geom* g, double alpha, sm::FreqArgs* fa) {
+  memset(fa, 0, sizeof(*fa));
+  fa->n_freq = g->n_freq;
+  const double krm = kQe * kQe * kQe / (2.0 * kPi * kMe * kMe * kC * kC * kC * kC);
+  const double gam = tgamma(alpha / 4.0 - 1.0 / 12.0) * tgamma(alpha / 4.0 + 19.0 / 12.0);
+  const double dig = 0.25 * digamma_host(alpha / 4.0 - 1.0 / 12.0) +
+                     0.25 * digamma_host(alpha / 4.0 + 19.0 / 12.0);
+  for (int f = 0; f < g->n_freq; ++f) {
+    const double nu = g->freq_hz[f];
+    const double lam = kC / nu;
+    const double base = 4.0 * kPi * nu * kMe * kC / (3.0 * kQe);
+    // Eq. ji with B_perp in uG inside the sums: (1e-6 B)^{(alpha+1)/2}
+    const double aI = sqrt(3.0) * kQe * kQe * kQe / (8.0 * kPi * kMe * kC * kC) *
+                      pow(base, (1.0 - alpha) / 2.0) * pow(2.0, (alpha + 1.0) / 2.0) /
+                      (alpha + 1.0) * gam * pow(1e-6, (alpha + 1.0) / 2.0);
+    const double rj = kC * kC / (2.0 * kKb * nu * nu);
+    fa->sI[f] = rj * aI * kKpcCm;
+    fa->sP[f] = fa->sI[f] * (alpha + 1.0) / (alpha + 7.0 / 3.0);  // Eq. jp / Eq. ji
+    fa->kappa[f] = krm * 1e-6 * kKpcCm * lam * lam / kPi;       // turns of 2 RM lambda^2
+    fa->dlnsI[f] = -0.5 * log(base) + 0.5 * log(2.0) - 1.0 / (alpha + 1.0) + dig + 0.5 * log(1e-6);
+    fa->dlnsP[f] = fa->dlnsI[f] + 1.0 / (alpha + 1.0) - 1.0 / (alpha + 7.0 / 3.0);
+  }
+}
+
+sm::EmitArgs emit_args(double alpha) {
+  sm::EmitArgs e;
+  e.alpha3 = alpha == 3.0 ? 1 : 0;
+  e.eI = (float)((alpha + 1.0) / 4.0);
+  return e;
+}
+
+size_t ws_phi_bytes(int64_t npix) { return (size_t)((npix * 8 + 255) / 256 * 256); }
+
+size_t ws_bytes_for(int64_t npix, bool adjoint) {
+  if (!adjoint) return 0;
+  return ws_phi_bytes(npix) + (size_t)sm::march_blocks(npix, 64) * sm::kNParam * sizeof(double);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t syn_version(void) { return 100; }
+
+const char* syn_last_error(void) { return g_err.c_str(); }
+
+size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t with_adjoint) {
+  sm::GeomArgs ga;
+  sm::FieldPack fp;
+  if (check_geom(geom, &ga) != SYN_OK) return 0;
+  if (check_field(field, &fp, false) != SYN_OK) return 0;
+  return ws_bytes_for(ga.npix, with_adjoint != 0);
+}
+
+syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  sm::GeomArgs ga;
+  sm::FieldPack fp;
+  syn_status s = check_geom(geom, &ga);
+  if (s != SYN_OK) return s;
+  s = check_field(field, &fp, false);
+  if (s != SYN_OK) return s;
+  if (maps == nullptr || ((uintptr_t)maps & 3) != 0) return fail(SYN_EINVAL, "maps must be a 4-byte aligned device pointer");
+  double* phi_end = nullptr;
+  if (ws != nullptr) {
+    if (ws_bytes < ws_bytes_for(ga.npix, true) || ((uintptr_t)ws & 7) != 0)
+      return fail(SYN_EWORKSPACE, "workspace smaller than syn_workspace_bytes(...,1) or misaligned");
+    phi_end = static_cast<double*>(ws);
+  }
+  sm::FreqArgs fa;
+  freq_args(geom, field->theta[12], &fa);
+  const int S = lanes_for(SYN_KERNEL_FORWARD, field->kind, ga.npix);
+  hipError_t e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, stream);
+  if (e != hipSuccess) return hip_fail(e, "forward launch");
+  return SYN_OK;
+}
+
+syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float* dmaps, void* ws,
+                       size_t ws_bytes, double* dtheta, float* dgrid_bn, float* dgrid_c,
+                       hipStream_t stream) {
+  sm::GeomArgs ga;
+  sm::FieldPack fp;
+  syn_status s = check_geom(geom, &ga);
+  if (s != SYN_OK) return s;
+  s = check_field(field, &fp, true);
+  if (s != SYN_OK) return s;
+  if (dmaps == nullptr || ((uintptr_t)dmaps & 3) != 0) return fail(SYN_EINVAL, "dmaps must be a 4-byte aligned device pointer");
+  if (ws == nullptr || ws_bytes < ws_bytes_for(ga.npix, true) || ((uintptr_t)ws & 7) != 0)
+    return fail(SYN_EWORKSPACE, "adjoint needs the workspace of the matching forward");
+  if (field->kind != SYN_FIELD_GRID && (dgrid_bn != nullptr || dgrid_c != nullptr))
+    return fail(SYN_EINVAL, "grid gradients need a GRID field");
+  if (dgrid_bn != nullptr && ((uintptr_t)dgrid_bn & 3) != 0) return fail(SYN_EINVAL, "dgrid_bn misaligned");
+  if (dgrid_c != nullptr && ((uintptr_t)dgrid_c & 3) != 0) return fail(SYN_EINVAL, "dgrid_c misaligned");
+  if (dgrid_c != nullptr && field->kind == SYN_FIELD_GRID && field->grid_c == nullptr)
+    return fail(SYN_EINVAL, "dgrid_c needs a gridded N0 (grid_c)");
+  if (dtheta == nullptr && dgrid_bn == nullptr && dgrid_c == nullptr) return SYN_OK;
+  if (dtheta != nullptr && ((uintptr_t)dtheta & 7) != 0) return fail(SYN_EINVAL, "dtheta misaligned");
+  sm::FreqArgs fa;
+  freq_args(geom, field->theta[12], &fa);
+  const int S = lanes_for(SYN_KERNEL_ADJOINT, field->kind, ga.npix);
+  double* phi_end = static_cast<double*>(ws);
+  double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + ws_phi_bytes(ga.npix));
+  hipError_t e = sm::launch_adjoint(ga, fa, emit_args(field->theta[12]), fp, S, dmaps, phi_end,
+                                    partials, dtheta, dgrid_bn, dgrid_c, stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  return SYN_OK;
+}
+
+size_t syn_chi2_workspace_bytes(int64_t n_pix, int32_t n_maps) {
+  if (n_pix < 1 || n_maps < 1 || n_maps > 3 * SYN_MAX_FREQ) return 0;
+  return (size_t)sm::chi2_partials(n_pix, n_maps) * sizeof(double);
+}
+
+syn_status syn_chi2(int64_t n_pix, int32_t n_maps, const float* maps, const float* target,
+                    const double* inv_sigma2, float* dmaps, double* chi2, void* ws,
+                    size_t ws_bytes, hipStream_t stream) {
+  if (n_pix < 1 || n_maps < 1 || n_maps > 3 * SYN_MAX_FREQ) return fail(SYN_EINVAL, "need n_pix >= 1 and 1 <= n_maps <= 48");
+  if (maps == nullptr || target == nullptr || inv_sigma2 == nullptr || chi2 == nullptr)
+    return fail(SYN_EINVAL, "maps, target, inv_sigma2 and chi2 are required");
+  if (((uintptr_t)chi2 & 7) != 0) return fail(SYN_EINVAL, "chi2 misaligned");
+  for (int i = 0; i < n_maps; ++i)
+    if (!(isfinite(inv_sigma2[i]) && inv_sigma2[i] >= 0.0)) return fail(SYN_EINVAL, "inv_sigma2 must be finite and >= 0");
+  const int64_t np = sm::chi2_partials(n_pix, n_maps);
+  if (ws == nullptr || ws_bytes < (size_t)np * sizeof(double) || ((uintptr_t)ws & 7) != 0)
+    return fail(SYN_EWORKSPACE, "chi2 workspace smaller than syn_chi2_workspace_bytes or misaligned");
+  hipError_t e = sm::launch_chi2(n_pix, n_maps, maps, target, inv_sigma2, dmaps, chi2,
+                                 static_cast<double*>(ws), np, stream);
+  if (e != hipSuccess) return hip_fail(e, "chi2 launch");
+  return SYN_OK;
+}
+
+syn_status syn_sample_model16(const double* theta, const int32_t n[3], const double lo[3],
+                              const double hi[3], float* out_bn, float* out_c,
+                              hipStream_t stream) {
+  if (theta == nullptr || n == nullptr || lo == nullptr || hi == nullptr) return fail(SYN_EINVAL, "NULL argument");
+  for (int k = 0; k < SYN_NPARAM; ++k)
+    if (!isfinite(theta[k])) return fail(SYN_EINVAL, "theta must be finite");
+  syn_status s = check_m16_theta(theta);
+  if (s != SYN_OK) return s;
+  for (int k = 0; k < 3; ++k)
+    if (n[k] < 2 || !(isfinite(lo[k]) && isfinite(hi[k]) && lo[k] < hi[k]))
+      return fail(SYN_EINVAL, "grid needs >= 2 nodes and finite lo < hi per axis");
+  if (out_bn != nullptr && ((uintptr_t)out_bn & 15) != 0) return fail(SYN_EINVAL, "out_bn must be 16-byte aligned");
+  if (out_bn == nullptr && out_c == nullptr) return SYN_OK;
+  hipError_t e = sm::launch_sample_model16(m16_args(theta), n, lo, hi, out_bn, out_c, stream);
+  if (e != hipSuccess) return hip_fail(e, "sample launch");
+  return SYN_OK;
+}
+
+syn_status syn_eval_fields(const syn_field* field, int64_t n, const float* xyz, float* out,
+                           hipStream_t stream) {
+  sm::FieldPack fp;
+  syn_status s = check_field(field, &fp, false);
+  if (s != SYN_OK) return s;
+  if (n < 0) return fail(SYN_EINVAL, "n must be >= 0");
+  if (n == 0) return SYN_OK;
+  if (xyz == nullptr || out == nullptr) return fail(SYN_EINVAL, "xyz and out are required");
+  hipError_t e = sm::launch_eval_fields(fp, n, xyz, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "eval launch");
+  return SYN_OK;
+}
+
+syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lanes) {
+  if (kernel < 0 || kernel > 2 || field_kind < 0 || field_kind > 3)
+    return fail(SYN_EINVAL, "unknown kernel family or field kind");
+  if (!(lanes == 0 || lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64))
+    return fail(SYN_EINVAL, "lanes per sightline must be 0, 1, 4, 16 or 64");
+  g_lanes[kernel][field_kind].store(lanes);
+  return SYN_OK;
+}
+
+int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix) {
+  return lanes_for(kernel, field_kind, npix);
+}
+
+syn_status syn_host_nest_pixel(int32_t nside, int64_t q, int64_t* ring, double* z, double* phi) {
+  const int order = ilog2_pow2(nside);
+  if (order < 0 || nside > SYN_MAX_NSIDE) return fail(SYN_EINVAL, "nside must be a power of two");
+  if (q < 0 || q >= 12LL * nside * nside) return fail(SYN_EINVAL, "pixel out of range");
+  const sm::PixelDir d = sm::nest_pixel(nside, order, q);
+  if (ring) *ring = d.ring;
+  if (z) *z = d.z;
+  if (phi) *phi = d.phi;
+  return SYN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Small kernels around the march: the chi^2 cotangent, sampling the analytic
+// model onto grid nodes, and point evaluation of any field kind.
+#include "sm_device.h"
+#include "sm_launch.h"
+
+namespace sm {
+
+constexpr int kMaxMaps = 3 * kMaxFreq;
+
+struct Chi2Args {
+  double inv_s2[kMaxMaps];
+};
+
+// Gaussian chi^2 of the maps against a target (log-likelihood of Sec. 3.1 with
+// one noise level per Stokes map) and its gradient.  Each block owns a fixed
+// strided slice, so the FP64 partial sums do not depend on timing.
+__global__ __launch_bounds__(256) void k_chi2(int64_t n_pix, int n_maps, const float* __restrict__ m,
+                                              const float* __restrict__ t, Chi2Args a,
+                                              float* __restrict__ dm, double* __restrict__ part) {
+  const int64_t total = n_pix * n_maps;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += stride) {
+    const int mi = (int)(i / n_pix);
+    const double r = (double)m[i] - (double)t[i];
+    acc += a.inv_s2[mi] * r * r;
+    if (dm != nullptr) dm[i] = (float)(2.0 * a.inv_s2[mi] * r);
+  }
+  __shared__ double red[4];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_sum_fixed(const double* __restrict__ part, int64_t n,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+int64_t chi2_partials(int64_t n_pix, int n_maps) {
+  const int64_t total = n_pix * n_maps;
+  int64_t nb = (total + 256 * 8 - 1) / (256 * 8);
+  if (nb < 1) nb = 1;
+  if (nb > 4096) nb = 4096;
+  return nb;
+}
+
+hipError_t launch_chi2(int64_t n_pix, int n_maps, const float* maps, const float* target,
+                       const double* inv_s2, float* dmaps, double* chi2, double* partials,
+                       int64_t n_partials, hipStream_t st) {
+  Chi2Args a{};
+  for (int i = 0; i < n_maps; ++i) a.inv_s2[i] = inv_s2[i];
+  k_chi2<<<dim3((unsigned)n_partials), dim3(256), 0, st>>>(n_pix, n_maps, maps, target, a, dmaps,
+                                                          partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (chi2 != nullptr) {
+    k_sum_fixed<<<dim3(1), dim3(256), 0, st>>>(partials, n_partials, chi2);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+struct NodeGrid {
+  int32_t n[3];
+  double lo[3], h[3];
+};
+
+__global__ __launch_bounds__(256) void k_sample_model16(Model16 m, NodeGrid ng, float* out_bn,
+                                                        float* out_c) {
+  const int64_t nv = (int64_t)ng.n[0] * ng.n[1] * ng.n[2];
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= nv) return;
+  const int64_t ix = v % ng.n[0];
+  const int64_t iy = (v / ng.n[0]) % ng.n[1];
+  const int64_t iz = v / ((int64_t)ng.n[0] * ng.n[1]);
+  const float x = (float)(ng.lo[0] + ng.h[0] * (double)ix);
+  const float y = (float)(ng.lo[1] + ng.h[1] * (double)iy);
+  const float z = (float)(ng.lo[2] + ng.h[2] * (double)iz);
+  const FV f = m.eval(x, y, z);
+  if (out_bn != nullptr) reinterpret_cast<float4*>(out_bn)[v] = make_float4(f.bx, f.by, f.bz, f.ne);
+  if (out_c != nullptr) out_c[v] = f.n0;
+}
+
+hipError_t launch_sample_model16(const M16Args& m, const int32_t n[3], const double lo[3],
+                                 const double hi[3], float* out_bn, float* out_c,
+                                 hipStream_t st) {
+  NodeGrid ng;
+  for (int k = 0; k < 3; ++k) {
+    ng.n[k] = n[k];
+    ng.lo[k] = lo[k];
+    ng.h[k] = (hi[k] - lo[k]) / (double)(n[k] - 1);
+  }
+  const int64_t nv = (int64_t)n[0] * n[1] * n[2];
+  k_sample_model16<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st>>>(Model16{m}, ng, out_bn,
+                                                                            out_c);
+  return hipGetLastError();
+}
+
+template <class F>
+__global__ __launch_bounds__(256) void k_eval_fields(F fld, int64_t n, const float* __restrict__ xyz,
+                                                     float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const FV f = fld.eval(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+  out[5 * i + 0] = f.bx;
+  out[5 * i + 1] = f.by;
+  out[5 * i + 2] = f.bz;
+  out[5 * i + 3] = f.ne;
+  out[5 * i + 4] = f.n0;
+}
+
+hipError_t launch_eval_fields(const FieldPack& fp, int64_t n, const float* xyz, float* out,
+                              hipStream_t st) {
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (fp.kind) {
+    case kModel16: k_eval_fields<<<grid, block, 0, st>>>(Model16{fp.m16}, n, xyz, out); break;
+    case kGrid:
+      k_eval_fields<<<grid, block, 0, st>>>(Grid{fp.grid, Model16{fp.m16}}, n, xyz, out);
+      break;
+    case kSphere: k_eval_fields<<<grid, block, 0, st>>>(Sphere{fp.sph}, n, xyz, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sm

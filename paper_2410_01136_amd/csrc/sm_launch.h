@@ -1,0 +1,49 @@
+// Host-side launchers of the march kernels (implemented in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sm_params.h"
+
+namespace sm {
+
+enum FieldKind { kModel16 = 0, kGrid = 1, kSphere = 2, kMlp = 3 };
+
+struct MlpArgs {
+  const void* packed;  // device, layout of mlp_layout.h
+  float lo[3], scale[3];  // x^ = (r - lo) * scale - 1
+};
+
+struct FieldPack {
+  int kind;
+  M16Args m16;
+  GridArgs grid;
+  SphereArgs sph;
+  MlpArgs mlp;
+};
+
+// Number of 256-thread blocks a launch with S lanes per sightline uses.
+inline int64_t march_blocks(int64_t npix, int S) { return (npix * S + 255) / 256; }
+
+hipError_t launch_forward(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                          const FieldPack& fp, int S, float* maps, double* phi_end,
+                          hipStream_t st);
+
+// partials: [march_blocks(npix, S)][16] doubles; dtheta: device double[16]
+hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                          const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
+                          double* partials, double* dtheta, float* gbn, float* gc,
+                          hipStream_t st);
+
+hipError_t launch_chi2(int64_t n_pix, int n_maps, const float* maps, const float* target,
+                       const double* inv_s2, float* dmaps, double* chi2, double* partials,
+                       int64_t n_partials, hipStream_t st);
+int64_t chi2_partials(int64_t n_pix, int n_maps);
+
+hipError_t launch_sample_model16(const M16Args& m, const int32_t n[3], const double lo[3],
+                                 const double hi[3], float* out_bn, float* out_c, hipStream_t st);
+
+hipError_t launch_eval_fields(const FieldPack& fp, int64_t n, const float* xyz, float* out,
+                              hipStream_t st);
+
+}  // namespace sm

@@ -1,0 +1,61 @@
+// Kernel argument blocks (plain data, filled on the host, passed by value).
+#pragma once
+
+#include <stdint.h>
+
+namespace sm {
+
+constexpr int kMaxFreq = 16;
+constexpr int kNParam = 16;
+
+struct GeomArgs {
+  int32_t nside, order;  // order = log2(nside)
+  int32_t n_steps;
+  int64_t npix;
+  double r_obs[3];
+  double r_max;
+  double box_lo[3], box_hi[3];
+};
+
+struct M16Args {
+  float B0, psi0, psi1, chiB0;
+  float sin_psi0, cos_psi0;
+  float invRB, invzB, l2_invRB, l2_invzB;
+  float BH0, invzH, invRH, l2_invzH, l2_invRH;
+  float C0, invhr, invhz, l2_invhr, l2_invhz;
+  float n0, invhne, l2_invhne, l2_kappa;
+  float log2_rsun;
+};
+
+struct GridArgs {
+  const float4* bn;  // [nz][ny][nx] x (Bx, By, Bz, n_e)
+  const float* c;    // [nz][ny][nx] N0 or nullptr
+  int32_t n[3];
+  float lo[3], hi[3], inv_h[3], umax[3];
+};
+
+struct SphereArgs {
+  float b[3];
+  float ne, n0, r2;
+  float c[3];
+};
+
+// Per-frequency constants of the sums, all FP64:
+//   T_I = sI * dkpc * sum u,   T_Q + i T_U = sP * dkpc * sum zc e^{2 pi i t},
+//   t = kappa * dkpc * (Faraday sum of n_e B_par in uG cm^-3 units).
+struct FreqArgs {
+  int32_t n_freq;
+  double sI[kMaxFreq];
+  double sP[kMaxFreq];
+  double kappa[kMaxFreq];
+  // d ln sI / d alpha, d ln sP / d alpha (adjoint only)
+  double dlnsI[kMaxFreq];
+  double dlnsP[kMaxFreq];
+};
+
+struct EmitArgs {
+  int32_t alpha3;  // alpha == 3 exactly: integer powers, no log/exp
+  float eI;        // (alpha + 1) / 4
+};
+
+}  // namespace sm

@@ -1,0 +1,170 @@
+"""GPU forward march vs the FP64 oracle, element by element, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2410_01136_amd import inputs as I
+from parity import compare_maps, oracle_geom
+
+pytestmark = pytest.mark.gpu
+
+LANES = [1, 4, 16, 64]
+
+
+@pytest.fixture(scope="module")
+def sm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2410_01136_amd import binding
+    return binding
+
+
+@pytest.fixture
+def lanes(sm):
+    def set_(kind, S, kernel=0):
+        sm.set_lanes_per_ray(kernel, kind, S)
+    yield set_
+    for k in range(3):
+        for kind in range(4):
+            sm.set_lanes_per_ray(k, kind, 0)
+
+
+def run_gpu(sm, g: I.Geometry, field):
+    import torch
+    maps = sm.forward(sm.geom_from(g), field)
+    torch.cuda.synchronize()
+    return maps.cpu().numpy()
+
+
+def assert_parity(gpu, ref, label):
+    ok, rep = compare_maps(gpu, ref)
+    print(label, rep, flush=True)
+    assert ok, (label, rep)
+
+
+@pytest.mark.parametrize("S", LANES)
+def test_c0_model16_theta0(sm, orc, lanes, S):
+    g = I.geometry("C0")
+    lanes(sm.FIELD_MODEL16, S)
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.MODEL16, I.THETA0))
+    gpu = run_gpu(sm, g, sm.model16(I.THETA0))
+    assert_parity(gpu, ref, f"C0 S={S}")
+
+
+@pytest.mark.parametrize("S", [1, 16])
+@pytest.mark.parametrize("seed", [3001, 3002])
+def test_c0_model16_perturbed_general_alpha(sm, orc, lanes, S, seed):
+    # every term of the model switched on (pitch gradient, tilt, halo, n_e gradient)
+    # and alpha != 3, which takes the log/exp power path
+    th = I.perturbed_thetas(1, seed)[0]
+    th[2], th[3], th[6], th[15] = 0.12, 0.3, 1.5, 0.03
+    g = I.geometry("C0", freqs_hz=(0.7e9, 1.4e9))
+    lanes(sm.FIELD_MODEL16, S)
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.MODEL16, th))
+    gpu = run_gpu(sm, g, sm.model16(th))
+    assert_parity(gpu, ref, f"perturbed alpha={th[12]:.3f} S={S}")
+
+
+def small_turbulent_grid(orc, n=(41, 41, 11), with_c=True, seed0=1001):
+    reg_bn, reg_c = orc.sample_model16(I.THETA0, n, I.BOX_LO, I.BOX_HI)
+    bn = I.turbulent_grids(reg_bn, seeds=(seed0, seed0 + 1, seed0 + 2, seed0 + 3))
+    return bn, (reg_c if with_c else None)
+
+
+@pytest.mark.parametrize("S", LANES)
+def test_grid_three_frequencies(sm, orc, lanes, S):
+    import torch
+    g = I.geometry("C1", nside=16, n_steps=200)  # 200 steps: ragged last chunk for S = 16, 64
+    bn, c = small_turbulent_grid(orc)
+    lanes(sm.FIELD_GRID, S)
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.GRID, I.THETA0, grid_bn=bn, grid_c=c,
+                                                     grid_lo=I.BOX_LO, grid_hi=I.BOX_HI))
+    f = sm.grid(I.THETA0, torch.from_numpy(bn).cuda(), torch.from_numpy(c).cuda(), I.BOX_LO,
+                I.BOX_HI)
+    gpu = run_gpu(sm, g, f)
+    assert_parity(gpu, ref, f"grid S={S}")
+
+
+def test_grid_with_analytic_cr(sm, orc):
+    import torch
+    g = I.geometry("C2", nside=16, n_steps=96)
+    bn, _ = small_turbulent_grid(orc, n=(33, 33, 9), with_c=False, seed0=2101)
+    th = I.THETA0.copy()
+    th[12] = 2.7
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.GRID, th, grid_bn=bn, grid_c=None,
+                                                     grid_lo=I.BOX_LO, grid_hi=I.BOX_HI))
+    gpu = run_gpu(sm, g, sm.grid(th, torch.from_numpy(bn).cuda(), None, I.BOX_LO, I.BOX_HI))
+    assert_parity(gpu, ref, "grid + analytic N0")
+
+
+def test_sphere_e1_reduced(sm, orc):
+    g = I.geometry("E1", nside=16, n_steps=256)
+    th = I.sphere_theta()
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.SPHERE, th))
+    gpu = run_gpu(sm, g, sm.sphere(th))
+    # the sphere's edge decides which midpoints count; a midpoint within FP32
+    # rounding of the surface may fall on either side, so compare with the
+    # step-count tolerance as well
+    ok, rep = compare_maps(gpu, ref)
+    print("sphere", rep, flush=True)
+    frac_bad = (rep["fail_I"] + rep["fail_Q"] + rep["fail_U"]) / (3 * rep["n"])
+    assert frac_bad <= 0.01, rep
+
+
+@pytest.mark.parametrize("nside,steps", [(1, 1), (1, 7), (2, 64), (4, 1), (8, 33)])
+def test_small_and_ragged(sm, orc, lanes, nside, steps):
+    for S in (1, 64):
+        lanes(sm.FIELD_MODEL16, S)
+        g = I.geometry("C0", nside=nside, n_steps=steps)
+        ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.MODEL16, I.THETA0))
+        gpu = run_gpu(sm, g, sm.model16(I.THETA0))
+        assert_parity(gpu, ref, f"nside={nside} steps={steps} S={S}")
+
+
+def test_sixteen_frequencies(sm, orc):
+    g = I.geometry("C0", nside=4, n_steps=64, freqs_hz=tuple(np.geomspace(0.4e9, 30e9, 16)))
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.MODEL16, I.THETA0))
+    gpu = run_gpu(sm, g, sm.model16(I.THETA0))
+    assert_parity(gpu, ref, "16 freqs")
+
+
+def test_deterministic(sm):
+    g = I.geometry("C0")
+    a = run_gpu(sm, g, sm.model16(I.THETA0))
+    b = run_gpu(sm, g, sm.model16(I.THETA0))
+    assert np.array_equal(a, b)
+
+
+def test_lanes_agree_closely(sm, lanes):
+    # the lane split changes only the FP64 summation order
+    g = I.geometry("C0", nside=8)
+    out = []
+    for S in LANES:
+        lanes(sm.FIELD_MODEL16, S)
+        out.append(run_gpu(sm, g, sm.model16(I.THETA0)))
+    for o in out[1:]:
+        np.testing.assert_allclose(o, out[0], rtol=2e-6, atol=1e-9 * np.abs(out[0]).max())
+
+
+@pytest.mark.slow
+def test_c1_full_size_sampled(sm, orc):
+    """Full C1 shape (N_side 256, 512 steps, 3 freqs, 256^3 grids) in the launch
+    configuration the benchmark times; the oracle checks 1500 sampled pixels."""
+    import torch
+    g = I.geometry("C1")
+    print("building 256^3 grids", flush=True)
+    reg_bn, reg_c = orc.sample_model16(I.THETA0, (256, 256, 256), I.BOX_LO, I.BOX_HI)
+    bn = I.turbulent_grids(reg_bn)
+    del reg_bn
+    f_gpu = sm.grid(I.THETA0, torch.from_numpy(bn).cuda(), torch.from_numpy(reg_c).cuda(),
+                    I.BOX_LO, I.BOX_HI)
+    gpu = run_gpu(sm, g, f_gpu)
+    pix = I.sample_pixels(g.npix, 1500, seed=77)
+    ref = orc.forward_pixels(oracle_geom(orc, g), orc.Field(orc.GRID, I.THETA0, grid_bn=bn,
+                                                            grid_c=reg_c, grid_lo=I.BOX_LO,
+                                                            grid_hi=I.BOX_HI), pix)
+    ref = np.transpose(ref, (1, 2, 0))  # [f][3][n]
+    assert_parity(gpu[:, :, pix], ref, "C1 full size, sampled")
+    assert np.isfinite(gpu).all()
