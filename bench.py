@@ -1,0 +1,401 @@
+#!/usr/bin/env python3
+"""Benchmark of the synchrotron sightline march on one MI355X.
+
+Headline workload (value): the gridded forward march -- N_side 256 (786,432
+sightlines), 512 steps, frequencies {1, 2.3, 5} GHz, five FP32 channels on
+256^3 nodes over a 40 x 40 x 8 kpc box (analytic spiral-disk model plus a
+seeded k^-11/3 random field).  A step is one full forward pass over that
+input, already resident in HBM.  The metric counts sightline-steps as
+pixels x steps x frequencies per second.
+
+Also reported: the adjoint (N_side 64, 768 steps, 1.4 GHz, chi^2 gradient
+with respect to the 16 parameters and to a 128^3 B/n_e grid), the roofline
+of the dominant kernel, the map error against the FP64 oracle on sampled
+pixels, and the oracle's own throughput on the host cores (cpu_baseline).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sightline-steps/s (pix×steps×freqs) fwd & adjoint vs plain, at stated map error"
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
+PEAK_HBM_GBS = 8000.0
+# Algorithmic work of one (sightline, step) of the gridded forward at 3 frequencies,
+# counted from the method (FMA = 2, other arithmetic or transcendental = 1):
+#   midpoint 8, trilinear of 5 channels 117, projections 13, Faraday increment and
+#   midpoint prefix 4, emission at alpha = 3 9, I sum 1, and per frequency: phase 1,
+#   reduction 2, sin+cos 2, rotation 6, Q/U sums 2 (= 13) -> 152 + 3 * 13 = 191.
+FLOP_PER_PIX_STEP_C1 = 191.0
+# Compulsory HBM bytes of one launch: the grids are read once, maps written once.
+GATHER_BYTES_PER_PIX_STEP = 160.0  # 8 corners x 5 channels x 4 B from cache
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2410_01136_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM traffic per launch from a committed rocprofv3 PMC summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel)
+        if e and e.get("source_hash") == kernel_source_hash():
+            return e["hbm_bytes_per_launch"]
+    except (ValueError, KeyError):
+        return None
+    return None
+
+
+def time_launches(fn, steps, warmup):
+    """(wall ms per call, event ms per call) over `steps` calls after `warmup`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return wall, e0.elapsed_time(e1) / steps
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batched workloads")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in launch shapes")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures the march "
+              "on one GPU only (sightlines are independent; see DESIGN.md for how it shards)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2410_01136_amd import binding as sm
+    from paper_2410_01136_amd import inputs as I
+    from paper_2410_01136_amd import tune
+
+    torch.cuda.set_device(0)
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device: {dev.name}, {dev.multi_processor_count} CUs")
+
+    # ---------------------------------------------------------------- C1 inputs
+    g = I.geometry("C1")
+    n_nodes = (256, 256, 256)
+    t0 = time.time()
+    noise = I.turbulence_noise(n_nodes[::-1])
+    log(f"noise fields: {time.time() - t0:.1f} s")
+    reg_bn, reg_c = sm.sample_model16(I.THETA0, n_nodes, I.BOX_LO, I.BOX_HI)
+    torch.cuda.synchronize()
+    bn = I.apply_turbulence(reg_bn.cpu().numpy(), noise)
+    bn_t = torch.from_numpy(bn).cuda()
+    c_t = reg_c
+    del reg_bn, bn
+    field = sm.grid(I.THETA0, bn_t, c_t, I.BOX_LO, I.BOX_HI)
+    geom = sm.geom_from(g)
+    maps = torch.empty((len(g.freqs_hz), 3, g.npix), dtype=torch.float32, device="cuda")
+    lanes = sm.get_lanes_per_ray(sm.KERNEL_FORWARD, sm.FIELD_GRID, g.npix)
+
+    def fwd():
+        sm.forward(geom, field, maps=maps)
+
+    if not args.no_tune:
+        t = tune.tune_forward(geom, field, maps=maps, use_cache=False, write_cache=False)
+        log("tuned C1 forward:", t)
+    lanes = sm.get_lanes_per_ray(sm.KERNEL_FORWARD, sm.FIELD_GRID, g.npix)
+    log(f"C1: {g.npix} sightlines x {g.n_steps} steps x {len(g.freqs_hz)} freqs, lanes/ray {lanes}")
+    wall_ms, ev_ms = time_launches(fwd, args.steps, args.warmup)
+    units = g.units
+    value = units / (wall_ms * 1e-3)
+    log(f"C1 forward: {wall_ms:.3f} ms/step (events {ev_ms:.3f} ms/launch) -> {value:.4e} sightline-steps/s")
+    pix_steps = g.npix * g.n_steps
+    achieved = FLOP_PER_PIX_STEP_C1 * pix_steps / (ev_ms * 1e-3) / 1e12
+    traffic = load_traffic("k_forward<Grid>/C1")
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+        "traffic": traffic,
+        "kernel": "sm::k_forward<Grid, S=1, MF=4>",
+        "flop_per_unit": FLOP_PER_PIX_STEP_C1 / len(g.freqs_hz),
+        "units_per_launch": units,
+        "launch_ms": round(ev_ms, 4),
+        "gather_GBps_from_cache": round(GATHER_BYTES_PER_PIX_STEP * pix_steps / (ev_ms * 1e-3) / 1e9, 1),
+        "compulsory_hbm_GBps": round((bn_t.numel() * 4 + c_t.numel() * 4 + maps.numel() * 4)
+                                     / (ev_ms * 1e-3) / 1e9, 1),
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": float(f"{value:.6e}"),
+        "unit": "sightline-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 Faraday sum, phase reduction and Stokes sums)",
+        "data": "synthetic (seeded analytic model + k^-11/3 random fields)",
+        "config": {
+            "workload": "gridded forward march: N_side 256 (786432 sightlines), 512 steps, "
+                        "{1, 2.3, 5} GHz, 256^3 FP32 nodes x 5 channels over 40x40x8 kpc",
+            "nside": g.nside, "n_steps": g.n_steps, "freqs_hz": list(g.freqs_hz),
+            "grid_nodes": list(n_nodes), "lanes_per_ray": lanes,
+        },
+        "roofline": roofline,
+    }
+
+    # ---------------------------------------------------------------- adjoint (C2)
+    if not args.no_extras:
+        out["adjoint"] = bench_adjoint(sm, I, np, torch, tune, args)
+        out["batched"] = bench_batched(sm, I, np, torch, tune, args)
+
+    # ---------------------------------------------------------------- oracle leg
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["map_error"] = cpu_baseline_leg(sm, I, np, torch, g, noise, geom,
+                                                                 args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_adjoint(sm, I, np, torch, tune, args):
+    """C2: chi^2 gradient at theta0 against a target at perturbed parameters + 1% noise."""
+    res = {}
+    g = I.geometry("C2")
+    geom = sm.geom_from(g)
+    th_star = I.perturbed_thetas(1, 2001)[0]
+    tgt_maps = sm.forward(geom, sm.model16(th_star)).cpu().numpy()
+    target, inv = I.chi2_noise(tgt_maps, seed=2002)
+    target = torch.from_numpy(target).cuda()
+    field = sm.model16(I.THETA0)
+    ws = sm.alloc_workspace(geom, field)
+    maps = torch.empty((1, 3, g.npix), dtype=torch.float32, device="cuda")
+    state = {}
+
+    def fwd():
+        sm.forward(geom, field, maps=maps, ws=ws)
+
+    def cot():
+        state["chi"], state["dm"] = sm.chi2(maps, target, inv)
+
+    def adj():
+        state["dth"] = sm.adjoint(geom, field, state["dm"], ws)
+
+    fwd()
+    cot()
+    if not args.no_tune:
+        log("tuned C2 forward:", tune.tune_forward(geom, field, maps=maps, ws=ws, use_cache=False,
+                                                  write_cache=False))
+        log("tuned C2 adjoint:", tune.tune_adjoint(geom, field, state["dm"], ws, use_cache=False,
+                                                  write_cache=False))
+    f_wall, f_ev = time_launches(fwd, args.steps, args.warmup)
+    a_wall, a_ev = time_launches(adj, args.steps, args.warmup)
+
+    def full():
+        fwd()
+        cot()
+        adj()
+
+    t_wall, t_ev = time_launches(full, args.steps, args.warmup)
+    units = g.units
+    res["theta"] = {
+        "workload": "N_side 64, 768 steps, 1.4 GHz, 16-parameter analytic model, chi^2 of I/Q/U",
+        "forward_sightline_steps_per_s": float(f"{units / (f_ev * 1e-3):.4e}"),
+        "adjoint_sightline_steps_per_s": float(f"{units / (a_ev * 1e-3):.4e}"),
+        "adjoint_over_forward_time": round(a_ev / f_ev, 3),
+        "fwd_chi2_adj_ms": round(t_wall, 4),
+        "lanes_per_ray": {"forward": sm.get_lanes_per_ray(0, 0, g.npix),
+                          "adjoint": sm.get_lanes_per_ray(1, 0, g.npix)},
+    }
+    log("C2 theta:", res["theta"])
+    # grid gradient: B and n_e on 128^3 nodes sampled from theta0, analytic N0
+    bn, _ = sm.sample_model16(I.THETA0, (128, 128, 128), I.BOX_LO, I.BOX_HI)
+    gfield = sm.grid(I.THETA0, bn, None, I.BOX_LO, I.BOX_HI)
+    gws = sm.alloc_workspace(geom, gfield)
+    dbn = torch.zeros_like(bn)
+
+    def gfwd():
+        sm.forward(geom, gfield, maps=maps, ws=gws)
+
+    gfwd()
+    cot()
+
+    def gadj():
+        sm.adjoint(geom, gfield, state["dm"], gws, want_theta=False, dgrid_bn=dbn)
+
+    if not args.no_tune:
+        log("tuned C2 grid forward:", tune.tune_forward(geom, gfield, maps=maps, ws=gws,
+                                                       use_cache=False, write_cache=False))
+        log("tuned C2 grid adjoint:", tune.tune_adjoint(geom, gfield, state["dm"], gws,
+                                                       want_theta=False, dgrid_bn=dbn,
+                                                       use_cache=False, write_cache=False))
+
+    gf_wall, gf_ev = time_launches(gfwd, args.steps, args.warmup)
+    ga_wall, ga_ev = time_launches(gadj, args.steps, args.warmup)
+    res["grid"] = {
+        "workload": "N_side 64, 768 steps, 1.4 GHz, B/n_e on 128^3 nodes, gradient into the grid",
+        "forward_sightline_steps_per_s": float(f"{units / (gf_ev * 1e-3):.4e}"),
+        "adjoint_sightline_steps_per_s": float(f"{units / (ga_ev * 1e-3):.4e}"),
+        "adjoint_over_forward_time": round(ga_ev / gf_ev, 3),
+    }
+    log("C2 grid:", res["grid"])
+    return res
+
+
+def bench_batched(sm, I, np, torch, tune, args):
+    """C3: 256 parameter sets, N_side 32/64/128 mixed 1:2:1, 512 steps, 1 GHz: forward,
+    chi^2 and adjoint of every set in one graph-captured sequence of persistent kernels,
+    against the same work done set by set with the single-map entry points."""
+    n_sets = 256
+    thetas = I.perturbed_thetas(n_sets, 3001)
+    nsides = I.c3_nsides(n_sets, 3002)
+    g0 = I.geometry("C3")
+    geom = sm.geom_from(g0)
+    # per-set targets: the theta0 map at the set's N_side plus 1% noise
+    base = {}
+    for ns in (32, 64, 128):
+        m = sm.forward(sm.geom_from(I.geometry("C3", nside=int(ns))), sm.model16(I.THETA0))
+        base[int(ns)] = m.cpu().numpy()
+    pieces = [base[int(ns)][0] for ns in nsides]
+    tgt_np, inv = I.chi2_noise(np.concatenate(pieces, axis=-1)[None], seed=3003)
+    inv = inv[0]
+    target = torch.from_numpy(np.ascontiguousarray(tgt_np[0])).cuda()
+    total = target.shape[1]
+    if not args.no_tune:
+        log("tuned C3 batch:", tune.tune_batch(thetas, nsides, geom, target, inv, use_cache=False,
+                                               write_cache=False))
+    plan = tune.make_batch(thetas, nsides, geom, use_graph=True)
+    maps = torch.empty((3, total), dtype=torch.float32, device="cuda")
+    dmaps = torch.empty_like(maps)
+    chi2 = torch.empty(n_sets, dtype=torch.float64, device="cuda")
+    dth = torch.empty((n_sets, 16), dtype=torch.float64, device="cuda")
+    inv_c = np.ascontiguousarray(inv, dtype=np.float64)
+
+    def run():
+        sm.check(sm.syn_batch_run(plan, target.data_ptr(), inv_c.ctypes.data_as(sm._dp),
+                                  maps.data_ptr(), dmaps.data_ptr(), chi2.data_ptr(),
+                                  dth.data_ptr(), sm._stream()), "syn_batch_run")
+
+    b_wall, b_ev = time_launches(run, max(3, args.steps // 4), 1)
+    # the same work set by set through the single-map entry points
+    offs = [int(sm.syn_batch_offset(plan, s)) for s in range(n_sets)]
+    per = []
+    for s in range(n_sets):
+        gs = I.geometry("C3", nside=int(nsides[s]))
+        gm = sm.geom_from(gs)
+        f = sm.model16(thetas[s])
+        ws = sm.alloc_workspace(gm, f)
+        tg = target[:, offs[s]:offs[s] + gs.npix].contiguous().view(1, 3, -1)
+        per.append((gm, f, ws, tg))
+
+    def loop():
+        for gm, f, ws, tg in per:
+            m = sm.forward(gm, f, ws=ws)
+            _, dm = sm.chi2(m, tg, inv)
+            sm.adjoint(gm, f, dm, ws)
+
+    l_wall, l_ev = time_launches(loop, 2, 1)
+    sm.syn_batch_destroy(plan)
+    units = total * g0.n_steps
+    res = {
+        "workload": "256 parameter sets, N_side {32, 64, 128} mixed 1:2:1 (19,660,800 sightlines), "
+                    "512 steps, 1 GHz; forward + chi^2 + adjoint per set",
+        "graph_ms": round(b_wall, 3),
+        "fwd_plus_adj_sightline_steps_per_s": float(f"{units / (b_wall * 1e-3):.4e}"),
+        "set_by_set_ms": round(l_wall, 3),
+        "speedup_vs_set_by_set": round(l_wall / b_wall, 3),
+        "lanes_per_ray": sm.get_lanes_per_ray(sm.KERNEL_BATCH, sm.FIELD_MODEL16, total),
+    }
+    log("C3 batched:", res)
+    return res
+
+
+def cpu_baseline_leg(sm, I, np, torch, g, noise, geom, seconds):
+    """Times the FP64 oracle on a bounded pixel sample of the headline workload and
+    measures the GPU map error on the same pixels (both from oracle-built grids)."""
+    import oracle
+    t0 = time.time()
+    reg_bn, reg_c = oracle.sample_model16(I.THETA0, (256, 256, 256), I.BOX_LO, I.BOX_HI)
+    bn = I.apply_turbulence(reg_bn, noise)
+    del reg_bn
+    log(f"oracle grids: {time.time() - t0:.1f} s")
+    ofield = oracle.Field(oracle.GRID, I.THETA0, grid_bn=bn, grid_c=reg_c, grid_lo=I.BOX_LO,
+                          grid_hi=I.BOX_HI)
+    og = oracle.make_geom(g.nside, g.n_steps, g.freqs_hz, g.r_obs, g.r_max, g.box_lo, g.box_hi)
+    # calibrate the sample size to about `seconds` of oracle time
+    probe = I.sample_pixels(g.npix, 64, seed=91)
+    t0 = time.perf_counter()
+    oracle.forward_pixels(og, ofield, probe)
+    rate = probe.size / (time.perf_counter() - t0)
+    n = int(max(256, min(g.npix, rate * seconds)))
+    pix = I.sample_pixels(g.npix, n, seed=92)
+    t0 = time.perf_counter()
+    ref = oracle.forward_pixels(og, ofield, pix)
+    dt = time.perf_counter() - t0
+    cpu = {
+        "value": float(f"{pix.size * g.n_steps * len(g.freqs_hz) / dt:.4e}"),
+        "unit": "sightline-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{pix.size} seeded random pixels of the headline workload (all 512 steps, "
+                  f"3 frequencies), {dt:.1f} s",
+    }
+    log("cpu baseline:", cpu)
+    # GPU on the same (oracle-built) grids, compared on the sampled pixels
+    f = sm.grid(I.THETA0, torch.from_numpy(bn).cuda(), torch.from_numpy(reg_c).cuda(), I.BOX_LO,
+                I.BOX_HI)
+    gpu = sm.forward(geom, f).cpu().numpy()[:, :, pix].astype(np.float64)
+    ref = np.transpose(ref, (1, 2, 0))
+    pi = np.hypot(ref[:, 1], ref[:, 2])
+    err = {
+        "pixels": int(pix.size),
+        "max_rel_I": float(np.max(np.abs(gpu[:, 0] - ref[:, 0]) / np.abs(ref[:, 0]))),
+        "max_abs_QU_over_PI": float(np.max(np.maximum(np.abs(gpu[:, 1] - ref[:, 1]),
+                                                      np.abs(gpu[:, 2] - ref[:, 2])) / pi)),
+        "tolerance": "I 1e-5 relative; Q, U 1e-4 of PI",
+    }
+    log("map error:", err)
+    return cpu, err
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -168,10 +168,12 @@ syn_status syn_mlp_pack(const float* fourier, const float* w_in, const float* b_
    forward, chi^2 against per-set targets and the adjoint for every set in a
    single captured HIP graph of persistent work-queue kernels. */
 typedef struct syn_batch_desc {
-  int32_t n_sets;
+  int32_t n_sets;              /* 1 .. 65536                                    */
   const int32_t* nside;        /* [n_sets], powers of two                       */
   const double* theta;         /* [n_sets][16]                                  */
-  syn_geom geom;               /* nside ignored; one frequency                  */
+  syn_geom geom;               /* nside ignored; exactly one frequency          */
+  int32_t use_graph;           /* 1: capture the launch sequence once as a HIP
+                                  graph and replay it; 0: launch directly     */
 } syn_batch_desc;
 
 typedef struct syn_batch syn_batch;
@@ -182,11 +184,15 @@ typedef struct syn_batch syn_batch;
 syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan);
 int64_t syn_batch_total_pixels(const syn_batch* plan);
 int64_t syn_batch_offset(const syn_batch* plan, int32_t set);
-/* Runs forward, chi^2 with inv_sigma2 (host double[3]) against target (device
-   float [3][total]) and the adjoint.  Outputs (device): maps float [3][total],
-   dmaps float [3][total], chi2 double [n_sets], dtheta double [n_sets][16].
-   The first call captures the graph on stream; later calls replay it and
-   must pass the same pointers. */
+/* Runs forward, chi^2 with inv_sigma2 (host double[3], one weight per Stokes
+   map, shared by all sets) against target (device float [3][total]) and the
+   adjoint.  Outputs (device): maps float [3][total], dmaps float [3][total]
+   (= d chi2 / d maps), chi2 double [n_sets], dtheta double [n_sets][16]
+   (= d chi2_s / d theta_s).  With use_graph the first call captures the
+   sequence (on a private stream) and every call launches the graph on
+   `stream`; a call with different pointers or weights captures again.  Calls
+   on one plan must not overlap (they share the plan's work counters).  The
+   plan is bound to the device current at creation. */
 syn_status syn_batch_run(syn_batch* plan, const float* target, const double* inv_sigma2,
                          float* maps, float* dmaps, double* chi2, double* dtheta,
                          hipStream_t stream);

@@ -44,7 +44,8 @@ class SynField(ctypes.Structure):
 
 class SynBatchDesc(ctypes.Structure):
     _fields_ = [("n_sets", ctypes.c_int32), ("nside", ctypes.POINTER(ctypes.c_int32)),
-                ("theta", ctypes.POINTER(ctypes.c_double)), ("geom", SynGeom)]
+                ("theta", ctypes.POINTER(ctypes.c_double)), ("geom", SynGeom),
+                ("use_graph", ctypes.c_int32)]
 
 
 _vp, _i32, _i64, _sz, _dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, \

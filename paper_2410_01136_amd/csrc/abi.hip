@@ -7,8 +7,10 @@
 
 #include <atomic>
 #include <string>
+#include <vector>
 
 #include "../../include/synmarch.h"
+#include "batch.h"
 #include "sm_device.h"
 #include "sm_launch.h"
 
@@ -186,10 +188,9 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
       ga.c = f->grid_c;
       for (int k = 0; k < 3; ++k) {
         ga.n[k] = f->grid_n[k];
-        ga.lo[k] = (float)f->grid_lo_kpc[k];
-        ga.hi[k] = (float)f->grid_hi_kpc[k];
-        ga.inv_h[k] = (float)((double)(f->grid_n[k] - 1) / (f->grid_hi_kpc[k] - f->grid_lo_kpc[k]));
-        ga.umax[k] = (float)(f->grid_n[k] - 1);
+        ga.lo[k] = f->grid_lo_kpc[k];
+        ga.inv_h[k] = (double)(f->grid_n[k] - 1) / (f->grid_hi_kpc[k] - f->grid_lo_kpc[k]);
+        ga.umax[k] = (double)(f->grid_n[k] - 1);
       }
       return SYN_OK;
     }
@@ -398,5 +399,198 @@ syn_status syn_host_nest_pixel(int32_t nside, int64_t q, int64_t* ring, double* 
   if (phi) *phi = d.phi;
   return SYN_OK;
 }
+
+// ---- many parameter sets -----------------------------------------------------
+}  // extern "C"
+
+struct syn_batch {
+  sm::BatchLaunch L{};
+  std::vector<int64_t> offsets;
+  int device = 0;
+  int use_graph = 1;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool captured = false;
+  const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double key_inv[3] = {0, 0, 0};
+};
+
+namespace {
+
+void batch_free(syn_batch* b) {
+  if (b == nullptr) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->L.sets) hipFree(const_cast<sm::BatchSet*>(b->L.sets));
+  if (b->L.counters) hipFree(b->L.counters);
+  if (b->L.phi) hipFree(b->L.phi);
+  if (b->L.partials) hipFree(b->L.partials);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
+  if (plan == nullptr) return fail(SYN_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  if (desc == nullptr || desc->nside == nullptr || desc->theta == nullptr)
+    return fail(SYN_EINVAL, "desc, nside and theta are required");
+  if (desc->n_sets < 1 || desc->n_sets > 65536) return fail(SYN_EINVAL, "n_sets must be in [1, 65536]");
+  if (desc->geom.n_freq != 1) return fail(SYN_EUNSUPPORTED, "batches use exactly one frequency");
+  int64_t all_pix = 0;
+  for (int s = 0; s < desc->n_sets; ++s) {
+    syn_geom g = desc->geom;
+    g.nside = desc->nside[s];
+    sm::GeomArgs ga;
+    syn_status st = check_geom(&g, &ga);
+    if (st != SYN_OK) return st;
+    all_pix += ga.npix;
+  }
+  const int S = lanes_for(SYN_KERNEL_BATCH, SYN_FIELD_MODEL16, all_pix);
+  std::vector<sm::BatchSet> sets(desc->n_sets);
+  std::vector<int64_t> offsets(desc->n_sets);
+  int64_t total = 0, items = 0;
+  for (int s = 0; s < desc->n_sets; ++s) {
+    syn_geom g = desc->geom;
+    g.nside = desc->nside[s];
+    sm::BatchSet& B = sets[s];
+    memset(&B, 0, sizeof(B));
+    syn_status st = check_geom(&g, &B.g);
+    if (st != SYN_OK) return st;
+    syn_field f{};
+    f.kind = SYN_FIELD_MODEL16;
+    memcpy(f.theta, desc->theta + 16 * (int64_t)s, sizeof(f.theta));
+    sm::FieldPack fp;
+    st = check_field(&f, &fp, true);
+    if (st != SYN_OK) return st;
+    B.m = fp.m16;
+    sm::FreqArgs fa;
+    freq_args(&g, f.theta[12], &fa);
+    B.fa.n_freq = 1;
+    B.fa.sI[0] = fa.sI[0];
+    B.fa.sP[0] = fa.sP[0];
+    B.fa.kappa[0] = fa.kappa[0];
+    B.fa.dlnsI[0] = fa.dlnsI[0];
+    B.fa.dlnsP[0] = fa.dlnsP[0];
+    B.ea = emit_args(f.theta[12]);
+    B.map_off = total;
+    offsets[s] = total;
+    const int64_t ni = sm::march_blocks(B.g.npix, S);
+    if (items + ni > (int64_t)INT32_MAX) return fail(SYN_EINVAL, "batch too large");
+    B.item0 = (int32_t)items;
+    B.n_items = (int32_t)ni;
+    total += B.g.npix;
+    items += ni;
+  }
+  syn_batch* b = new syn_batch();
+  b->offsets = offsets;
+  b->use_graph = desc->use_graph != 0;
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(e, "hipGetDevice");
+  }
+  sm::BatchLaunch& L = b->L;
+  L.S = S;
+  L.n_sets = desc->n_sets;
+  L.n_items = (int)items;
+  L.total = total;
+  sm::BatchSet* dsets = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&dsets), sizeof(sm::BatchSet) * sets.size()) != hipSuccess ||
+      (L.sets = dsets, hipMalloc(reinterpret_cast<void**>(&L.counters), 2 * sizeof(unsigned int))) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&L.phi), sizeof(double) * (size_t)total) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&L.partials), sizeof(double) * 16 * (size_t)items) != hipSuccess) {
+    (void)hipGetLastError();
+    batch_free(b);
+    return fail(SYN_ENOMEM, "device allocation of the batch plan failed");
+  }
+  e = hipMemcpy(dsets, sets.data(), sizeof(sm::BatchSet) * sets.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(e, "hipMemcpy batch sets");
+  }
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess || cus < 1) cus = 256;
+  L.blocks_fwd = cus * sm::batch_blocks_per_cu(S, false);
+  L.blocks_adj = cus * sm::batch_blocks_per_cu(S, true);
+  if (b->use_graph) {
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e, "hipStreamCreate");
+    }
+  }
+  *plan = b;
+  return SYN_OK;
+}
+
+int64_t syn_batch_total_pixels(const syn_batch* plan) { return plan ? plan->L.total : -1; }
+
+int64_t syn_batch_offset(const syn_batch* plan, int32_t set) {
+  if (plan == nullptr || set < 0 || set >= plan->L.n_sets) return -1;
+  return plan->offsets[set];
+}
+
+syn_status syn_batch_run(syn_batch* plan, const float* target, const double* inv_sigma2,
+                         float* maps, float* dmaps, double* chi2, double* dtheta,
+                         hipStream_t stream) {
+  if (plan == nullptr) return fail(SYN_EINVAL, "plan is NULL");
+  if (target == nullptr || inv_sigma2 == nullptr || maps == nullptr || dmaps == nullptr ||
+      chi2 == nullptr || dtheta == nullptr)
+    return fail(SYN_EINVAL, "target, inv_sigma2, maps, dmaps, chi2 and dtheta are required");
+  if (((uintptr_t)chi2 & 7) != 0 || ((uintptr_t)dtheta & 7) != 0) return fail(SYN_EINVAL, "chi2/dtheta misaligned");
+  for (int k = 0; k < 3; ++k)
+    if (!(isfinite(inv_sigma2[k]) && inv_sigma2[k] >= 0.0)) return fail(SYN_EINVAL, "inv_sigma2 must be finite and >= 0");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != plan->device) return fail(SYN_EINVAL, "plan belongs to another device");
+  sm::BatchLaunch& L = plan->L;
+  L.target = target;
+  for (int k = 0; k < 3; ++k) L.chi2_args.inv_s2[k] = inv_sigma2[k];
+  L.maps = maps;
+  L.dmaps = dmaps;
+  L.chi2 = chi2;
+  L.dtheta = dtheta;
+  if (!plan->use_graph) {
+    e = sm::launch_batch(L, stream);
+    return e == hipSuccess ? SYN_OK : hip_fail(e, "batch launch");
+  }
+  const void* key[5] = {target, maps, dmaps, chi2, dtheta};
+  bool same = plan->captured;
+  for (int k = 0; k < 5 && same; ++k) same = key[k] == plan->key[k];
+  for (int k = 0; k < 3 && same; ++k) same = inv_sigma2[k] == plan->key_inv[k];
+  if (!same) {
+    if (plan->exec) {
+      hipGraphExecDestroy(plan->exec);
+      plan->exec = nullptr;
+    }
+    if (plan->graph) {
+      hipGraphDestroy(plan->graph);
+      plan->graph = nullptr;
+    }
+    plan->captured = false;
+    e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = sm::launch_batch(L, plan->cap);
+    e = hipStreamEndCapture(plan->cap, &plan->graph);
+    if (le != hipSuccess) return hip_fail(le, "batch capture");
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    for (int k = 0; k < 5; ++k) plan->key[k] = key[k];
+    for (int k = 0; k < 3; ++k) plan->key_inv[k] = inv_sigma2[k];
+    plan->captured = true;
+  }
+  e = hipGraphLaunch(plan->exec, stream);
+  return e == hipSuccess ? SYN_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+void syn_batch_destroy(syn_batch* plan) { batch_free(plan); }
 
 }  // extern "C"

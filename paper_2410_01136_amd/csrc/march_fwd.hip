@@ -7,7 +7,7 @@
 // scan.  Sightlines are enumerated in HEALPix NESTED order, so one wavefront
 // covers a compact sky patch and its rays sample neighbouring grid cells; the
 // result is written at the RING index.
-#include "sm_device.h"
+#include "march_body.h"
 #include "sm_launch.h"
 
 namespace sm {
@@ -22,72 +22,7 @@ __global__ __launch_bounds__(256) void k_forward(GeomArgs g, FreqArgs fa, EmitAr
   int64_t q = tid / S;
   const bool valid = q < g.npix;
   if (!valid) q = g.npix - 1;  // idle lanes march a real sightline, results dropped
-  const Ray ray = make_ray(g, q);
-
-  double carry = 0.0;  // Faraday sum (n_e B_par, uG cm^-3) of all earlier chunks
-  double accI = 0.0;
-  double accQ[MF], accU[MF];
-#pragma unroll
-  for (int f = 0; f < MF; ++f) accQ[f] = accU[f] = 0.0;
-
-  for (int c0 = 0; c0 < g.n_steps; c0 += S) {
-    const int n = c0 + sub;
-    const bool act = n < g.n_steps;
-    const double s = ((double)n + 0.5) * ray.dkpc;  // midpoint of segment n
-    const float x = (float)(g.r_obs[0] + s * ray.nx);
-    const float y = (float)(g.r_obs[1] + s * ray.ny);
-    const float z = (float)(g.r_obs[2] + s * ray.nz);
-    const FV v = fld.eval(x, y, z);
-    const float bl = v.bx * ray.elx + v.by * ray.ely;
-    const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
-    const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);
-    const double cn = act ? (double)v.ne * bpar : 0.0;
-    double psi;  // Faraday sum at the midpoint: earlier segments + half of this one
-    if constexpr (S == 1) {
-      psi = carry + 0.5 * cn;
-      carry += cn;
-    } else {
-      const double incl = group_inclusive_scan<S>(cn, sub);
-      psi = carry + incl - 0.5 * cn;
-      carry += group_bcast<S>(incl, S - 1);
-    }
-    Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
-    if (!act) e.u = e.zr = e.zi = 0.0f;
-    accI += (double)e.u;
-    const double psid = psi * ray.dkpc;
-#pragma unroll
-    for (int f = 0; f < MF; ++f) {
-      if (f < fa.n_freq) {
-        const double t = psid * fa.kappa[f];  // turns of 2 RM lambda^2
-        const float fr = (float)(t - rint(t));
-        float sn, cs;
-        sincos_turns(fr, &sn, &cs);
-        accQ[f] += (double)(e.zr * cs - e.zi * sn);
-        accU[f] += (double)(e.zr * sn + e.zi * cs);
-      }
-    }
-  }
-
-  if constexpr (S > 1) {
-    accI = group_sum<S>(accI);
-#pragma unroll
-    for (int f = 0; f < MF; ++f) {
-      accQ[f] = group_sum<S>(accQ[f]);
-      accU[f] = group_sum<S>(accU[f]);
-    }
-  }
-  if (valid && sub == 0) {
-    const int64_t np = g.npix;
-#pragma unroll
-    for (int f = 0; f < MF; ++f) {
-      if (f < fa.n_freq) {
-        maps[(3 * f + 0) * np + ray.ring] = (float)(fa.sI[f] * ray.dkpc * accI);
-        maps[(3 * f + 1) * np + ray.ring] = (float)(fa.sP[f] * ray.dkpc * accQ[f]);
-        maps[(3 * f + 2) * np + ray.ring] = (float)(fa.sP[f] * ray.dkpc * accU[f]);
-      }
-    }
-    if (phi_end != nullptr) phi_end[ray.ring] = carry;
-  }
+  fwd_lane<F, S, MF>(g, fa, ea, fld, q, sub, valid, maps, MapAddr{g.npix, 0}, phi_end);
 }
 
 template <class F, int S>

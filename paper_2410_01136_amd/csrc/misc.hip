@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_eval_fields(F fld, int64_t n, const flo
                                                      float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const FV f = fld.eval(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+  const FV f = fld.eval_point(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
   out[5 * i + 0] = f.bx;
   out[5 * i + 1] = f.by;
   out[5 * i + 2] = f.bz;

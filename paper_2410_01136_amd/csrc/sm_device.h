@@ -188,6 +188,19 @@ struct Model16 {
     return v;
   }
 
+  // fields at distance s [kpc] along the ray (position rounded to FP32 once)
+  __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
+    return eval((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
+                (float)(g.r_obs[2] + s * r.nz));
+  }
+  __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
+                                double* tb) const {
+    vjp((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
+        (float)(g.r_obs[2] + s * r.nz), gv, tb);
+  }
+
+  __device__ inline FV eval_point(float x, float y, float z) const { return eval(x, y, z); }
+
   // cosmic-ray normalisation alone (grids with an analytic N0)
   __device__ inline float n0_at(float x, float y, float z) const {
     const float rho = __builtin_sqrtf(x * x + y * y);
@@ -255,7 +268,11 @@ struct Model16 {
   }
 };
 
-// Trilinear interpolation of node-centred grids.
+// Trilinear interpolation of node-centred grids.  The cell coordinate
+// u = (r - lo) / h is formed in FP64 straight from the distance along the ray
+// (u = u0 + s du with per-ray constants), so the interpolation weights carry
+// no FP32 rounding of the position (which on a rough grid would add ~1e-5
+// relative noise to every field value).
 struct Grid {
   GridArgs p;
   Model16 cr;  // analytic N0 when p.c == nullptr
@@ -266,83 +283,135 @@ struct Grid {
     bool inside;
   };
 
-  __device__ inline Cell cell(float x, float y, float z) const {
+  __device__ inline Cell cell_at(const GeomArgs& g, const Ray& r, double s) const {
     Cell c;
-    c.inside = (x >= p.lo[0]) & (x <= p.hi[0]) & (y >= p.lo[1]) & (y <= p.hi[1]) &
-               (z >= p.lo[2]) & (z <= p.hi[2]);
-    // clamping before the integer conversion keeps every index in bounds, also
-    // for non-finite coordinates (fmaxf/fminf return the non-NaN operand)
-    const float ux = fminf(fmaxf((x - p.lo[0]) * p.inv_h[0], 0.0f), p.umax[0]);
-    const float uy = fminf(fmaxf((y - p.lo[1]) * p.inv_h[1], 0.0f), p.umax[1]);
-    const float uz = fminf(fmaxf((z - p.lo[2]) * p.inv_h[2], 0.0f), p.umax[2]);
-    const int ix = min((int)ux, p.n[0] - 2);
-    const int iy = min((int)uy, p.n[1] - 2);
-    const int iz = min((int)uz, p.n[2] - 2);
-    c.tx = ux - (float)ix;
-    c.ty = uy - (float)iy;
-    c.tz = uz - (float)iz;
-    c.base = (int64_t)ix + (int64_t)p.n[0] * ((int64_t)iy + (int64_t)p.n[1] * (int64_t)iz);
+    const double n3[3] = {r.nx, r.ny, r.nz};
+    int i3[3];
+    float t3[3];
+    bool in = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      // hoisted by the compiler: n_k / h_k and (r_obs_k - lo_k) / h_k
+      const double u = s * (n3[k] * p.inv_h[k]) + (g.r_obs[k] - p.lo[k]) * p.inv_h[k];
+      in = in && (u >= 0.0) && (u <= p.umax[k]);
+      // clamping before the integer conversion keeps every index in bounds, also
+      // for non-finite input (fmax/fmin return the non-NaN operand)
+      const double uc = fmin(fmax(u, 0.0), p.umax[k]);
+      const double fl = fmin(floor(uc), p.umax[k] - 1.0);
+      i3[k] = (int)fl;
+      t3[k] = (float)(uc - fl);
+    }
+    c.inside = in;
+    c.tx = t3[0];
+    c.ty = t3[1];
+    c.tz = t3[2];
+    c.base = (int64_t)i3[0] + (int64_t)p.n[0] * ((int64_t)i3[1] + (int64_t)p.n[1] * (int64_t)i3[2]);
     return c;
   }
 
-  __device__ inline FV eval(float x, float y, float z) const {
-    const Cell c = cell(x, y, z);
+  __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
+    const Cell c = cell_at(g, r, s);
     const int64_t sy = p.n[0], sz = (int64_t)p.n[0] * p.n[1];
-    const float4* g = p.bn;
-    const float4 v000 = g[c.base], v100 = g[c.base + 1];
-    const float4 v010 = g[c.base + sy], v110 = g[c.base + sy + 1];
-    const float4 v001 = g[c.base + sz], v101 = g[c.base + sz + 1];
-    const float4 v011 = g[c.base + sy + sz], v111 = g[c.base + sy + sz + 1];
+    const float4* gb = p.bn;
+    const float4 v000 = gb[c.base], v100 = gb[c.base + 1];
+    const float4 v010 = gb[c.base + sy], v110 = gb[c.base + sy + 1];
+    const float4 v001 = gb[c.base + sz], v101 = gb[c.base + sz + 1];
+    const float4 v011 = gb[c.base + sy + sz], v111 = gb[c.base + sy + sz + 1];
+    const float in = c.inside ? 1.0f : 0.0f;
     const float wx0 = 1.0f - c.tx, wy0 = 1.0f - c.ty, wz0 = 1.0f - c.tz;
-    const float w00 = wy0 * wz0, w10 = c.ty * wz0, w01 = wy0 * c.tz, w11 = c.ty * c.tz;
+    const float y0z0 = in * wy0 * wz0, y1z0 = in * c.ty * wz0;
+    const float y0z1 = in * wy0 * c.tz, y1z1 = in * c.ty * c.tz;
+    const float w000 = wx0 * y0z0, w100 = c.tx * y0z0, w010 = wx0 * y1z0, w110 = c.tx * y1z0;
+    const float w001 = wx0 * y0z1, w101 = c.tx * y0z1, w011 = wx0 * y1z1, w111 = c.tx * y1z1;
     auto tri = [&](float a000, float a100, float a010, float a110, float a001, float a101,
                    float a011, float a111) {
-      return w00 * (wx0 * a000 + c.tx * a100) + w10 * (wx0 * a010 + c.tx * a110) +
-             w01 * (wx0 * a001 + c.tx * a101) + w11 * (wx0 * a011 + c.tx * a111);
+      return w000 * a000 + w100 * a100 + w010 * a010 + w110 * a110 + w001 * a001 + w101 * a101 +
+             w011 * a011 + w111 * a111;
     };
     FV v;
-    const float in = c.inside ? 1.0f : 0.0f;
-    v.bx = in * tri(v000.x, v100.x, v010.x, v110.x, v001.x, v101.x, v011.x, v111.x);
-    v.by = in * tri(v000.y, v100.y, v010.y, v110.y, v001.y, v101.y, v011.y, v111.y);
-    v.bz = in * tri(v000.z, v100.z, v010.z, v110.z, v001.z, v101.z, v011.z, v111.z);
-    v.ne = in * tri(v000.w, v100.w, v010.w, v110.w, v001.w, v101.w, v011.w, v111.w);
+    v.bx = tri(v000.x, v100.x, v010.x, v110.x, v001.x, v101.x, v011.x, v111.x);
+    v.by = tri(v000.y, v100.y, v010.y, v110.y, v001.y, v101.y, v011.y, v111.y);
+    v.bz = tri(v000.z, v100.z, v010.z, v110.z, v001.z, v101.z, v011.z, v111.z);
+    v.ne = tri(v000.w, v100.w, v010.w, v110.w, v001.w, v101.w, v011.w, v111.w);
     if (p.c != nullptr) {
       const float* gc = p.c;
-      v.n0 = in * tri(gc[c.base], gc[c.base + 1], gc[c.base + sy], gc[c.base + sy + 1],
-                      gc[c.base + sz], gc[c.base + sz + 1], gc[c.base + sy + sz],
-                      gc[c.base + sy + sz + 1]);
+      v.n0 = tri(gc[c.base], gc[c.base + 1], gc[c.base + sy], gc[c.base + sy + 1], gc[c.base + sz],
+                 gc[c.base + sz + 1], gc[c.base + sy + sz], gc[c.base + sy + sz + 1]);
     } else {
-      v.n0 = cr.n0_at(x, y, z);
+      v.n0 = cr.n0_at((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
+                      (float)(g.r_obs[2] + s * r.nz));
     }
     return v;
   }
 
-  // theta-gradient of a grid field: only an analytic N0 depends on theta
-  __device__ inline void vjp(float x, float y, float z, const FV& g, double* tb) const {
-    if (p.c == nullptr) cr.vjp_n0(x, y, z, g.n0, tb);
+  // fields at a point: the same code path with the point as the ray origin
+  __device__ inline FV eval_point(float x, float y, float z) const {
+    GeomArgs g{};
+    g.r_obs[0] = x;
+    g.r_obs[1] = y;
+    g.r_obs[2] = z;
+    Ray r{};
+    return eval_at(g, r, 0.0);
   }
 
-  // Scatters dL/d(field) at (x, y, z) onto the 8 corner nodes (atomic adds).
-  __device__ inline void scatter(float x, float y, float z, const FV& g, float* gbn,
-                                 float* gc) const {
-    const Cell c = cell(x, y, z);
-    if (!c.inside) return;
+  // theta-gradient of a grid field: only an analytic N0 depends on theta
+  __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
+                                double* tb) const {
+    if (p.c == nullptr)
+      cr.vjp_n0((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
+                (float)(g.r_obs[2] + s * r.nz), gv.n0, tb);
+  }
+
+  // Gradient accumulator of one lane: the 8 corners x 5 channels of the cell the
+  // lane is in.  Consecutive steps of a sightline mostly stay in one cell, so
+  // contributions are summed in registers and sent to memory (atomic adds)
+  // only when the lane leaves the cell.
+  struct Acc {
+    int64_t base = -1;
+    float a[8][5];
+  };
+
+  __device__ inline void flush(Acc& A, float* gbn, float* gc) const {
+    if (A.base < 0) return;
     const int64_t sy = p.n[0], sz = (int64_t)p.n[0] * p.n[1];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t v = A.base + (k & 1) + ((k >> 1) & 1) * sy + (k >> 2) * sz;
+      if (gbn != nullptr) {
+        unsafeAtomicAdd(gbn + 4 * v + 0, A.a[k][0]);
+        unsafeAtomicAdd(gbn + 4 * v + 1, A.a[k][1]);
+        unsafeAtomicAdd(gbn + 4 * v + 2, A.a[k][2]);
+        unsafeAtomicAdd(gbn + 4 * v + 3, A.a[k][3]);
+      }
+      if (gc != nullptr && p.c != nullptr) unsafeAtomicAdd(gc + v, A.a[k][4]);
+    }
+    A.base = -1;
+  }
+
+  // Adds dL/d(field) at distance s, spread over the cell's 8 corner nodes.
+  __device__ inline void accumulate_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
+                                       Acc& A, float* gbn, float* gc) const {
+    const Cell c = cell_at(g, r, s);
+    if (!c.inside) return;
+    if (c.base != A.base) {
+      flush(A, gbn, gc);
+      A.base = c.base;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 5; ++ch) A.a[k][ch] = 0.0f;
+    }
     const float wx[2] = {1.0f - c.tx, c.tx};
     const float wy[2] = {1.0f - c.ty, c.ty};
     const float wz[2] = {1.0f - c.tz, c.tz};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-      const float w = wx[dx] * wy[dy] * wz[dz];
-      const int64_t v = c.base + dx + dy * sy + dz * sz;
-      if (gbn != nullptr) {
-        unsafeAtomicAdd(gbn + 4 * v + 0, w * g.bx);
-        unsafeAtomicAdd(gbn + 4 * v + 1, w * g.by);
-        unsafeAtomicAdd(gbn + 4 * v + 2, w * g.bz);
-        unsafeAtomicAdd(gbn + 4 * v + 3, w * g.ne);
-      }
-      if (gc != nullptr && p.c != nullptr) unsafeAtomicAdd(gc + v, w * g.n0);
+      const float w = wx[k & 1] * wy[(k >> 1) & 1] * wz[k >> 2];
+      A.a[k][0] = fmaf(w, gv.bx, A.a[k][0]);
+      A.a[k][1] = fmaf(w, gv.by, A.a[k][1]);
+      A.a[k][2] = fmaf(w, gv.bz, A.a[k][2]);
+      A.a[k][3] = fmaf(w, gv.ne, A.a[k][3]);
+      A.a[k][4] = fmaf(w, gv.n0, A.a[k][4]);
     }
   }
 };
@@ -350,6 +419,11 @@ struct Grid {
 // Homogeneous sphere (Sec. 2.4 test).
 struct Sphere {
   SphereArgs p;
+  __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
+    return eval((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
+                (float)(g.r_obs[2] + s * r.nz));
+  }
+  __device__ inline FV eval_point(float x, float y, float z) const { return eval(x, y, z); }
   __device__ inline FV eval(float x, float y, float z) const {
     const float dx = x - p.c[0], dy = y - p.c[1], dz = z - p.c[2];
     const bool in = (p.r2 <= 0.0f) || (dx * dx + dy * dy + dz * dz < p.r2);
@@ -438,8 +512,30 @@ __device__ inline EmitBar emission_vjp(float n0, float bl, float bb, bool alpha3
   return r;
 }
 
-// sin and cos of 2 pi t for |t| <= 1/2.
-__device__ inline void sincos_turns(float t, float* s, float* c) { sincospif(2.0f * t, s, c); }
+// sin(2 pi t) and cos(2 pi t) of a turn count t held in FP64.  t is reduced
+// modulo one in FP64 (exact), then to a quarter turn |r| <= 1/4 around the
+// nearest half turn in FP32 (exact), where odd/even polynomials fitted to
+// sin(2 pi r) and cos(2 pi r) (weighted least squares on Chebyshev nodes,
+// refined toward minimax) give |error| <= 2.1e-7 in FP32 Horner form.
+__device__ inline void sincos_turns(double t, float* sn, float* cs) {
+  const float t1 = (float)(t - rint(t));  // [-1/2, 1/2]
+  const float k2 = rintf(2.0f * t1);      // -1, 0, 1 half turns
+  const float r = fmaf(-0.5f, k2, t1);    // [-1/4, 1/4]
+  const float x2 = r * r;
+  float s = fmaf(x2, 3.953670502e+01f, -7.654978180e+01f);
+  s = fmaf(x2, s, 8.160100555e+01f);
+  s = fmaf(x2, s, -4.134165573e+01f);
+  s = fmaf(x2, s, 6.283185005e+00f);
+  s *= r;
+  float c = fmaf(x2, -2.498223686e+01f, 6.014401627e+01f);
+  c = fmaf(x2, c, -8.545357513e+01f);
+  c = fmaf(x2, c, 6.493934631e+01f);
+  c = fmaf(x2, c, -1.973920822e+01f);
+  c = fmaf(x2, c, 1.0f);
+  const bool flip = k2 != 0.0f;  // an odd number of half turns negates both
+  *sn = flip ? -s : s;
+  *cs = flip ? -c : c;
+}
 
 // ---------------------------------------------------------------------------
 // Sub-wavefront scans over groups of S consecutive lanes.

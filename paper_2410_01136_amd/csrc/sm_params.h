@@ -31,7 +31,7 @@ struct GridArgs {
   const float4* bn;  // [nz][ny][nx] x (Bx, By, Bz, n_e)
   const float* c;    // [nz][ny][nx] N0 or nullptr
   int32_t n[3];
-  float lo[3], hi[3], inv_h[3], umax[3];
+  double lo[3], inv_h[3], umax[3];  // umax = n - 1
 };
 
 struct SphereArgs {

@@ -155,15 +155,22 @@ def grf(shape_zyx: Sequence[int], spacing_zyx: Sequence[float], seed: int,
     amp = k2 ** (slope / 4.0)  # sqrt(P) = k^(slope/2) = (k^2)^(slope/4)
     amp[0, 0, 0] = 0.0
     fk *= amp
-    g = np.fft.irfftn(fk, s=(nz, ny, nx))
+    g = np.fft.irfftn(fk, s=(nz, ny, nx), axes=(0, 1, 2))
     g /= g.std()
     return g.astype(np.float32)
 
 
-def turbulent_grids(reg_bn: np.ndarray, seeds=(1001, 1002, 1003, 1004),
-                    lo=BOX_LO, hi=BOX_HI, b_frac: float = 0.5,
-                    ne_sigma: float = 0.5) -> np.ndarray:
-    """Add the seeded random fluctuations to a regular B/n_e node grid.
+def turbulence_noise(shape_zyx: Sequence[int], seeds=(1001, 1002, 1003, 1004), lo=BOX_LO,
+                     hi=BOX_HI) -> np.ndarray:
+    """Four unit-variance k^-11/3 fields [4][nz][ny][nx] (B_x, B_y, B_z, n_e)."""
+    nz, ny, nx = (int(v) for v in shape_zyx)
+    spacing = [(hi[2] - lo[2]) / (nz - 1), (hi[1] - lo[1]) / (ny - 1), (hi[0] - lo[0]) / (nx - 1)]
+    return np.stack([grf((nz, ny, nx), spacing, s) for s in seeds])
+
+
+def apply_turbulence(reg_bn: np.ndarray, noise: np.ndarray, b_frac: float = 0.5,
+                     ne_sigma: float = 0.5) -> np.ndarray:
+    """Add seeded random fluctuations to a regular B/n_e node grid.
 
     reg_bn: [nz][ny][nx][4] float32 (Bx, By, Bz [uG], n_e [cm^-3]) sampled from
     the analytic model by the caller.  B gets a local Gaussian fluctuation of
@@ -171,17 +178,20 @@ def turbulent_grids(reg_bn: np.ndarray, seeds=(1001, 1002, 1003, 1004),
     k^-11/3 field); n_e is multiplied by exp(s g - s^2 / 2), s = ne_sigma
     (lognormal, mean preserving).  Returns a new float32 array.
     """
-    nz, ny, nx, _ = reg_bn.shape
-    spacing = [(hi[2] - lo[2]) / (nz - 1), (hi[1] - lo[1]) / (ny - 1), (hi[0] - lo[0]) / (nx - 1)]
     out = np.array(reg_bn, dtype=np.float32, copy=True)
     bmag = np.sqrt((reg_bn[..., :3].astype(np.float64) ** 2).sum(-1))
     for k in range(3):
-        g = grf((nz, ny, nx), spacing, seeds[k])
-        out[..., k] += (b_frac / math.sqrt(3.0) * bmag * g).astype(np.float32)
-        del g
-    g = grf((nz, ny, nx), spacing, seeds[3])
-    out[..., 3] = (reg_bn[..., 3] * np.exp(ne_sigma * g - 0.5 * ne_sigma ** 2)).astype(np.float32)
+        out[..., k] += (b_frac / math.sqrt(3.0) * bmag * noise[k]).astype(np.float32)
+    out[..., 3] = (reg_bn[..., 3] * np.exp(ne_sigma * noise[3] - 0.5 * ne_sigma ** 2)).astype(np.float32)
     return out
+
+
+def turbulent_grids(reg_bn: np.ndarray, seeds=(1001, 1002, 1003, 1004),
+                    lo=BOX_LO, hi=BOX_HI, b_frac: float = 0.5,
+                    ne_sigma: float = 0.5) -> np.ndarray:
+    """apply_turbulence with freshly generated noise of the given seeds."""
+    noise = turbulence_noise(reg_bn.shape[:3], seeds, lo, hi)
+    return apply_turbulence(reg_bn, noise, b_frac, ne_sigma)
 
 
 def chi2_noise(maps: np.ndarray, seed: int, frac: float = 0.01):

@@ -1,0 +1,173 @@
+"""Launch-shape autotuner for the march kernels.
+
+The one tunable of every kernel family is S, the number of lanes that share a
+sightline (1, 4, 16 or 64): larger S gives more parallelism for small maps
+(few sightlines), smaller S fewer scan instructions and more register reuse
+for large maps.  The tuner times each candidate with HIP events on the
+workload at hand and applies the fastest through syn_set_lanes_per_ray.
+Results are cached in a JSON file keyed by device, kernel-source hash and
+workload shape (environment variable SYNMARCH_TUNE_CACHE, default
+~/.cache/synmarch/tune.json); a missing or unreadable cache falls back to the
+built-in choice.
+"""
+from __future__ import annotations
+
+import glob
+import hashlib
+import json
+import os
+from typing import Callable, Dict, Iterable, Optional
+
+import torch
+
+from . import binding as sm
+
+CANDIDATES = (1, 4, 16, 64)
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def cache_path() -> str:
+    return os.environ.get("SYNMARCH_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "synmarch", "tune.json"))
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(_HERE, "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _key(kernel: int, kind: int, npix: int, n_steps: int, n_freq: int) -> str:
+    dev = torch.cuda.get_device_name(torch.cuda.current_device()) if torch.cuda.is_available() else "cpu"
+    return f"{dev}|{source_hash()}|k{kernel}|f{kind}|p{npix}|n{n_steps}|q{n_freq}"
+
+
+def load_cache(path: Optional[str] = None) -> Dict[str, int]:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return {k: int(v) for k, v in d.items() if int(v) in CANDIDATES}
+    except (OSError, ValueError, TypeError):
+        return {}
+
+
+def save_cache(d: Dict[str, int], path: Optional[str] = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_candidate(run: Callable[[], None], reps: int = 5) -> float:
+    """Median milliseconds of `run` over `reps` timed calls after one warm-up."""
+    run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(kernel: int, kind: int, shape, run: Callable[[], None],
+         candidates: Iterable[int] = CANDIDATES, reps: int = 5, use_cache: bool = True,
+         write_cache: bool = True) -> Dict[str, object]:
+    """Times `run` for every lane count and applies the fastest.
+
+    shape: (npix, n_steps, n_freq) of the workload, for the cache key.
+    Returns {"lanes": best, "ms": {S: ms}, "cached": bool}.
+    """
+    key = _key(kernel, kind, *shape)
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        sm.set_lanes_per_ray(kernel, kind, cache[key])
+        return {"lanes": cache[key], "ms": {}, "cached": True}
+    ms = {}
+    for S in candidates:
+        sm.set_lanes_per_ray(kernel, kind, S)
+        ms[S] = time_candidate(run, reps)
+    best = min(ms, key=ms.get)
+    sm.set_lanes_per_ray(kernel, kind, best)
+    if write_cache:
+        cache = load_cache()
+        cache[key] = best
+        try:
+            save_cache(cache)
+        except OSError:
+            pass
+    return {"lanes": best, "ms": ms, "cached": False}
+
+
+def tune_forward(geom, field, maps=None, ws=None, **kw):
+    npix = 12 * geom.nside ** 2
+    if maps is None:
+        maps = torch.empty((geom.n_freq, 3, npix), dtype=torch.float32, device="cuda")
+    return tune(sm.KERNEL_FORWARD, field.s.kind, (npix, geom.n_steps, geom.n_freq),
+                lambda: sm.forward(geom, field, maps=maps, ws=ws), **kw)
+
+
+def tune_adjoint(geom, field, dmaps, ws, want_theta=True, dgrid_bn=None, dgrid_c=None, **kw):
+    npix = 12 * geom.nside ** 2
+    return tune(sm.KERNEL_ADJOINT, field.s.kind, (npix, geom.n_steps, geom.n_freq),
+                lambda: sm.adjoint(geom, field, dmaps, ws, want_theta=want_theta,
+                                   dgrid_bn=dgrid_bn, dgrid_c=dgrid_c), **kw)
+
+
+def make_batch(thetas, nsides, geom, use_graph=True):
+    """Creates a batch plan (ctypes handle) for MODEL16 parameter sets."""
+    import ctypes
+    import numpy as np
+    desc = sm.SynBatchDesc()
+    ns = np.ascontiguousarray(nsides, dtype=np.int32)
+    th = np.ascontiguousarray(thetas, dtype=np.float64)
+    desc.n_sets = int(ns.size)
+    desc.nside = ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    desc.theta = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    desc.geom = geom
+    desc.use_graph = int(use_graph)
+    plan = ctypes.c_void_p()
+    sm.check(sm.syn_batch_create(ctypes.byref(desc), ctypes.byref(plan)), "syn_batch_create")
+    return plan
+
+
+def tune_batch(thetas, nsides, geom, target, inv_sigma2, candidates: Iterable[int] = CANDIDATES,
+               reps: int = 3, **kw):
+    """Tunes the lane count of the persistent many-set kernels (plans are
+    rebuilt per candidate, since a plan fixes its launch shape)."""
+    import numpy as np
+    total = int(sum(12 * int(n) ** 2 for n in nsides))
+    inv = np.ascontiguousarray(inv_sigma2, dtype=np.float64)
+    maps = torch.empty((3, total), dtype=torch.float32, device="cuda")
+    dmaps = torch.empty_like(maps)
+    chi2 = torch.empty(len(nsides), dtype=torch.float64, device="cuda")
+    dth = torch.empty((len(nsides), 16), dtype=torch.float64, device="cuda")
+    plans = {}
+
+    def runner():
+        cur = sm.get_lanes_per_ray(sm.KERNEL_BATCH, sm.FIELD_MODEL16, total)
+        if cur not in plans:
+            plans[cur] = make_batch(thetas, nsides, geom)
+
+        def run():
+            sm.check(sm.syn_batch_run(plans[cur], target.data_ptr(), inv.ctypes.data_as(sm._dp),
+                                      maps.data_ptr(), dmaps.data_ptr(), chi2.data_ptr(),
+                                      dth.data_ptr(), sm._stream()), "syn_batch_run")
+        run()
+
+    try:
+        return tune(sm.KERNEL_BATCH, sm.FIELD_MODEL16, (total, geom.n_steps, 1), runner,
+                    candidates=candidates, reps=reps, **kw)
+    finally:
+        torch.cuda.synchronize()
+        for p in plans.values():
+            sm.syn_batch_destroy(p)

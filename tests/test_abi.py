@@ -163,3 +163,21 @@ def test_library_pixel_order_matches_oracle_ring(sm, orc, nside):
         z2, phi2 = orc.pix2zphi(nside, ring)
         assert z == pytest.approx(z2, abs=1e-14) and phi == pytest.approx(phi2, abs=1e-13)
     assert seen.all()
+
+
+def test_batch_create_rejects_bad_input_on_host(sm):
+    import ctypes
+    thetas = np.ascontiguousarray(I.perturbed_thetas(2, seed=1))
+    g = I.geometry("C3", nside=4, n_steps=16)
+    for nsides, nfreq_ok in (([8, 3], True), ([8, 8], False)):
+        desc = sm.SynBatchDesc()
+        ns = np.array(nsides, dtype=np.int32)
+        desc.n_sets = 2
+        desc.nside = ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        desc.theta = thetas.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        desc.geom = sm.geom_from(g) if nfreq_ok else sm.make_geom(4, 16, [1e9, 2e9], r_max=20.0)
+        desc.use_graph = 1
+        plan = ctypes.c_void_p()
+        st = sm.syn_batch_create(ctypes.byref(desc), ctypes.byref(plan))
+        assert st == (sm.SYN_EINVAL if nfreq_ok else sm.SYN_EUNSUPPORTED)
+        assert not plan.value

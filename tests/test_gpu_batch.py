@@ -1,0 +1,149 @@
+"""Many parameter sets in one persistent, graph-captured launch.
+
+Every replay of the captured graph is checked against eager single-set calls
+of the same library (forward, chi^2, adjoint) with eager work and
+synchronisations in between, and two sets are checked against the oracle.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2410_01136_amd import inputs as I
+from parity import compare_maps, oracle_geom
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2410_01136_amd import binding
+    return binding
+
+
+@pytest.fixture
+def lanes(sm):
+    yield lambda k, S: sm.set_lanes_per_ray(k, sm.FIELD_MODEL16, S)
+    for k in range(3):
+        sm.set_lanes_per_ray(k, sm.FIELD_MODEL16, 0)
+
+
+def make_plan(sm, thetas, nsides, g, use_graph=True):
+    desc = sm.SynBatchDesc()
+    desc.n_sets = len(nsides)
+    ns = np.ascontiguousarray(nsides, dtype=np.int32)
+    th = np.ascontiguousarray(thetas, dtype=np.float64)
+    desc.nside = ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    desc.theta = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    desc.geom = sm.geom_from(g)
+    desc.use_graph = int(use_graph)
+    plan = ctypes.c_void_p()
+    sm.check(sm.syn_batch_create(ctypes.byref(desc), ctypes.byref(plan)), "syn_batch_create")
+    return plan
+
+
+@pytest.mark.parametrize("S", [1, 16])
+def test_batch_graph_replays_match_eager(sm, orc, lanes, S):
+    import torch
+    for k in range(3):
+        lanes(k, S)
+    nsides = [4, 8, 16, 8, 2, 16, 4]
+    thetas = I.perturbed_thetas(len(nsides), seed=3101)
+    g = I.geometry("C3", nside=4, n_steps=96)
+    plan = make_plan(sm, thetas, nsides, g)
+    try:
+        total = sm.syn_batch_total_pixels(plan)
+        offs = [sm.syn_batch_offset(plan, s) for s in range(len(nsides))]
+        assert offs[0] == 0 and total == sum(12 * n * n for n in nsides)
+        rng = np.random.default_rng(3103)
+        inv = np.array([4.0e4, 9.0e4, 9.0e4])
+        # targets: each set's map at slightly different parameters, ragged [3][total]
+        tgt = np.zeros((3, total), dtype=np.float32)
+        eager_maps = []
+        for s, ns in enumerate(nsides):
+            gs = I.geometry("C3", nside=ns, n_steps=96)
+            th2 = thetas[s] * (1 + 0.02 * rng.standard_normal(16))
+            th2[12] = thetas[s][12]
+            m = sm.forward(sm.geom_from(gs), sm.model16(th2)).cpu().numpy()[0]
+            tgt[:, offs[s]:offs[s] + 12 * ns * ns] = m
+        tgt_t = torch.from_numpy(tgt).cuda()
+        maps = torch.empty((3, total), dtype=torch.float32, device="cuda")
+        dmaps = torch.empty_like(maps)
+        chi2 = torch.empty(len(nsides), dtype=torch.float64, device="cuda")
+        dth = torch.empty((len(nsides), 16), dtype=torch.float64, device="cuda")
+        # eager single-set reference
+        ref_maps, ref_dm, ref_chi, ref_dth = [], [], [], []
+        for s, ns in enumerate(nsides):
+            gs = I.geometry("C3", nside=ns, n_steps=96)
+            geom = sm.geom_from(gs)
+            f = sm.model16(thetas[s])
+            ws = sm.alloc_workspace(geom, f)
+            m = sm.forward(geom, f, ws=ws)
+            c, dm = sm.chi2(m, tgt_t[:, offs[s]:offs[s] + 12 * ns * ns].contiguous().view(1, 3, -1), inv)
+            d = sm.adjoint(geom, f, dm, ws)
+            ref_maps.append(m.cpu().numpy()[0])
+            ref_dm.append(dm.cpu().numpy()[0])
+            ref_chi.append(c.item())
+            ref_dth.append(d.cpu().numpy())
+        for rep in range(3):
+            maps.fill_(np.nan)
+            dth.fill_(np.nan)
+            st = sm.syn_batch_run(plan, tgt_t.data_ptr(), inv.ctypes.data_as(sm._dp), maps.data_ptr(),
+                                  dmaps.data_ptr(), chi2.data_ptr(), dth.data_ptr(),
+                                  sm._stream())
+            sm.check(st, "syn_batch_run")
+            torch.cuda.synchronize()
+            # eager work between replays
+            _ = (maps * 2).sum().item()
+            mh, dmh, ch, dh = maps.cpu().numpy(), dmaps.cpu().numpy(), chi2.cpu().numpy(), dth.cpu().numpy()
+            for s, ns in enumerate(nsides):
+                sl = slice(offs[s], offs[s] + 12 * ns * ns)
+                np.testing.assert_array_equal(mh[:, sl], ref_maps[s])
+                np.testing.assert_array_equal(dmh[:, sl], ref_dm[s])
+                assert ch[s] == pytest.approx(ref_chi[s], rel=1e-12)
+                np.testing.assert_allclose(dh[s], ref_dth[s], rtol=1e-10,
+                                           atol=1e-12 * np.abs(ref_dth[s]).max())
+        # two sets against the oracle
+        for s in (1, 5):
+            gs = I.geometry("C3", nside=nsides[s], n_steps=96)
+            ref = orc.forward(oracle_geom(orc, gs), orc.Field(orc.MODEL16, thetas[s]))
+            sl = slice(offs[s], offs[s] + 12 * nsides[s] ** 2)
+            ok, rep = compare_maps(mh[None, :, sl], ref)
+            assert ok, rep
+            rth, _, _ = orc.adjoint(oracle_geom(orc, gs), orc.Field(orc.MODEL16, thetas[s]),
+                                    dmh[None, :, sl].astype(np.float64))
+            sk = np.maximum(np.abs(thetas[s]), 1e-2)
+            assert np.all(np.abs(dh[s] - rth) * sk <= 1e-3 * np.abs(rth * sk).max())
+    finally:
+        sm.syn_batch_destroy(plan)
+
+
+def test_batch_without_graph_equals_graph(sm):
+    import torch
+    nsides = [8, 4, 8]
+    thetas = I.perturbed_thetas(3, seed=3201)
+    g = I.geometry("C3", nside=4, n_steps=64)
+    outs = []
+    for use_graph in (True, False):
+        plan = make_plan(sm, thetas, nsides, g, use_graph=use_graph)
+        try:
+            total = sm.syn_batch_total_pixels(plan)
+            tgt = torch.zeros((3, total), dtype=torch.float32, device="cuda")
+            inv = np.ones(3)
+            maps = torch.empty((3, total), dtype=torch.float32, device="cuda")
+            dmaps = torch.empty_like(maps)
+            chi2 = torch.empty(3, dtype=torch.float64, device="cuda")
+            dth = torch.empty((3, 16), dtype=torch.float64, device="cuda")
+            for _ in range(2):
+                sm.check(sm.syn_batch_run(plan, tgt.data_ptr(), inv.ctypes.data_as(sm._dp),
+                                          maps.data_ptr(), dmaps.data_ptr(), chi2.data_ptr(),
+                                          dth.data_ptr(), sm._stream()), "run")
+            torch.cuda.synchronize()
+            outs.append((maps.cpu().numpy(), chi2.cpu().numpy(), dth.cpu().numpy()))
+        finally:
+            sm.syn_batch_destroy(plan)
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
