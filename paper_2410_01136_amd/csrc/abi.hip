@@ -61,19 +61,24 @@ double digamma_host(double x) {
 // ---- launch shapes ----------------------------------------------------------
 std::atomic<int> g_lanes[3][4];  // [kernel family][field kind], 0 = default
 
-int default_lanes(int64_t npix) {
-  // enough lanes to give every SIMD of the 256 CUs several waves
-  const int64_t target = 1 << 19;
-  for (int S : {1, 4, 16}) {
-    if (npix * S >= target) return S;
+// Built-in lanes per sightline, from autotuner runs on MI355X: small maps need
+// many lanes per sightline to fill 256 CUs; large maps prefer fewer (less scan
+// work, better locality).  The many-set kernels and the grid-gradient adjoint
+// (which accumulates per cell in registers along consecutive steps) use 1.
+int default_lanes(int kernel, int kind, int64_t npix) {
+  if (kernel == SYN_KERNEL_BATCH) return 1;
+  if (kernel == SYN_KERNEL_ADJOINT) {
+    if (kind == SYN_FIELD_GRID) return 1;
+    return npix < (1 << 14) ? 16 : 4;
   }
-  return 64;
+  if (npix < (1 << 14)) return 64;
+  return npix < (1 << 22) ? 16 : 4;
 }
 
 int lanes_for(int kernel, int kind, int64_t npix) {
   const int s = (kernel >= 0 && kernel < 3 && kind >= 0 && kind < 4) ? g_lanes[kernel][kind].load()
                                                                       : 0;
-  return s > 0 ? s : default_lanes(npix);
+  return s > 0 ? s : default_lanes(kernel, kind, npix);
 }
 
 // ---- argument checks --------------------------------------------------------
