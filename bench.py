@@ -99,6 +99,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batched workloads")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in launch shapes")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the coordinate-MLP surrogate")
+    ap.add_argument("--surrogate-steps", type=int, default=2000, help="training steps of the surrogate")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample")
     ap.add_argument("--only", choices=("c1", "copy"), default=None,
@@ -207,6 +209,8 @@ def main() -> int:
     if not args.no_extras:
         out["adjoint"] = bench_adjoint(sm, I, np, torch, tune, args)
         out["batched"] = bench_batched(sm, I, np, torch, tune, args)
+    if not args.no_surrogate:
+        out["surrogate"] = bench_surrogate(sm, I, np, torch, args, field)
 
     # ---------------------------------------------------------------- oracle leg
     if not args.no_cpu_baseline:
@@ -365,6 +369,54 @@ def bench_batched(sm, I, np, torch, tune, args):
         "lanes_per_ray": sm.get_lanes_per_ray(sm.KERNEL_BATCH, sm.FIELD_MODEL16, total),
     }
     log("C3 batched:", res)
+    return res
+
+
+def bench_surrogate(sm, I, np, torch, args, grid_field):
+    """C4: coordinate MLP trained on 1e7 points of the gridded fields, fused into the
+    march (BF16 MFMA, FP32 accumulation) at N_side 512, 1024 steps, 1 GHz; timed and
+    judged against the plain trilinear march of the same fields on the same GPU."""
+    from paper_2410_01136_amd import surrogate as S
+    tr = S.train(lambda pts: sm.eval_fields(grid_field, pts), I.BOX_LO, I.BOX_HI,
+                 n_points=10_000_000, steps=args.surrogate_steps, seed=4001, init_seed=4002,
+                 log=log)
+    log(f"surrogate trained: {tr.seconds:.1f} s, final loss {tr.final_loss:.4e}")
+    packed = S.pack(tr.model)
+    mf = S.mlp_field(tr.model, packed, alpha=3.0)
+    g = I.geometry("C4")
+    geom = sm.geom_from(g)
+    m_mlp = torch.empty((1, 3, g.npix), dtype=torch.float32, device="cuda")
+    m_grid = torch.empty_like(m_mlp)
+    s_wall, s_ev = time_launches(lambda: sm.forward(geom, mf, maps=m_mlp), 3, 1)
+    p_wall, p_ev = time_launches(lambda: sm.forward(geom, grid_field, maps=m_grid), 10, 2)
+    a = m_mlp[0].double()
+    b = m_grid[0].double()
+    rms = lambda x: float(torch.sqrt((x * x).mean()))
+    pa = torch.hypot(a[1], a[2])
+    pb = torch.hypot(b[1], b[2])
+    units = g.npix * g.n_steps
+    flops = 2.0 * (32 * 128 + 3 * 128 * 128 + 128 * 5) * units
+    res = {
+        "workload": "N_side 512 (3,145,728 sightlines), 1024 steps, 1 GHz, 40x40x8 kpc box; MLP 3 -> "
+                    "16 Fourier -> 4 x 128 GELU -> 5, BF16 weights, FP32 accumulation",
+        "train_seconds": round(tr.seconds, 1), "train_steps": tr.steps,
+        "train_loss_standardised": tr.final_loss,
+        "surrogate_ms": round(s_ev, 2),
+        "surrogate_sightline_steps_per_s": float(f"{units / (s_ev * 1e-3):.4e}"),
+        "mfma_tflops": round(flops / (s_ev * 1e-3) / 1e12, 2),
+        "mfma_frac_of_bf16_peak": round(flops / (s_ev * 1e-3) / 2.5e15, 4),
+        "plain_trilinear_ms": round(p_ev, 3),
+        "plain_sightline_steps_per_s": float(f"{units / (p_ev * 1e-3):.4e}"),
+        "surrogate_over_plain_time": round(s_ev / p_ev, 2),
+        "map_error_vs_plain": {
+            "I_rel_rms": rms(a[0] - b[0]) / rms(b[0]),
+            "Q_rel_rms": rms(a[1] - b[1]) / rms(b[1]),
+            "U_rel_rms": rms(a[2] - b[2]) / rms(b[2]),
+            "PI_rel_rms": rms(pa - pb) / rms(pb),
+            "I_median_abs_rel": float(torch.median(torch.abs(a[0] - b[0]) / torch.abs(b[0]))),
+        },
+    }
+    log("C4 surrogate:", res)
     return res
 
 

@@ -82,6 +82,9 @@ def _load():
     lib.or_sample_model16.argtypes = [dp, ctypes.POINTER(ctypes.c_int32), dp, dp,
                                       ctypes.c_void_p, ctypes.c_void_p]
     lib.or_num_threads.restype = ctypes.c_int
+    lib.or_midpoints.argtypes = [gp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
+    lib.or_forward_tabulated.argtypes = [gp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_int64, dp, dp]
     _lib = lib
     return lib
 
@@ -244,3 +247,29 @@ def rayleigh_jeans(nu):
 
 def num_threads():
     return _load().or_num_threads()
+
+
+def midpoints(geom: _Geom, pix) -> np.ndarray:
+    """Sightline midpoints [n][n_steps][3] (kpc) of the given pixels."""
+    lib = _load()
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    out = np.zeros((pix.size, geom.n_steps, 3))
+    if lib.or_midpoints(ctypes.byref(geom), pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                        pix.size, _dptr(out)) != 0:
+        raise ValueError("oracle rejected the request")
+    return out
+
+
+def forward_tabulated(geom: _Geom, alpha: float, pix, fields) -> np.ndarray:
+    """The march over given field samples fields[n][n_steps][5] -> [n][n_freq][3] (K)."""
+    lib = _load()
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    fl = np.ascontiguousarray(fields, dtype=np.float64)
+    if fl.shape != (pix.size, geom.n_steps, 5):
+        raise ValueError("fields must be [n_pix][n_steps][5]")
+    out = np.zeros((pix.size, geom.n_freq, 3))
+    if lib.or_forward_tabulated(ctypes.byref(geom), float(alpha),
+                                pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), pix.size,
+                                _dptr(fl), _dptr(out)) != 0:
+        raise ValueError("oracle rejected the request")
+    return out

@@ -449,9 +449,28 @@ typedef struct {
   double chi0;
 } or_local;
 
-static void or_local_eval(const or_field* f, const or_ray* ray, const double r[3], or_local* q) {
-  double B[3], ne, n0;
-  or_fields(f, r, B, &ne, &n0);
+/* Field values at midpoint n of a sightline: either a field model evaluated at
+   the midpoint r, or a table of samples given by the caller. */
+typedef struct {
+  const or_field* f;       /* field model, or NULL for a table */
+  const double* table;     /* [n_steps][5] = Bx, By, Bz [uG], n_e, N0 */
+} or_source;
+
+static void or_source_eval(const or_source* src, int n, const double r[3], double B[3], double* ne,
+                           double* n0) {
+  if (src->f != NULL) {
+    or_fields(src->f, r, B, ne, n0);
+  } else {
+    const double* v = src->table + 5 * (int64_t)n;
+    B[0] = v[0];
+    B[1] = v[1];
+    B[2] = v[2];
+    *ne = v[3];
+    *n0 = v[4];
+  }
+}
+
+static void or_local_from(const or_ray* ray, const double B[3], double ne, double n0, or_local* q) {
   double bl = 0, bb = 0, bn = 0;
   for (int k = 0; k < 3; ++k) {
     bl += B[k] * ray->el[k];
@@ -467,20 +486,28 @@ static void or_local_eval(const or_field* f, const or_ray* ray, const double r[3
   q->chi0 = atan2(q->num, q->den);
 }
 
+static void or_local_eval(const or_field* f, const or_ray* ray, const double r[3], or_local* q) {
+  double B[3], ne, n0;
+  or_fields(f, r, B, &ne, &n0);
+  or_local_from(ray, B, ne, n0, q);
+}
+
 /* Forward march of one pixel: out[f][3] = T_I, T_Q, T_U [K]; returns the
    total Faraday depth sum of the segment increments [rad cm^-2]. */
-static double or_march_pixel(const or_geom* g, const or_field* f, int64_t p, double* out) {
+static double or_march_source(const or_geom* g, const or_source* src, double alpha, int64_t p,
+                              double* out) {
   or_ray ray;
   or_make_ray(g, p, &ray);
-  const double alpha = f->theta[12];
   const double krm = or_k_rm();
   double I[OR_MAX_FREQ] = {0}, Q[OR_MAX_FREQ] = {0}, U[OR_MAX_FREQ] = {0};
   double rm_before = 0.0; /* integral of n_e B_LOS over all earlier segments */
   for (int n = 0; n < g->n_steps; ++n) {
     double r[3];
     or_midpoint(g, &ray, n, r);
+    double B[3], ne, n0;
+    or_source_eval(src, n, r, B, &ne, &n0);
     or_local q;
-    or_local_eval(f, &ray, r, &q);
+    or_local_from(&ray, B, ne, n0, &q);
     const double seg = q.ne * q.blos * ray.dcm;
     const double RM = krm * (rm_before + 0.5 * seg);
     rm_before += seg;
@@ -502,6 +529,11 @@ static double or_march_pixel(const or_geom* g, const or_field* f, int64_t p, dou
     out[3 * k + 2] = rj * U[k];
   }
   return krm * rm_before;
+}
+
+static double or_march_pixel(const or_geom* g, const or_field* f, int64_t p, double* out) {
+  const or_source src = {f, NULL};
+  return or_march_source(g, &src, f->theta[12], p, out);
 }
 
 static int or_check(const or_geom* g, const or_field* f) {
@@ -539,6 +571,35 @@ int or_forward_pixels(const or_geom* g, const or_field* f, const int64_t* pix, i
   for (int64_t i = 0; i < n; ++i) {
     double ph = or_march_pixel(g, f, pix[i], out + i * 3 * g->n_freq);
     if (phi_end) phi_end[i] = ph;
+  }
+  return 0;
+}
+
+/* Midpoints of the given pixels' sightlines: out[i][n][3] (kpc). */
+int or_midpoints(const or_geom* g, const int64_t* pix, int64_t n, double* out) {
+  if (g->nside < 1 || g->n_steps < 1) return -1;
+  const int64_t npix = 12LL * g->nside * g->nside;
+  for (int64_t i = 0; i < n; ++i) {
+    if (pix[i] < 0 || pix[i] >= npix) return -1;
+    or_ray ray;
+    or_make_ray(g, pix[i], &ray);
+    for (int k = 0; k < g->n_steps; ++k) or_midpoint(g, &ray, k, out + (i * g->n_steps + k) * 3);
+  }
+  return 0;
+}
+
+/* The march over tabulated field samples: fields[i][n][5] = (Bx, By, Bz [uG],
+   n_e, N0) at midpoint n of pixel pix[i]; out[i][f][3] in K. */
+int or_forward_tabulated(const or_geom* g, double alpha, const int64_t* pix, int64_t n,
+                         const double* fields, double* out) {
+  if (g->nside < 1 || g->n_steps < 1 || g->n_freq < 1 || g->n_freq > OR_MAX_FREQ) return -1;
+  const int64_t npix = 12LL * g->nside * g->nside;
+  for (int64_t i = 0; i < n; ++i)
+    if (pix[i] < 0 || pix[i] >= npix) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; ++i) {
+    const or_source src = {NULL, fields + i * (int64_t)g->n_steps * 5};
+    or_march_source(g, &src, alpha, pix[i], out + i * 3 * g->n_freq);
   }
   return 0;
 }

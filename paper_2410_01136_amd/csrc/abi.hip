@@ -211,8 +211,21 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
       s.r2 = f->theta[5] > 0.0 ? (float)(f->theta[5] * f->theta[5]) : 0.0f;
       return SYN_OK;
     }
-    case SYN_FIELD_MLP:
-      return fail(SYN_EUNSUPPORTED, "MLP fields are not available in this build");
+    case SYN_FIELD_MLP: {
+      if (for_adjoint) return fail(SYN_EUNSUPPORTED, "the MLP surrogate has no adjoint");
+      if (f->mlp == nullptr || ((uintptr_t)f->mlp & 15) != 0)
+        return fail(SYN_EINVAL, "mlp must be a 16-byte aligned device pointer to syn_mlp_pack output");
+      for (int k = 0; k < 3; ++k)
+        if (!(isfinite(f->grid_lo_kpc[k]) && isfinite(f->grid_hi_kpc[k]) &&
+              f->grid_lo_kpc[k] < f->grid_hi_kpc[k]))
+          return fail(SYN_EINVAL, "the MLP needs a finite normalisation box grid_lo < grid_hi");
+      fp->mlp.packed = f->mlp;
+      for (int k = 0; k < 3; ++k) {
+        fp->mlp.lo[k] = (float)f->grid_lo_kpc[k];
+        fp->mlp.scale[k] = (float)(2.0 / (f->grid_hi_kpc[k] - f->grid_lo_kpc[k]));
+      }
+      return SYN_OK;
+    }
     default:
       return fail(SYN_EINVAL, "unknown field kind");
   }
@@ -290,8 +303,13 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
   }
   sm::FreqArgs fa;
   freq_args(geom, field->theta[12], &fa);
-  const int S = lanes_for(SYN_KERNEL_FORWARD, field->kind, ga.npix);
-  hipError_t e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, stream);
+  hipError_t e;
+  if (field->kind == SYN_FIELD_MLP) {
+    e = sm::launch_forward_mlp(ga, fa, emit_args(field->theta[12]), fp.mlp, maps, phi_end, stream);
+  } else {
+    const int S = lanes_for(SYN_KERNEL_FORWARD, field->kind, ga.npix);
+    e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "forward launch");
   return SYN_OK;
 }
@@ -376,7 +394,8 @@ syn_status syn_eval_fields(const syn_field* field, int64_t n, const float* xyz, 
   if (n < 0) return fail(SYN_EINVAL, "n must be >= 0");
   if (n == 0) return SYN_OK;
   if (xyz == nullptr || out == nullptr) return fail(SYN_EINVAL, "xyz and out are required");
-  hipError_t e = sm::launch_eval_fields(fp, n, xyz, out, stream);
+  hipError_t e = field->kind == SYN_FIELD_MLP ? sm::launch_eval_mlp(fp.mlp, n, xyz, out, stream)
+                                              : sm::launch_eval_fields(fp, n, xyz, out, stream);
   if (e != hipSuccess) return hip_fail(e, "eval launch");
   return SYN_OK;
 }

@@ -10,8 +10,8 @@ namespace sm {
 enum FieldKind { kModel16 = 0, kGrid = 1, kSphere = 2, kMlp = 3 };
 
 struct MlpArgs {
-  const void* packed;  // device, layout of mlp_layout.h
-  float lo[3], scale[3];  // x^ = (r - lo) * scale - 1
+  const void* packed;     // device, layout of mlp_layout.h
+  float lo[3], scale[3];  // x^ = (r - lo) * scale - 1, scale = 2 / (hi - lo)
 };
 
 struct FieldPack {
@@ -45,5 +45,10 @@ hipError_t launch_sample_model16(const M16Args& m, const int32_t n[3], const dou
 
 hipError_t launch_eval_fields(const FieldPack& fp, int64_t n, const float* xyz, float* out,
                               hipStream_t st);
+
+hipError_t launch_forward_mlp(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                              const MlpArgs& m, float* maps, double* phi_end, hipStream_t st);
+hipError_t launch_eval_mlp(const MlpArgs& m, int64_t n, const float* xyz, float* out,
+                           hipStream_t st);
 
 }  // namespace sm

@@ -1,0 +1,93 @@
+"""The coordinate-MLP surrogate on the matrix cores.
+
+* Field level: the kernel's network vs a plain PyTorch FP32 evaluation of the
+  same BF16 weights with BF16-rounded layer inputs.  The two differ only where
+  an FP32 pre-activation falls on the other side of a BF16 rounding boundary
+  (summation order), so the bound is a few BF16 ulps of the output scale.
+* March level: the fused march vs the FP64 oracle marching over the PyTorch
+  reference fields sampled at the oracle's own midpoints.
+"""
+import numpy as np
+import pytest
+
+from paper_2410_01136_amd import inputs as I
+from parity import oracle_geom
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2410_01136_amd import binding, surrogate
+    return binding, surrogate, torch
+
+
+def make_model(surrogate, torch, seed=21):
+    m = surrogate.FieldMLP(I.BOX_LO, I.BOX_HI, seed=seed).cuda()
+    # physical output ranges: B ~ uG, n_e ~ 0.02 cm^-3, N0 ~ 4e-5 cm^-3
+    m.out_scale.copy_(torch.tensor([3.0, 3.0, 3.0, 0.5, 0.3]))
+    m.out_shift.copy_(torch.tensor([0.0, 0.0, 0.0, -4.0, -10.1]))
+    return m
+
+
+@pytest.mark.parametrize("n", [1, 64, 5001])
+def test_mlp_fields_match_reference(env, n):
+    sm, S, torch = env
+    model = make_model(S, torch)
+    packed = S.pack(model)
+    f = S.mlp_field(model, packed)
+    rng = np.random.default_rng(n)
+    pts = torch.from_numpy(rng.uniform(I.BOX_LO, I.BOX_HI, (n, 3)).astype(np.float32)).cuda()
+    got = sm.eval_fields(f, pts)
+    ref = S.reference_eval(model, pts)
+    torch.cuda.synchronize()
+    g, r = got.cpu().numpy().astype(np.float64), ref.cpu().numpy().astype(np.float64)
+    # compare B linearly and n_e, N0 in log space
+    g[:, 3:] = np.log(g[:, 3:])
+    r[:, 3:] = np.log(r[:, 3:])
+    scale = np.maximum(np.abs(r).max(0), 1e-30)
+    err = np.abs(g - r) / scale
+    print("MLP fields: max", err.max(0), "median", np.median(err, 0), flush=True)
+    assert np.all(err <= 5e-3)
+    assert np.all(np.median(err, 0) <= 2e-4)
+
+
+def test_mlp_march_vs_oracle_on_reference_fields(env, orc):
+    sm, S, torch = env
+    model = make_model(S, torch, seed=22)
+    packed = S.pack(model)
+    f = S.mlp_field(model, packed, alpha=3.0)
+    # 200 steps: three full 64-step tiles and a ragged one; 5 GHz keeps the
+    # Faraday phase moderate so single BF16 flips do not dominate Q/U
+    g = I.geometry("C1", nside=8, n_steps=200, freqs_hz=(3.0e9, 5.0e9))
+    maps = sm.forward(sm.geom_from(g), f)
+    torch.cuda.synchronize()
+    gpu = maps.cpu().numpy()
+    og = oracle_geom(orc, g)
+    pix = np.arange(g.npix)
+    mids = orc.midpoints(og, pix)
+    with torch.no_grad():
+        fl = S.reference_eval(model, torch.from_numpy(mids.reshape(-1, 3).astype(np.float32)).cuda())
+    fields = fl.cpu().numpy().astype(np.float64).reshape(g.npix, g.n_steps, 5)
+    ref = np.transpose(orc.forward_tabulated(og, 3.0, pix, fields), (1, 2, 0))
+    dI = np.abs(gpu[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
+    pi = np.hypot(ref[:, 1], ref[:, 2])
+    dP = np.maximum(np.abs(gpu[:, 1] - ref[:, 1]), np.abs(gpu[:, 2] - ref[:, 2])) / pi
+    print("MLP march: I max", dI.max(), "median", np.median(dI), "| Q/U over PI max", dP.max(),
+          "median", np.median(dP), flush=True)
+    assert np.median(dI) <= 1e-4 and dI.max() <= 2e-3
+    assert np.median(dP) <= 1e-3 and dP.max() <= 5e-2
+
+
+def test_mlp_adjoint_is_rejected(env):
+    sm, S, torch = env
+    model = make_model(S, torch)
+    f = S.mlp_field(model, S.pack(model))
+    g = sm.geom_from(I.geometry("C4", nside=2, n_steps=16))
+    ws = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    dm = torch.zeros((1, 3, 48), dtype=torch.float32, device="cuda")
+    with pytest.raises(sm.SynError):
+        sm.adjoint(g, f, dm, ws)

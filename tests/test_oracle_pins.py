@@ -407,3 +407,26 @@ def test_grid_with_analytic_cr_matches_model(orc):
         assert np.allclose(B, Bm, rtol=1e-6, atol=1e-6)
         assert ne == pytest.approx(nem, rel=1e-6)
         assert n0 == n0m
+
+
+def test_tabulated_march_equals_field_march(orc):
+    # marching over tabulated samples of a field gives the same maps as marching
+    # over the field itself (the table path only replaces the field evaluation)
+    th = I.perturbed_thetas(1, 77)[0]
+    g = orc.make_geom(4, 40, [0.9e9, 2e9], r_max=20.0)
+    f = orc.Field(orc.MODEL16, th)
+    pix = np.array([0, 5, 77, 130, 191])
+    mids = orc.midpoints(g, pix)
+    tab = np.zeros((pix.size, 40, 5))
+    for i in range(pix.size):
+        for n in range(40):
+            B, ne, n0 = orc.fields_at(f, mids[i, n])
+            tab[i, n] = [*B, ne, n0]
+    ref = orc.forward_pixels(g, f, pix)
+    got = orc.forward_tabulated(g, th[12], pix, tab)
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+    # midpoints lie at (n + 1/2) L / N from the observer
+    n_hat = mids[:, 1] - mids[:, 0]
+    d = np.linalg.norm(mids - np.array(g.r_obs[:])[None, None, :], axis=-1)
+    step = np.linalg.norm(n_hat, axis=-1)
+    np.testing.assert_allclose(d, (np.arange(40)[None, :] + 0.5) * step[:, None], rtol=1e-12)
