@@ -55,7 +55,9 @@ __global__ __launch_bounds__(256) void k_batch_fwd(const BatchSet* __restrict__ 
 }
 
 struct Model16NoScatter : Model16 {
-  struct Acc {};
+  struct Acc {
+    float* lds = nullptr;
+  };
   __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
                                        float*) const {}
   __device__ inline void flush(Acc&, float*, float*) const {}

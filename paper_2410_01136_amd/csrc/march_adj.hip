@@ -31,8 +31,19 @@ __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitAr
   double tb[THETA ? kNParam : 1];
 #pragma unroll
   for (int k = 0; k < (THETA ? kNParam : 1); ++k) tb[k] = 0.0;
+  float* box = nullptr;
+  if constexpr (GRID) {
+    __shared__ float lds_box[kAdjBoxFloats];
+    for (int j = threadIdx.x; j < kAdjBoxFloats; j += 256) lds_box[j] = 0.0f;
+    __syncthreads();
+    box = lds_box;
+  }
   adj_lane<F, S, MF, THETA, GRID>(g, fa, ea, fld, q, sub, valid, dmaps, MapAddr{g.npix, 0}, phi_end,
-                                  tb, gbn, gc);
+                                  tb, gbn, gc, box);
+  if constexpr (GRID) {
+    __syncthreads();
+    fld.flush_box(box, gbn, gc, threadIdx.x, 256);
+  }
   if constexpr (THETA) {
     const double r = block_reduce16(tb, threadIdx.x);
     if (threadIdx.x < kNParam) partials[blk * kNParam + threadIdx.x] = r;
@@ -107,10 +118,13 @@ static hipError_t adj_s(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& e
 
 // Model16 fields have no grid to scatter into.
 struct Model16NoGrid : Model16 {
-  struct Acc {};
+  struct Acc {
+    float* lds = nullptr;
+  };
   __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
                                        float*) const {}
   __device__ inline void flush(Acc&, float*, float*) const {}
+  __device__ inline void flush_box(const float*, float*, float*, int, int) const {}
 };
 
 hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,

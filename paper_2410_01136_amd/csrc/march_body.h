@@ -52,7 +52,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     } else {
       const double incl = group_inclusive_scan<S>(cn, sub);
       psi = carry + incl - 0.5 * cn;
-      carry += group_bcast<S>(incl, S - 1);
+      carry += group_last<S>(incl);
     }
     Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
     if (!act) e.u = e.zr = e.zi = 0.0f;
@@ -97,7 +97,7 @@ template <class F, int S, int MF, bool THETA, bool GRID, class FA>
 __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, const float* __restrict__ dmaps,
                                 MapAddr ma, const double* __restrict__ phi_end, double* tb,
-                                float* gbn, float* gc) {
+                                float* gbn, float* gc, float* lds_box = nullptr) {
   const Ray ray = make_ray(g, q);
   const double dk = ray.dkpc;
 
@@ -122,6 +122,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   }
 
   typename F::Acc acc;                                 // grid-gradient accumulator
+  if constexpr (GRID) acc.lds = lds_box;
   double E = valid ? phi_end[ma.off + ray.ring] : 0.0;  // sum over steps before the chunk end
   double suf = 0.0;                                    // phase cotangents of later chunks
   double accI = 0.0, accPr[MF], accPi[MF];
@@ -144,7 +145,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       psi = E + 0.5 * cn;
     } else {
       const double incl = group_inclusive_scan<S>(cn, sub);
-      const double tot = group_bcast<S>(incl, S - 1);
+      const double tot = group_last<S>(incl);
       psi = E - tot + incl - 0.5 * cn;
       E -= tot;
     }
@@ -177,7 +178,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       suf += pb;
     } else {
       const double sincl = group_suffix_scan<S>(pb, sub);
-      const double stot = group_bcast<S>(sincl, 0);
+      const double stot = group_first<S>(sincl);
       cbar = suf + sincl - 0.5 * pb;
       suf += stot;
     }

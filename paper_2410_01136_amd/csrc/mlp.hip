@@ -46,26 +46,12 @@ __device__ inline float gelu_tanh(float x) {
   return x * frcp(1.0f + e);
 }
 
-// sin and cos of 2 pi t in FP32 (reduction to a quarter turn, the same fitted
-// polynomials as the phase rotation).
+// sin and cos of 2 pi t in FP32: reduced to [-1/2, 1/2] turn, then the
+// hardware sine and cosine (argument in turns).
 __device__ inline void sincos_turns_f(float t, float* sn, float* cs) {
-  const float t1 = t - rintf(t);
-  const float k2 = rintf(2.0f * t1);
-  const float r = fmaf(-0.5f, k2, t1);
-  const float x2 = r * r;
-  float s = fmaf(x2, 3.953670502e+01f, -7.654978180e+01f);
-  s = fmaf(x2, s, 8.160100555e+01f);
-  s = fmaf(x2, s, -4.134165573e+01f);
-  s = fmaf(x2, s, 6.283185005e+00f);
-  s *= r;
-  float c = fmaf(x2, -2.498223686e+01f, 6.014401627e+01f);
-  c = fmaf(x2, c, -8.545357513e+01f);
-  c = fmaf(x2, c, 6.493934631e+01f);
-  c = fmaf(x2, c, -1.973920822e+01f);
-  c = fmaf(x2, c, 1.0f);
-  const bool flip = k2 != 0.0f;
-  *sn = flip ? -s : s;
-  *cs = flip ? -c : c;
+  const float r = t - rintf(t);
+  *sn = __builtin_amdgcn_sinf(r);
+  *cs = __builtin_amdgcn_cosf(r);
 }
 
 // Copies the packed network from global memory into LDS (whole workgroup).
@@ -208,7 +194,7 @@ __global__ __launch_bounds__(512) void k_forward_mlp(GeomArgs g, FreqArgs fa, Em
       const double cn = act ? (double)v.ne * bpar : 0.0;
       const double incl = group_inclusive_scan<64>(cn, lane);
       const double psi = carry + incl - 0.5 * cn;
-      carry += group_bcast<64>(incl, 63);
+      carry += group_last<64>(incl);
       Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
       if (!act) e.u = e.zr = e.zi = 0.0f;
       accI += (double)e.u;

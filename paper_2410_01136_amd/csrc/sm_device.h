@@ -279,6 +279,7 @@ struct Grid {
 
   struct Cell {
     int64_t base;  // node index of the (0, 0, 0) corner
+    int ix, iy, iz;
     float tx, ty, tz;
     bool inside;
   };
@@ -293,15 +294,19 @@ struct Grid {
     for (int k = 0; k < 3; ++k) {
       // hoisted by the compiler: n_k / h_k and (r_obs_k - lo_k) / h_k
       const double u = s * (n3[k] * p.inv_h[k]) + (g.r_obs[k] - p.lo[k]) * p.inv_h[k];
+      // inside the grid box: 0 <= u <= n - 1 (the last cell takes its upper face)
       in = in && (u >= 0.0) && (u <= p.umax[k]);
-      // clamping before the integer conversion keeps every index in bounds, also
-      // for non-finite input (fmax/fmin return the non-NaN operand)
-      const double uc = fmin(fmax(u, 0.0), p.umax[k]);
-      const double fl = fmin(floor(uc), p.umax[k] - 1.0);
+      // cell index clamped to [0, n - 2] before the integer conversion, so the
+      // conversion is defined and every corner read is in bounds for any u
+      // (fmax/fmin return the non-NaN operand)
+      const double fl = fmin(fmax(floor(u), 0.0), p.umax[k] - 1.0);
       i3[k] = (int)fl;
-      t3[k] = (float)(uc - fl);
+      t3[k] = (float)(u - fl);
     }
     c.inside = in;
+    c.ix = i3[0];
+    c.iy = i3[1];
+    c.iz = i3[2];
     c.tx = t3[0];
     c.ty = t3[1];
     c.tz = t3[2];
@@ -317,10 +322,9 @@ struct Grid {
     const float4 v010 = gb[c.base + sy], v110 = gb[c.base + sy + 1];
     const float4 v001 = gb[c.base + sz], v101 = gb[c.base + sz + 1];
     const float4 v011 = gb[c.base + sy + sz], v111 = gb[c.base + sy + sz + 1];
-    const float in = c.inside ? 1.0f : 0.0f;
     const float wx0 = 1.0f - c.tx, wy0 = 1.0f - c.ty, wz0 = 1.0f - c.tz;
-    const float y0z0 = in * wy0 * wz0, y1z0 = in * c.ty * wz0;
-    const float y0z1 = in * wy0 * c.tz, y1z1 = in * c.ty * c.tz;
+    const float y0z0 = wy0 * wz0, y1z0 = c.ty * wz0;
+    const float y0z1 = wy0 * c.tz, y1z1 = c.ty * c.tz;
     const float w000 = wx0 * y0z0, w100 = c.tx * y0z0, w010 = wx0 * y1z0, w110 = c.tx * y1z0;
     const float w001 = wx0 * y0z1, w101 = c.tx * y0z1, w011 = wx0 * y1z1, w111 = c.tx * y1z1;
     auto tri = [&](float a000, float a100, float a010, float a110, float a001, float a101,
@@ -329,14 +333,18 @@ struct Grid {
              w011 * a011 + w111 * a111;
     };
     FV v;
-    v.bx = tri(v000.x, v100.x, v010.x, v110.x, v001.x, v101.x, v011.x, v111.x);
-    v.by = tri(v000.y, v100.y, v010.y, v110.y, v001.y, v101.y, v011.y, v111.y);
-    v.bz = tri(v000.z, v100.z, v010.z, v110.z, v001.z, v101.z, v011.z, v111.z);
-    v.ne = tri(v000.w, v100.w, v010.w, v110.w, v001.w, v101.w, v011.w, v111.w);
+    // outside the grid box the gridded fields are zero (a select, so that the
+    // meaningless weights of such points never reach the result)
+    v.bx = c.inside ? tri(v000.x, v100.x, v010.x, v110.x, v001.x, v101.x, v011.x, v111.x) : 0.0f;
+    v.by = c.inside ? tri(v000.y, v100.y, v010.y, v110.y, v001.y, v101.y, v011.y, v111.y) : 0.0f;
+    v.bz = c.inside ? tri(v000.z, v100.z, v010.z, v110.z, v001.z, v101.z, v011.z, v111.z) : 0.0f;
+    v.ne = c.inside ? tri(v000.w, v100.w, v010.w, v110.w, v001.w, v101.w, v011.w, v111.w) : 0.0f;
     if (p.c != nullptr) {
       const float* gc = p.c;
-      v.n0 = tri(gc[c.base], gc[c.base + 1], gc[c.base + sy], gc[c.base + sy + 1], gc[c.base + sz],
-                 gc[c.base + sz + 1], gc[c.base + sy + sz], gc[c.base + sy + sz + 1]);
+      v.n0 = c.inside ? tri(gc[c.base], gc[c.base + 1], gc[c.base + sy], gc[c.base + sy + 1],
+                            gc[c.base + sz], gc[c.base + sz + 1], gc[c.base + sy + sz],
+                            gc[c.base + sy + sz + 1])
+                      : 0.0f;
     } else {
       v.n0 = cr.n0_at((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
                       (float)(g.r_obs[2] + s * r.nz));
@@ -364,15 +372,31 @@ struct Grid {
 
   // Gradient accumulator of one lane: the 8 corners x 5 channels of the cell the
   // lane is in.  Consecutive steps of a sightline mostly stay in one cell, so
-  // contributions are summed in registers and sent to memory (atomic adds)
-  // only when the lane leaves the cell.
+  // contributions are summed in registers and sent on only when the lane leaves
+  // the cell: into the workgroup's LDS box when the cell lies in the box around
+  // the observer (where all sightlines meet and global atomics would pile up on
+  // the same nodes), else straight to memory with atomic adds.
   struct Acc {
     int64_t base = -1;
+    int ix = 0, iy = 0, iz = 0;
     float a[8][5];
+    float* lds = nullptr;  // kAdjBoxFloats floats, or nullptr
   };
 
   __device__ inline void flush(Acc& A, float* gbn, float* gc) const {
     if (A.base < 0) return;
+    const int lx = A.ix - p.box0[0], ly = A.iy - p.box0[1], lz = A.iz - p.box0[2];
+    if (A.lds != nullptr && lx >= 0 && lx < kAdjBox - 1 && ly >= 0 && ly < kAdjBox - 1 && lz >= 0 &&
+        lz < kAdjBox - 1) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int j = ((lz + (k >> 2)) * kAdjBox + (ly + ((k >> 1) & 1))) * kAdjBox + lx + (k & 1);
+#pragma unroll
+        for (int ch = 0; ch < 5; ++ch) atomicAdd(A.lds + 5 * j + ch, A.a[k][ch]);
+      }
+      A.base = -1;
+      return;
+    }
     const int64_t sy = p.n[0], sz = (int64_t)p.n[0] * p.n[1];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -388,6 +412,26 @@ struct Grid {
     A.base = -1;
   }
 
+  // Adds a workgroup's LDS box to memory (after a barrier); nodes of the box
+  // that lie outside the grid hold zeros and are skipped.
+  __device__ inline void flush_box(const float* box, float* gbn, float* gc, int tid,
+                                   int nthreads) const {
+    for (int j = tid; j < kAdjBox * kAdjBox * kAdjBox; j += nthreads) {
+      const int gx = p.box0[0] + j % kAdjBox;
+      const int gy = p.box0[1] + (j / kAdjBox) % kAdjBox;
+      const int gz = p.box0[2] + j / (kAdjBox * kAdjBox);
+      if (gx >= p.n[0] || gy >= p.n[1] || gz >= p.n[2]) continue;
+      const int64_t v = (int64_t)gx + (int64_t)p.n[0] * ((int64_t)gy + (int64_t)p.n[1] * gz);
+      if (gbn != nullptr)
+        for (int ch = 0; ch < 4; ++ch) {
+          const float val = box[5 * j + ch];
+          if (val != 0.0f) unsafeAtomicAdd(gbn + 4 * v + ch, val);
+        }
+      if (gc != nullptr && p.c != nullptr && box[5 * j + 4] != 0.0f)
+        unsafeAtomicAdd(gc + v, box[5 * j + 4]);
+    }
+  }
+
   // Adds dL/d(field) at distance s, spread over the cell's 8 corner nodes.
   __device__ inline void accumulate_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
                                        Acc& A, float* gbn, float* gc) const {
@@ -396,6 +440,9 @@ struct Grid {
     if (c.base != A.base) {
       flush(A, gbn, gc);
       A.base = c.base;
+      A.ix = c.ix;
+      A.iy = c.iy;
+      A.iz = c.iz;
 #pragma unroll
       for (int k = 0; k < 8; ++k)
 #pragma unroll
@@ -512,52 +559,68 @@ __device__ inline EmitBar emission_vjp(float n0, float bl, float bb, bool alpha3
   return r;
 }
 
-// sin(2 pi t) and cos(2 pi t) of a turn count t held in FP64.  t is reduced
-// modulo one in FP64 (exact), then to a quarter turn |r| <= 1/4 around the
-// nearest half turn in FP32 (exact), where odd/even polynomials fitted to
-// sin(2 pi r) and cos(2 pi r) (weighted least squares on Chebyshev nodes,
-// refined toward minimax) give |error| <= 2.1e-7 in FP32 Horner form.
+// sin(2 pi t) and cos(2 pi t) of a turn count t held in FP64: t is reduced
+// modulo one in FP64 (exact), and the hardware sine and cosine, which take
+// their argument in turns, act on the reduced FP32 value in [-1/2, 1/2]
+// (measured on MI355X over 2^20 + 1 points of that range: |error| <= 1.24e-7,
+// mean error below 1e-9, i.e. no bias).
 __device__ inline void sincos_turns(double t, float* sn, float* cs) {
-  const float t1 = (float)(t - rint(t));  // [-1/2, 1/2]
-  const float k2 = rintf(2.0f * t1);      // -1, 0, 1 half turns
-  const float r = fmaf(-0.5f, k2, t1);    // [-1/4, 1/4]
-  const float x2 = r * r;
-  float s = fmaf(x2, 3.953670502e+01f, -7.654978180e+01f);
-  s = fmaf(x2, s, 8.160100555e+01f);
-  s = fmaf(x2, s, -4.134165573e+01f);
-  s = fmaf(x2, s, 6.283185005e+00f);
-  s *= r;
-  float c = fmaf(x2, -2.498223686e+01f, 6.014401627e+01f);
-  c = fmaf(x2, c, -8.545357513e+01f);
-  c = fmaf(x2, c, 6.493934631e+01f);
-  c = fmaf(x2, c, -1.973920822e+01f);
-  c = fmaf(x2, c, 1.0f);
-  const bool flip = k2 != 0.0f;  // an odd number of half turns negates both
-  *sn = flip ? -s : s;
-  *cs = flip ? -c : c;
+  const float r = (float)(t - rint(t));
+  *sn = __builtin_amdgcn_sinf(r);
+  *cs = __builtin_amdgcn_cosf(r);
 }
 
 // ---------------------------------------------------------------------------
 // Sub-wavefront scans over groups of S consecutive lanes.
 // ---------------------------------------------------------------------------
+// A double moved across lanes by a DPP control (both 32-bit halves); lanes
+// whose source lies outside their 16-lane row receive +0.0.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffu), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// DPP controls (row = 16 lanes): shift right / left by n within the row, and
+// read lane n of the row.
+constexpr int kDppRowShr = 0x110, kDppRowShl = 0x100, kDppRowShare = 0x150;
+
 template <int S>
 __device__ inline double group_inclusive_scan(double v, int sub) {
+  if constexpr (S == 16) {  // a group is exactly one DPP row
+    v += dpp_f64<kDppRowShr + 1>(v);
+    v += dpp_f64<kDppRowShr + 2>(v);
+    v += dpp_f64<kDppRowShr + 4>(v);
+    v += dpp_f64<kDppRowShr + 8>(v);
+    return v;
+  } else {
 #pragma unroll
-  for (int d = 1; d < S; d <<= 1) {
-    const double y = __shfl_up(v, d, S);
-    if (sub >= d) v += y;
+    for (int d = 1; d < S; d <<= 1) {
+      const double y = __shfl_up(v, d, S);
+      if (sub >= d) v += y;
+    }
+    return v;
   }
-  return v;
 }
 
 template <int S>
 __device__ inline double group_suffix_scan(double v, int sub) {
+  if constexpr (S == 16) {
+    v += dpp_f64<kDppRowShl + 1>(v);
+    v += dpp_f64<kDppRowShl + 2>(v);
+    v += dpp_f64<kDppRowShl + 4>(v);
+    v += dpp_f64<kDppRowShl + 8>(v);
+    return v;
+  } else {
 #pragma unroll
-  for (int d = 1; d < S; d <<= 1) {
-    const double y = __shfl_down(v, d, S);
-    if (sub + d < S) v += y;
+    for (int d = 1; d < S; d <<= 1) {
+      const double y = __shfl_down(v, d, S);
+      if (sub + d < S) v += y;
+    }
+    return v;
   }
-  return v;
 }
 
 template <int S>
@@ -569,7 +632,26 @@ __device__ inline double group_sum(double v) {
 
 template <int S>
 __device__ inline double group_bcast(double v, int lane_in_group) {
-  return (S == 1) ? v : __shfl(v, lane_in_group, S);
+  if constexpr (S == 1) {
+    return v;
+  } else {
+    return __shfl(v, lane_in_group, S);
+  }
+}
+
+// Value of the last (S - 1) or first (0) lane of the group, to every lane of it.
+template <int S>
+__device__ inline double group_last(double v) {
+  if constexpr (S == 1) return v;
+  else if constexpr (S == 16) return dpp_f64<kDppRowShare + 15>(v);
+  else return __shfl(v, S - 1, S);
+}
+
+template <int S>
+__device__ inline double group_first(double v) {
+  if constexpr (S == 1) return v;
+  else if constexpr (S == 16) return dpp_f64<kDppRowShare + 0>(v);
+  else return __shfl(v, 0, S);
 }
 
 // Hardware block id -> logical block id such that consecutive logical blocks

@@ -32,7 +32,13 @@ struct GridArgs {
   const float* c;    // [nz][ny][nx] N0 or nullptr
   int32_t n[3];
   double lo[3], inv_h[3], umax[3];  // umax = n - 1
+  int32_t box0[3];   // first node of the adjoint's LDS accumulation box
 };
+
+// Nodes per axis of the box around the observer in which the grid adjoint
+// accumulates gradients in LDS (every sightline starts there).
+constexpr int kAdjBox = 12;
+constexpr int kAdjBoxFloats = kAdjBox * kAdjBox * kAdjBox * 5;
 
 struct SphereArgs {
   float b[3];

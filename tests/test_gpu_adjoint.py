@@ -172,3 +172,30 @@ def test_c2_full_size_theta_gradient(sm, orc):
     ref, _, _ = orc.adjoint(og, orc.Field(orc.MODEL16, I.THETA0), ref_dm)
     assert chi.item() == pytest.approx((inv[..., None] * (ref_maps - target) ** 2).sum(), rel=1e-3)
     assert_theta_close(dth, ref, I.THETA0, "C2 full")
+
+
+@pytest.mark.parametrize("S", [1, 4])
+def test_grid_gradient_sub_box(sm, orc, lanes, S):
+    # grid box smaller than the geometry box, fewer nodes than the LDS box on z
+    import torch
+    lo, hi = (-12.0, -10.0, -3.0), (12.0, 10.0, 3.0)
+    reg_bn, reg_c = orc.sample_model16(THETA_T, (21, 19, 7), lo, hi)
+    bn = I.turbulent_grids(reg_bn, seeds=(2301, 2302, 2303, 2304), lo=lo, hi=hi)
+    g = I.geometry("C2", nside=8, n_steps=64, freqs_hz=(1.4e9,))
+    dm = I.cotangents((1, 3, g.npix), seed=26)
+    lanes(sm.FIELD_GRID, S)
+    bn_t, c_t = torch.from_numpy(bn).cuda(), torch.from_numpy(reg_c).cuda()
+    field = sm.grid(THETA_T, bn_t, c_t, lo, hi)
+    geom = sm.geom_from(g)
+    ws = sm.alloc_workspace(geom, field)
+    sm.forward(geom, field, ws=ws)
+    dbn, dc = torch.zeros_like(bn_t), torch.zeros_like(c_t)
+    sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws, want_theta=False, dgrid_bn=dbn,
+               dgrid_c=dc)
+    torch.cuda.synchronize()
+    ofield = orc.Field(orc.GRID, THETA_T, grid_bn=bn, grid_c=reg_c, grid_lo=lo, grid_hi=hi)
+    _, rbn, rc = orc.adjoint(oracle_geom(orc, g), ofield, dm.astype(np.float64), want_grid=True)
+    for a, b in ((dbn.cpu().numpy().astype(np.float64), rbn), (dc.cpu().numpy().astype(np.float64), rc)):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print(f"sub-box grid S={S}: rel L2 {rel:.2e}", flush=True)
+        assert rel <= 1e-3

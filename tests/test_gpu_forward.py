@@ -168,3 +168,19 @@ def test_c1_full_size_sampled(sm, orc):
     ref = np.transpose(ref, (1, 2, 0))  # [f][3][n]
     assert_parity(gpu[:, :, pix], ref, "C1 full size, sampled")
     assert np.isfinite(gpu).all()
+
+
+def test_grid_smaller_than_geometry_box(sm, orc, lanes):
+    # sightlines run past the grid box, where the gridded fields vanish (N0 too)
+    import torch
+    lo, hi = (-12.0, -10.0, -3.0), (12.0, 10.0, 3.0)
+    reg_bn, reg_c = orc.sample_model16(I.THETA0, (25, 21, 13), lo, hi)
+    bn = I.turbulent_grids(reg_bn, seeds=(1201, 1202, 1203, 1204), lo=lo, hi=hi)
+    g = I.geometry("C1", nside=8, n_steps=160)
+    for S in (1, 16):
+        lanes(sm.FIELD_GRID, S)
+        ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.GRID, I.THETA0, grid_bn=bn, grid_c=reg_c,
+                                                         grid_lo=lo, grid_hi=hi))
+        gpu = run_gpu(sm, g, sm.grid(I.THETA0, torch.from_numpy(bn).cuda(),
+                                     torch.from_numpy(reg_c).cuda(), lo, hi))
+        assert_parity(gpu, ref, f"grid sub-box S={S}")
