@@ -24,7 +24,7 @@
  *     respect to the 16 analytic parameters and to grid voxels), which the
  *     tests pin against central finite differences of this same forward.
  *
- * Readings of passages the paper leaves open (each is listed in the design doc):
+ * Readings of passages the paper leaves open:
  *   - B_LOS is signed, B_par = -B.n (positive toward the observer); the paper
  *     writes an absolute value, which would stop field reversals cancelling.
  *   - The denominator of Eq. chi is read as -B.e_l = B_x sin l - B_y cos l

@@ -80,6 +80,7 @@ syn_batch_run = _sig("syn_batch_run", _i32, [_vp, _vp, _dp, _vp, _vp, _vp, _vp, 
 syn_batch_destroy = _sig("syn_batch_destroy", None, [_vp])
 syn_set_lanes_per_ray = _sig("syn_set_lanes_per_ray", _i32, [_i32, _i32, _i32])
 syn_get_lanes_per_ray = _sig("syn_get_lanes_per_ray", _i32, [_i32, _i32, _i64])
+syn_set_grid_addressing = _sig("syn_set_grid_addressing", _i32, [_i32])
 syn_host_nest_pixel = _sig("syn_host_nest_pixel", _i32,
                            [_i32, _i64, ctypes.POINTER(_i64), _dp, _dp])
 
@@ -273,6 +274,11 @@ def eval_fields(field: Field, xyz: torch.Tensor, stream=None) -> torch.Tensor:
     check(syn_eval_fields(ctypes.byref(field.s), n, xyz.data_ptr(), out.data_ptr(),
                           _stream(stream)), "syn_eval_fields")
     return out
+
+
+def set_grid_addressing(mode: int) -> None:
+    """0: automatic (32-bit buffer offsets where the grid allows), 1: 64-bit addresses."""
+    check(syn_set_grid_addressing(mode), "syn_set_grid_addressing")
 
 
 def set_lanes_per_ray(kernel: int, kind: int, lanes: int) -> None:

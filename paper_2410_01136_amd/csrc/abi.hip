@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <string>
 #include <vector>
@@ -60,6 +61,7 @@ double digamma_host(double x) {
 
 // ---- launch shapes ----------------------------------------------------------
 std::atomic<int> g_lanes[3][4];  // [kernel family][field kind], 0 = default
+std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 always 64-bit
 
 // Built-in lanes per sightline, from autotuner runs on MI355X: small maps need
 // many lanes per sightline to fill 256 CUs; large maps prefer fewer (less scan
@@ -197,6 +199,15 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
         ga.inv_h[k] = (double)(f->grid_n[k] - 1) / (f->grid_hi_kpc[k] - f->grid_lo_kpc[k]);
         ga.umax[k] = (double)(f->grid_n[k] - 1);
       }
+      const uint64_t nx = (uint64_t)f->grid_n[0], nxy = nx * (uint64_t)f->grid_n[1];
+      const uint64_t nodes = nxy * (uint64_t)f->grid_n[2];
+      // 32-bit sizes and strides, used only when the whole grid fits them
+      ga.bn_bytes = (uint32_t)std::min<uint64_t>(nodes * 16, 0xFFFFFFFFull);
+      ga.c_bytes = (uint32_t)std::min<uint64_t>(nodes * 4, 0xFFFFFFFFull);
+      ga.sy16 = (uint32_t)std::min<uint64_t>(nx * 16, 0xFFFFFFFFull);
+      ga.sz16 = (uint32_t)std::min<uint64_t>(nxy * 16, 0xFFFFFFFFull);
+      ga.sy4 = (uint32_t)(nx * 4);
+      ga.sz4 = (uint32_t)std::min<uint64_t>(nxy * 4, 0xFFFFFFFFull);
       return SYN_OK;
     }
     case SYN_FIELD_SPHERE: {
@@ -286,6 +297,30 @@ size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t
   return ws_bytes_for(ga.npix, with_adjoint != 0);
 }
 
+// Whether the forward may read this grid with 32-bit buffer offsets: the float4
+// grid (and so the N0 grid) is under 4 GiB, (nz * ny) fits the 24-bit multiplies
+// of the node index, and the cell coordinate of any point a sightline of this
+// geometry reaches stays below 2^30 in magnitude (so its integer part fits).
+bool grid_buffer_ok(const sm::GeomArgs& ga, const sm::GridArgs& gr) {
+  if (g_grid_addressing.load() != 0) return false;
+  const uint64_t nodes = (uint64_t)gr.n[0] * (uint64_t)gr.n[1] * (uint64_t)gr.n[2];
+  if (nodes * 16 > 0xFFFFFF00ull) return false;
+  if ((uint64_t)gr.n[1] * (uint64_t)gr.n[2] >= (1u << 24)) return false;
+  // longest sightline: r_max, or the distance to the farthest box corner
+  double corner = 0.0;
+  bool faces = true;
+  for (int k = 0; k < 3; ++k) {
+    const double d = fmax(ga.r_obs[k] - ga.box_lo[k], ga.box_hi[k] - ga.r_obs[k]);
+    faces = faces && isfinite(d);
+    corner += d * d;
+  }
+  const double L = faces ? fmin(ga.r_max, sqrt(corner)) : ga.r_max;
+  if (!isfinite(L)) return false;
+  for (int k = 0; k < 3; ++k)
+    if ((fabs(ga.r_obs[k] - gr.lo[k]) + L) * gr.inv_h[k] + 2.0 >= 1073741824.0) return false;
+  return true;
+}
+
 syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps, void* ws,
                        size_t ws_bytes, hipStream_t stream) {
   sm::GeomArgs ga;
@@ -308,6 +343,7 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
     e = sm::launch_forward_mlp(ga, fa, emit_args(field->theta[12]), fp.mlp, maps, phi_end, stream);
   } else {
     const int S = lanes_for(SYN_KERNEL_FORWARD, field->kind, ga.npix);
+    if (field->kind == SYN_FIELD_GRID) fp.grid_buffer = grid_buffer_ok(ga, fp.grid);
     e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, stream);
   }
   if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -419,6 +455,12 @@ syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lan
   if (!(lanes == 0 || lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64))
     return fail(SYN_EINVAL, "lanes per sightline must be 0, 1, 4, 16 or 64");
   g_lanes[kernel][field_kind].store(lanes);
+  return SYN_OK;
+}
+
+syn_status syn_set_grid_addressing(int32_t mode) {
+  if (mode != 0 && mode != 1) return fail(SYN_EINVAL, "grid addressing mode must be 0 or 1");
+  g_grid_addressing.store(mode);
   return SYN_OK;
 }
 

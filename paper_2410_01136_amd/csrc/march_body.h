@@ -30,6 +30,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
                                 int64_t q, int sub, bool valid, float* __restrict__ maps,
                                 MapAddr ma, double* __restrict__ phi_end) {
   const Ray ray = make_ray(g, q);
+  const auto rctx = fld.ray_ctx(g, ray);
   double carry = 0.0;  // Faraday sum (n_e B_par, uG cm^-3) of all earlier chunks
   double accI = 0.0;
   double accQ[MF], accU[MF];
@@ -40,7 +41,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     const int n = c0 + sub;
     const bool act = n < g.n_steps;
     const double s = ((double)n + 0.5) * ray.dkpc;  // midpoint of segment n
-    const FV v = fld.eval_at(g, ray, s);
+    const FV v = fld.eval_step(g, ray, rctx, s, n);
     const float bl = v.bx * ray.elx + v.by * ray.ely;
     const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
     const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);

@@ -55,7 +55,10 @@ hipError_t launch_forward(const GeomArgs& g, const FreqArgs& fa, const EmitArgs&
                           hipStream_t st) {
   switch (fp.kind) {
     case kModel16: return fwd_s(g, fa, ea, Model16{fp.m16}, S, maps, phi_end, st);
-    case kGrid: return fwd_s(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, maps, phi_end, st);
+    case kGrid:
+      if (fp.grid_buffer)
+        return fwd_s(g, fa, ea, GridB{fp.grid, Model16{fp.m16}}, S, maps, phi_end, st);
+      return fwd_s(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, maps, phi_end, st);
     case kSphere: return fwd_s(g, fa, ea, Sphere{fp.sph}, S, maps, phi_end, st);
     default: return hipErrorInvalidValue;
   }

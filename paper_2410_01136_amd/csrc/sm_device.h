@@ -189,6 +189,14 @@ struct Model16 {
   }
 
   // fields at distance s [kpc] along the ray (position rounded to FP32 once)
+  // forward-march hook: per-sightline constants of the field (none here) and
+  // the fields at step n, midpoint distance s
+  struct RayCtx {};
+  __device__ inline RayCtx ray_ctx(const GeomArgs&, const Ray&) const { return {}; }
+  __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx&, double s,
+                                 int) const {
+    return eval_at(g, r, s);
+  }
   __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
     return eval((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
                 (float)(g.r_obs[2] + s * r.nz));
@@ -314,6 +322,14 @@ struct Grid {
     return c;
   }
 
+  // forward-march hook: per-sightline constants of the field (none here) and
+  // the fields at step n, midpoint distance s
+  struct RayCtx {};
+  __device__ inline RayCtx ray_ctx(const GeomArgs&, const Ray&) const { return {}; }
+  __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx&, double s,
+                                 int) const {
+    return eval_at(g, r, s);
+  }
   __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
     const Cell c = cell_at(g, r, s);
     const int64_t sy = p.n[0], sz = (int64_t)p.n[0] * p.n[1];
@@ -463,9 +479,118 @@ struct Grid {
   }
 };
 
+// The gridded field read through buffer resources with 32-bit byte offsets
+// (grids below 4 GiB): one offset per step and the corner rows as scalar
+// offsets, instead of eight 64-bit addresses.  Cell indices are clamped to the
+// grid, so every access stays inside it whatever the hardware range check
+// covers; values at midpoints outside the grid box are dropped.  The host uses
+// this form only where the cell coordinate of every midpoint of the geometry
+// fits an int and (nz * ny) < 2^24 (24-bit multiplies).
+struct GridB : Grid {
+  // Steps [n_lo, n_hi) of the sightline have their midpoint inside the grid box:
+  // the box's slab interval along the ray in distance, converted to step indices
+  // once per sightline instead of six comparisons per step.
+  struct RayCtx {
+    int n_lo, n_hi;
+  };
+  __device__ inline RayCtx ray_ctx(const GeomArgs& g, const Ray& r) const {
+    const double n3[3] = {r.nx, r.ny, r.nz};
+    double slo = -INFINITY, shi = INFINITY;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double b = n3[k] * p.inv_h[k];
+      const double u0 = (g.r_obs[k] - p.lo[k]) * p.inv_h[k];
+      if (b != 0.0) {
+        const double s0 = -u0 / b, s1 = (p.umax[k] - u0) / b;
+        slo = fmax(slo, fmin(s0, s1));
+        shi = fmin(shi, fmax(s0, s1));
+      } else if (!(u0 >= 0.0 && u0 <= p.umax[k])) {
+        slo = INFINITY;
+        shi = -INFINITY;
+      }
+    }
+    // step n is inside iff slo <= (n + 1/2) dkpc <= shi
+    const double ns = (double)g.n_steps;
+    RayCtx x;
+    x.n_lo = (int)fmin(fmax(ceil(slo / r.dkpc - 0.5), 0.0), ns);
+    x.n_hi = (int)fmin(fmax(floor(shi / r.dkpc - 0.5) + 1.0, 0.0), ns);
+    if (x.n_hi < x.n_lo) x.n_hi = x.n_lo;
+    return x;
+  }
+
+  __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx& x, double s,
+                                 int n) const {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const bool in = (uint32_t)(n - x.n_lo) < (uint32_t)(x.n_hi - x.n_lo);
+    const double n3[3] = {r.nx, r.ny, r.nz};
+    int i3[3];
+    float t3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double u = s * (n3[k] * p.inv_h[k]) + (g.r_obs[k] - p.lo[k]) * p.inv_h[k];
+      // cell index in [0, n - 2] for any u (the last cell takes its upper face),
+      // so every corner read is inside the grid
+      const int ik = min(max((int)floor(u), 0), p.n[k] - 2);
+      i3[k] = ik;
+      t3[k] = (float)(u - (double)ik);
+    }
+    const uint32_t node = __umul24(__umul24((uint32_t)i3[2], (uint32_t)p.n[1]) + (uint32_t)i3[1],
+                                   (uint32_t)p.n[0]) + (uint32_t)i3[0];
+    const uint32_t ob = node * 16u;
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void*)p.bn, (short)0, (int)p.bn_bytes, 0x00020000);
+    auto ld4 = [&](uint32_t off, uint32_t so) {
+      return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rb, off, so, 0));
+    };
+    const uint32_t syz = p.sy16 + p.sz16;
+    const f4v v000 = ld4(ob, 0), v100 = ld4(ob + 16u, 0);
+    const f4v v010 = ld4(ob, p.sy16), v110 = ld4(ob + 16u, p.sy16);
+    const f4v v001 = ld4(ob, p.sz16), v101 = ld4(ob + 16u, p.sz16);
+    const f4v v011 = ld4(ob, syz), v111 = ld4(ob + 16u, syz);
+    const float tx = t3[0], ty = t3[1], tz = t3[2];
+    const float wx0 = 1.0f - tx, wy0 = 1.0f - ty, wz0 = 1.0f - tz;
+    const float y0z0 = wy0 * wz0, y1z0 = ty * wz0;
+    const float y0z1 = wy0 * tz, y1z1 = ty * tz;
+    const float w000 = wx0 * y0z0, w100 = tx * y0z0, w010 = wx0 * y1z0, w110 = tx * y1z0;
+    const float w001 = wx0 * y0z1, w101 = tx * y0z1, w011 = wx0 * y1z1, w111 = tx * y1z1;
+    auto tri = [&](float a000, float a100, float a010, float a110, float a001, float a101,
+                   float a011, float a111) {
+      return w000 * a000 + w100 * a100 + w010 * a010 + w110 * a110 + w001 * a001 + w101 * a101 +
+             w011 * a011 + w111 * a111;
+    };
+    FV v;
+    v.bx = in ? tri(v000.x, v100.x, v010.x, v110.x, v001.x, v101.x, v011.x, v111.x) : 0.0f;
+    v.by = in ? tri(v000.y, v100.y, v010.y, v110.y, v001.y, v101.y, v011.y, v111.y) : 0.0f;
+    v.bz = in ? tri(v000.z, v100.z, v010.z, v110.z, v001.z, v101.z, v011.z, v111.z) : 0.0f;
+    v.ne = in ? tri(v000.w, v100.w, v010.w, v110.w, v001.w, v101.w, v011.w, v111.w) : 0.0f;
+    if (p.c != nullptr) {
+      const __amdgpu_buffer_rsrc_t rc =
+          __builtin_amdgcn_make_buffer_rsrc((void*)p.c, (short)0, (int)p.c_bytes, 0x00020000);
+      auto ld2 = [&](uint32_t so) {
+        return __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(rc, node * 4u, so, 0));
+      };
+      const f2v c00 = ld2(0), c10 = ld2(p.sy4), c01 = ld2(p.sz4), c11 = ld2(p.sy4 + p.sz4);
+      v.n0 = in ? tri(c00.x, c00.y, c10.x, c10.y, c01.x, c01.y, c11.x, c11.y) : 0.0f;
+    } else {
+      v.n0 = cr.n0_at((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
+                      (float)(g.r_obs[2] + s * r.nz));
+    }
+    return v;
+  }
+};
+
 // Homogeneous sphere (Sec. 2.4 test).
 struct Sphere {
   SphereArgs p;
+  // forward-march hook: per-sightline constants of the field (none here) and
+  // the fields at step n, midpoint distance s
+  struct RayCtx {};
+  __device__ inline RayCtx ray_ctx(const GeomArgs&, const Ray&) const { return {}; }
+  __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx&, double s,
+                                 int) const {
+    return eval_at(g, r, s);
+  }
   __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
     return eval((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
                 (float)(g.r_obs[2] + s * r.nz));

@@ -18,6 +18,7 @@ struct FieldPack {
   int kind;
   M16Args m16;
   GridArgs grid;
+  bool grid_buffer = false;  // forward reads the grid with 32-bit buffer offsets
   SphereArgs sph;
   MlpArgs mlp;
 };

@@ -33,6 +33,10 @@ struct GridArgs {
   int32_t n[3];
   double lo[3], inv_h[3], umax[3];  // umax = n - 1
   int32_t box0[3];   // first node of the adjoint's LDS accumulation box
+  // 32-bit buffer addressing (grids under 4 GiB): sizes in bytes and the byte
+  // strides of one y row and one z plane in the float4 grid and in the N0 grid
+  uint32_t bn_bytes, c_bytes;
+  uint32_t sy16, sz16, sy4, sz4;
 };
 
 // Nodes per axis of the box around the observer in which the grid adjoint

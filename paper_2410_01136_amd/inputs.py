@@ -7,7 +7,7 @@ for reference inputs, the HIP library for benchmark inputs -- and handed in.
 
 Workloads (the paper's own workloads are the toy sphere of Sec. 2.4 and the
 WMAP-model maps of Sec. 3.1; these synthetic configurations follow the same
-shapes and value ranges, see the design doc for the recipe):
+shapes and value ranges):
 
 * ``C0`` plain forward, analytic spiral-disk model, N_side 16, 256 steps,
   1 GHz, sightlines capped at 20 kpc.

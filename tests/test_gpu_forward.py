@@ -184,3 +184,20 @@ def test_grid_smaller_than_geometry_box(sm, orc, lanes):
         gpu = run_gpu(sm, g, sm.grid(I.THETA0, torch.from_numpy(bn).cuda(),
                                      torch.from_numpy(reg_c).cuda(), lo, hi))
         assert_parity(gpu, ref, f"grid sub-box S={S}")
+
+
+def test_grid_addressing_modes_agree(sm, orc, lanes):
+    # 32-bit buffer offsets and 64-bit addresses read the same nodes
+    import torch
+    g = I.geometry("C1", nside=16, n_steps=96)
+    bn, c = small_turbulent_grid(orc, n=(37, 29, 13), seed0=1301)
+    f = sm.grid(I.THETA0, torch.from_numpy(bn).cuda(), torch.from_numpy(c).cuda(), I.BOX_LO,
+                I.BOX_HI)
+    out = []
+    try:
+        for mode in (0, 1):
+            sm.set_grid_addressing(mode)
+            out.append(run_gpu(sm, g, f))
+    finally:
+        sm.set_grid_addressing(0)
+    assert np.array_equal(out[0], out[1])
