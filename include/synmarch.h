@@ -209,13 +209,16 @@ enum { SYN_KERNEL_FORWARD = 0, SYN_KERNEL_ADJOINT = 1, SYN_KERNEL_BATCH = 2 };
 syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lanes);
 int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix);
 
-/* Grid addressing of the forward march over a GRID field.
+/* Grid reads of the forward march over a GRID field.
    0 (default) = automatic: grids under 4 GiB whose cell indices along every
      sightline of the geometry fit in 30 bits are read through buffer resources
-     with 32-bit byte offsets (fewer address instructions and registers), larger
-     ones through 64-bit addresses;
-   1 = always 64-bit addresses.
-   Both give identical maps.  Process-wide; SYN_EINVAL for any other mode. */
+     with 32-bit byte offsets, each distinct cell of a wavefront loaded once into
+     LDS and shared by the lanes in it; larger grids through 64-bit addresses;
+   1 = always 64-bit addresses, each lane reading its own cell;
+   2 = 32-bit buffer offsets, each lane reading its own cell (where allowed).
+   All read the same node values and agree to FP32 rounding (the compiler may
+   fuse the interpolation sums differently per variant).  Process-wide;
+   SYN_EINVAL for any other mode. */
 syn_status syn_set_grid_addressing(int32_t mode);
 
 const char* syn_last_error(void);

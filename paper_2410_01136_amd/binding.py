@@ -277,7 +277,8 @@ def eval_fields(field: Field, xyz: torch.Tensor, stream=None) -> torch.Tensor:
 
 
 def set_grid_addressing(mode: int) -> None:
-    """0: automatic (32-bit buffer offsets where the grid allows), 1: 64-bit addresses."""
+    """0: automatic (buffer reads shared through LDS where the grid allows),
+    1: 64-bit addresses per lane, 2: buffer reads per lane."""
     check(syn_set_grid_addressing(mode), "syn_set_grid_addressing")
 
 

@@ -61,7 +61,7 @@ double digamma_host(double x) {
 
 // ---- launch shapes ----------------------------------------------------------
 std::atomic<int> g_lanes[3][4];  // [kernel family][field kind], 0 = default
-std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 always 64-bit
+std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 64-bit, 2 buffer unshared
 
 // Built-in lanes per sightline, from autotuner runs on MI355X: small maps need
 // many lanes per sightline to fill 256 CUs; large maps prefer fewer (less scan
@@ -302,7 +302,6 @@ size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t
 // of the node index, and the cell coordinate of any point a sightline of this
 // geometry reaches stays below 2^30 in magnitude (so its integer part fits).
 bool grid_buffer_ok(const sm::GeomArgs& ga, const sm::GridArgs& gr) {
-  if (g_grid_addressing.load() != 0) return false;
   const uint64_t nodes = (uint64_t)gr.n[0] * (uint64_t)gr.n[1] * (uint64_t)gr.n[2];
   if (nodes * 16 > 0xFFFFFF00ull) return false;
   if ((uint64_t)gr.n[1] * (uint64_t)gr.n[2] >= (1u << 24)) return false;
@@ -343,7 +342,12 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
     e = sm::launch_forward_mlp(ga, fa, emit_args(field->theta[12]), fp.mlp, maps, phi_end, stream);
   } else {
     const int S = lanes_for(SYN_KERNEL_FORWARD, field->kind, ga.npix);
-    if (field->kind == SYN_FIELD_GRID) fp.grid_buffer = grid_buffer_ok(ga, fp.grid);
+    if (field->kind == SYN_FIELD_GRID) {
+      const int mode = g_grid_addressing.load();
+      fp.grid_path = (mode == 1 || !grid_buffer_ok(ga, fp.grid)) ? sm::kGridGlobal
+                     : mode == 2                                 ? sm::kGridBuffer
+                                                                 : sm::kGridShared;
+    }
     e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, stream);
   }
   if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -459,7 +463,7 @@ syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lan
 }
 
 syn_status syn_set_grid_addressing(int32_t mode) {
-  if (mode != 0 && mode != 1) return fail(SYN_EINVAL, "grid addressing mode must be 0 or 1");
+  if (mode < 0 || mode > 2) return fail(SYN_EINVAL, "grid addressing mode must be 0, 1 or 2");
   g_grid_addressing.store(mode);
   return SYN_OK;
 }

@@ -41,7 +41,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     const int n = c0 + sub;
     const bool act = n < g.n_steps;
     const double s = ((double)n + 0.5) * ray.dkpc;  // midpoint of segment n
-    const FV v = fld.eval_step(g, ray, rctx, s, n);
+    const FV v = fld.template eval_step<S>(g, ray, rctx, s, n);
     const float bl = v.bx * ray.elx + v.by * ray.ely;
     const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
     const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);

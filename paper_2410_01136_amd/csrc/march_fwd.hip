@@ -56,7 +56,9 @@ hipError_t launch_forward(const GeomArgs& g, const FreqArgs& fa, const EmitArgs&
   switch (fp.kind) {
     case kModel16: return fwd_s(g, fa, ea, Model16{fp.m16}, S, maps, phi_end, st);
     case kGrid:
-      if (fp.grid_buffer)
+      if (fp.grid_path == kGridShared)
+        return fwd_s(g, fa, ea, GridL{fp.grid, Model16{fp.m16}}, S, maps, phi_end, st);
+      if (fp.grid_path == kGridBuffer)
         return fwd_s(g, fa, ea, GridB{fp.grid, Model16{fp.m16}}, S, maps, phi_end, st);
       return fwd_s(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, maps, phi_end, st);
     case kSphere: return fwd_s(g, fa, ea, Sphere{fp.sph}, S, maps, phi_end, st);

@@ -193,6 +193,7 @@ struct Model16 {
   // the fields at step n, midpoint distance s
   struct RayCtx {};
   __device__ inline RayCtx ray_ctx(const GeomArgs&, const Ray&) const { return {}; }
+  template <int S>
   __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx&, double s,
                                  int) const {
     return eval_at(g, r, s);
@@ -326,6 +327,7 @@ struct Grid {
   // the fields at step n, midpoint distance s
   struct RayCtx {};
   __device__ inline RayCtx ray_ctx(const GeomArgs&, const Ray&) const { return {}; }
+  template <int S>
   __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx&, double s,
                                  int) const {
     return eval_at(g, r, s);
@@ -518,65 +520,218 @@ struct GridB : Grid {
     return x;
   }
 
-  __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx& x, double s,
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  typedef float f2v __attribute__((ext_vector_type(2)));
+
+  // Cell of a midpoint: node index of its (0, 0, 0) corner, clamped into
+  // [0, n - 2] on every axis for any u (the last cell takes its upper face), so
+  // every corner read is inside the grid; in = the midpoint is in the grid box.
+  struct CellB {
+    uint32_t node;
+    float tx, ty, tz;
+    bool in;
+  };
+  __device__ inline CellB cell_b(const GeomArgs& g, const Ray& r, const RayCtx& x, double s,
                                  int n) const {
-    typedef float f4v __attribute__((ext_vector_type(4)));
-    typedef float f2v __attribute__((ext_vector_type(2)));
-    const bool in = (uint32_t)(n - x.n_lo) < (uint32_t)(x.n_hi - x.n_lo);
     const double n3[3] = {r.nx, r.ny, r.nz};
     int i3[3];
     float t3[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double u = s * (n3[k] * p.inv_h[k]) + (g.r_obs[k] - p.lo[k]) * p.inv_h[k];
-      // cell index in [0, n - 2] for any u (the last cell takes its upper face),
-      // so every corner read is inside the grid
       const int ik = min(max((int)floor(u), 0), p.n[k] - 2);
       i3[k] = ik;
       t3[k] = (float)(u - (double)ik);
     }
-    const uint32_t node = __umul24(__umul24((uint32_t)i3[2], (uint32_t)p.n[1]) + (uint32_t)i3[1],
-                                   (uint32_t)p.n[0]) + (uint32_t)i3[0];
-    const uint32_t ob = node * 16u;
-    const __amdgpu_buffer_rsrc_t rb =
-        __builtin_amdgcn_make_buffer_rsrc((void*)p.bn, (short)0, (int)p.bn_bytes, 0x00020000);
-    auto ld4 = [&](uint32_t off, uint32_t so) {
-      return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rb, off, so, 0));
-    };
-    const uint32_t syz = p.sy16 + p.sz16;
-    const f4v v000 = ld4(ob, 0), v100 = ld4(ob + 16u, 0);
-    const f4v v010 = ld4(ob, p.sy16), v110 = ld4(ob + 16u, p.sy16);
-    const f4v v001 = ld4(ob, p.sz16), v101 = ld4(ob + 16u, p.sz16);
-    const f4v v011 = ld4(ob, syz), v111 = ld4(ob + 16u, syz);
-    const float tx = t3[0], ty = t3[1], tz = t3[2];
+    CellB c;
+    c.node = __umul24(__umul24((uint32_t)i3[2], (uint32_t)p.n[1]) + (uint32_t)i3[1],
+                      (uint32_t)p.n[0]) + (uint32_t)i3[0];
+    c.tx = t3[0];
+    c.ty = t3[1];
+    c.tz = t3[2];
+    c.in = (uint32_t)(n - x.n_lo) < (uint32_t)(x.n_hi - x.n_lo);
+    return c;
+  }
+
+  // The 8 corner records (B_x, B_y, B_z, n_e) of a cell, corner x + 2y + 4z, and
+  // the 4 N0 rows (x0, x1), row y + 2z.
+  struct Corners {
+    f4v b[8];
+    f2v c[4];
+  };
+  __device__ inline __amdgpu_buffer_rsrc_t rsrc_bn() const {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p.bn, (short)0, (int)p.bn_bytes, 0x00020000);
+  }
+  __device__ inline __amdgpu_buffer_rsrc_t rsrc_c() const {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p.c, (short)0, (int)p.c_bytes, 0x00020000);
+  }
+  __device__ inline f4v ld4(uint32_t off, uint32_t so) const {
+    return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rsrc_bn(), off, so, 0));
+  }
+  __device__ inline f2v ld2(uint32_t off, uint32_t so) const {
+    return __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(rsrc_c(), off, so, 0));
+  }
+
+  // Each lane reads its own cell's corners (corner rows as scalar offsets).
+  __device__ inline void load_direct(uint32_t node, Corners& k) const {
+    const uint32_t ob = node * 16u, syz = p.sy16 + p.sz16;
+    k.b[0] = ld4(ob, 0);
+    k.b[1] = ld4(ob + 16u, 0);
+    k.b[2] = ld4(ob, p.sy16);
+    k.b[3] = ld4(ob + 16u, p.sy16);
+    k.b[4] = ld4(ob, p.sz16);
+    k.b[5] = ld4(ob + 16u, p.sz16);
+    k.b[6] = ld4(ob, syz);
+    k.b[7] = ld4(ob + 16u, syz);
+    if (p.c != nullptr) {
+      const uint32_t oc = node * 4u;
+      k.c[0] = ld2(oc, 0);
+      k.c[1] = ld2(oc, p.sy4);
+      k.c[2] = ld2(oc, p.sz4);
+      k.c[3] = ld2(oc, p.sy4 + p.sz4);
+    }
+  }
+
+  // Trilinear interpolation of the loaded corners (zero outside the grid box).
+  __device__ inline FV interp(const GeomArgs& g, const Ray& r, double s, const CellB& c,
+                              const Corners& k) const {
+    const float tx = c.tx, ty = c.ty, tz = c.tz;
     const float wx0 = 1.0f - tx, wy0 = 1.0f - ty, wz0 = 1.0f - tz;
     const float y0z0 = wy0 * wz0, y1z0 = ty * wz0;
     const float y0z1 = wy0 * tz, y1z1 = ty * tz;
-    const float w000 = wx0 * y0z0, w100 = tx * y0z0, w010 = wx0 * y1z0, w110 = tx * y1z0;
-    const float w001 = wx0 * y0z1, w101 = tx * y0z1, w011 = wx0 * y1z1, w111 = tx * y1z1;
-    auto tri = [&](float a000, float a100, float a010, float a110, float a001, float a101,
-                   float a011, float a111) {
-      return w000 * a000 + w100 * a100 + w010 * a010 + w110 * a110 + w001 * a001 + w101 * a101 +
-             w011 * a011 + w111 * a111;
+    const float w[8] = {wx0 * y0z0, tx * y0z0, wx0 * y1z0, tx * y1z0,
+                        wx0 * y0z1, tx * y0z1, wx0 * y1z1, tx * y1z1};
+    auto tri = [&](int ch) {
+      float a = w[0] * k.b[0][ch];
+#pragma unroll
+      for (int j = 1; j < 8; ++j) a += w[j] * k.b[j][ch];
+      return a;
     };
     FV v;
-    v.bx = in ? tri(v000.x, v100.x, v010.x, v110.x, v001.x, v101.x, v011.x, v111.x) : 0.0f;
-    v.by = in ? tri(v000.y, v100.y, v010.y, v110.y, v001.y, v101.y, v011.y, v111.y) : 0.0f;
-    v.bz = in ? tri(v000.z, v100.z, v010.z, v110.z, v001.z, v101.z, v011.z, v111.z) : 0.0f;
-    v.ne = in ? tri(v000.w, v100.w, v010.w, v110.w, v001.w, v101.w, v011.w, v111.w) : 0.0f;
+    v.bx = c.in ? tri(0) : 0.0f;
+    v.by = c.in ? tri(1) : 0.0f;
+    v.bz = c.in ? tri(2) : 0.0f;
+    v.ne = c.in ? tri(3) : 0.0f;
     if (p.c != nullptr) {
-      const __amdgpu_buffer_rsrc_t rc =
-          __builtin_amdgcn_make_buffer_rsrc((void*)p.c, (short)0, (int)p.c_bytes, 0x00020000);
-      auto ld2 = [&](uint32_t so) {
-        return __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(rc, node * 4u, so, 0));
-      };
-      const f2v c00 = ld2(0), c10 = ld2(p.sy4), c01 = ld2(p.sz4), c11 = ld2(p.sy4 + p.sz4);
-      v.n0 = in ? tri(c00.x, c00.y, c10.x, c10.y, c01.x, c01.y, c11.x, c11.y) : 0.0f;
+      float a = w[0] * k.c[0].x + w[1] * k.c[0].y + w[2] * k.c[1].x + w[3] * k.c[1].y +
+                w[4] * k.c[2].x + w[5] * k.c[2].y + w[6] * k.c[3].x + w[7] * k.c[3].y;
+      v.n0 = c.in ? a : 0.0f;
     } else {
       v.n0 = cr.n0_at((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
                       (float)(g.r_obs[2] + s * r.nz));
     }
     return v;
+  }
+
+  template <int S>
+  __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx& x, double s,
+                                 int n) const {
+    const CellB c = cell_b(g, r, x, s, n);
+    Corners k;
+    load_direct(c.node, k);
+    return interp(g, r, s, c, k);
+  }
+};
+
+// GridB with the corner reads shared across a wavefront: consecutive lanes of
+// one sightline mostly lie in the same cell, yet each lane's own corner loads
+// cost the texture-address unit one access per group of four lanes and per
+// cache line touched, which bounds the direct form.  Here the wavefront finds
+// its distinct cells (runs of equal cells along each sightline), loads every
+// distinct cell once -- eight lanes per cell for the (B, n_e) corners, four for
+// the N0 rows, so each group of four lanes reads one cell -- into LDS, and each
+// lane then reads its cell's corners from LDS.  Wavefronts with more distinct
+// cells than the LDS slots fall back to the direct reads.  Every lane of the
+// wavefront must call eval_step together.
+struct GridL : GridB {
+  static constexpr int kSlots = 32;      // distinct cells per wavefront and step chunk
+  static constexpr int kRecFloats = 44;  // 8 x 4 corners + 4 x 2 N0 + 4 padding (bank spread)
+  static constexpr int kRoundsB = kSlots / 8, kRoundsC = kSlots / 16;
+
+  template <int S>
+  __device__ inline bool load_shared(uint32_t node, Corners& k) const {
+    __shared__ uint32_t s_node[4][kSlots];
+    __shared__ float s_rec[4][kSlots][kRecFloats];
+    const int lane = (int)__lane_id();
+    const int w = (int)(threadIdx.x >> 6);
+    // a run starts where the cell differs from the previous lane's, or at the
+    // first lane of a sightline
+    uint32_t prev;
+    if constexpr (S == 64)
+      prev = (uint32_t)__shfl_up((int)node, 1, 64);
+    else
+      prev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)node, 0x111 /* row_shr:1 */, 0xf, 0xf,
+                                                   true);
+    const bool start = ((lane & (S - 1)) == 0) || (prev != node);
+    const uint64_t m = __ballot(start);
+    const int nsl = __popcll(m);
+    if (nsl > kSlots) return false;
+    const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const int slot = start ? below : below - 1;
+    if (start) s_node[w][slot] = node;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // all loads of the chunk are issued before the first LDS store, so their
+    // latencies overlap: (B, n_e) corner (lane & 7) of slots (lane >> 3) + 8 r,
+    // N0 row (lane & 3) of slots (lane >> 2) + 16 r
+    const uint32_t cn = (uint32_t)lane & 7u, row = (uint32_t)lane & 3u;
+    const uint32_t offb = (cn & 1u) * 16u + ((cn >> 1) & 1u) * p.sy16 + (cn >> 2) * p.sz16;
+    const uint32_t offc = (row & 1u) * p.sy4 + (row >> 1) * p.sz4;
+    const bool with_c = p.c != nullptr;
+    // (slot indices stay below kSlots, so the node reads are unconditional;
+    // only the loads of slots in use are issued)
+    uint32_t nb[kRoundsB], nc[kRoundsC];
+#pragma unroll
+    for (int r = 0; r < kRoundsB; ++r) nb[r] = s_node[w][(lane >> 3) + 8 * r];
+#pragma unroll
+    for (int r = 0; r < kRoundsC; ++r) nc[r] = s_node[w][(lane >> 2) + 16 * r];
+    f4v vb[kRoundsB];
+    f2v vc[kRoundsC];
+#pragma unroll
+    for (int r = 0; r < kRoundsB; ++r)
+      if ((lane >> 3) + 8 * r < nsl) vb[r] = ld4(nb[r] * 16u + offb, 0);
+    if (with_c) {
+#pragma unroll
+      for (int r = 0; r < kRoundsC; ++r)
+        if ((lane >> 2) + 16 * r < nsl) vc[r] = ld2(nc[r] * 4u + offc, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < kRoundsB; ++r) {
+      const int sl = (lane >> 3) + 8 * r;
+      if (sl < nsl) *reinterpret_cast<f4v*>(&s_rec[w][sl][4 * cn]) = vb[r];
+    }
+    if (with_c) {
+#pragma unroll
+      for (int r = 0; r < kRoundsC; ++r) {
+        const int sl = (lane >> 2) + 16 * r;
+        if (sl < nsl) *reinterpret_cast<f2v*>(&s_rec[w][sl][32 + 2 * row]) = vc[r];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < 8; ++j) k.b[j] = *reinterpret_cast<const f4v*>(&s_rec[w][slot][4 * j]);
+    if (with_c) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) k.c[j] = *reinterpret_cast<const f2v*>(&s_rec[w][slot][32 + 2 * j]);
+    }
+    return true;
+  }
+
+  template <int S>
+  __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx& x, double s,
+                                 int n) const {
+    const CellB c = cell_b(g, r, x, s, n);
+    Corners k;
+    if constexpr (S == 1) {
+      load_direct(c.node, k);
+    } else {
+      if (!load_shared<S>(c.node, k)) load_direct(c.node, k);
+    }
+    return interp(g, r, s, c, k);
   }
 };
 
@@ -587,6 +742,7 @@ struct Sphere {
   // the fields at step n, midpoint distance s
   struct RayCtx {};
   __device__ inline RayCtx ray_ctx(const GeomArgs&, const Ray&) const { return {}; }
+  template <int S>
   __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx&, double s,
                                  int) const {
     return eval_at(g, r, s);

@@ -9,6 +9,10 @@ namespace sm {
 
 enum FieldKind { kModel16 = 0, kGrid = 1, kSphere = 2, kMlp = 3 };
 
+// How the gridded forward reads the grid: 64-bit addresses, 32-bit buffer
+// offsets per lane, or buffer reads of each distinct cell shared through LDS.
+enum GridPath { kGridGlobal = 0, kGridBuffer = 1, kGridShared = 2 };
+
 struct MlpArgs {
   const void* packed;     // device, layout of mlp_layout.h
   float lo[3], scale[3];  // x^ = (r - lo) * scale - 1, scale = 2 / (hi - lo)
@@ -18,7 +22,7 @@ struct FieldPack {
   int kind;
   M16Args m16;
   GridArgs grid;
-  bool grid_buffer = false;  // forward reads the grid with 32-bit buffer offsets
+  int grid_path = 0;  // forward's grid reads: GridPath
   SphereArgs sph;
   MlpArgs mlp;
 };

@@ -143,7 +143,7 @@ def test_chi2_checks_on_host(sm):
 def test_lane_setting(sm):
     assert sm.syn_set_lanes_per_ray(0, 0, 3) == sm.SYN_EINVAL
     assert sm.syn_set_lanes_per_ray(5, 0, 4) == sm.SYN_EINVAL
-    assert sm.syn_set_grid_addressing(2) == sm.SYN_EINVAL
+    assert sm.syn_set_grid_addressing(3) == sm.SYN_EINVAL
     assert sm.syn_set_grid_addressing(0) == sm.SYN_OK
     sm.set_lanes_per_ray(0, 1, 16)
     assert sm.get_lanes_per_ray(0, 1, 10 ** 6) == 16
