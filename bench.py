@@ -80,6 +80,17 @@ def load_traffic(kernel: str):
     return None
 
 
+def grid_read_path(sm, npix: int) -> str:
+    """How the gridded forward reads the grid under the current setting (the
+    benchmark grids are all under 4 GiB)."""
+    mode = sm.get_grid_addressing()
+    if mode == 1:
+        return "64-bit addresses, per lane"
+    if mode == 3 or (mode == 0 and npix >= (1 << 18)):
+        return "buffer reads of each distinct cell shared through LDS"
+    return "buffer reads, per lane"
+
+
 def time_launches(fn, steps, warmup):
     """(wall ms per call, event ms per call) over `steps` calls after `warmup`."""
     import torch
@@ -180,7 +191,8 @@ def main() -> int:
         "traffic": traffic,
         "peak_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
         "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
-        "kernel": f"sm::k_forward<GridB, S={lanes}, MF=4> (grid read with 32-bit buffer offsets)",
+        "kernel": f"sm::k_forward<{'GridL' if 'shared' in grid_read_path(sm, g.npix) else 'GridB'}, "
+                  f"S={lanes}, MF=4> ({grid_read_path(sm, g.npix)})",
         "flop_per_unit": FLOP_PER_PIX_STEP_C1 / len(g.freqs_hz),
         "units_per_launch": units,
         "launch_ms": round(ev_ms, 4),
@@ -310,6 +322,14 @@ def bench_adjoint(sm, I, np, torch, tune, args):
         "adjoint_over_forward_time": round(ga_ev / gf_ev, 3),
     }
     log("C2 grid:", res["grid"])
+    res["grid"]["lanes_per_ray"] = {"forward": sm.get_lanes_per_ray(0, 1, g.npix),
+                                    "adjoint": sm.get_lanes_per_ray(1, 1, g.npix)}
+    res["grid"]["forward_read_path"] = grid_read_path(sm, g.npix)
+    # later workloads start from the library's own launch choices
+    for k in range(3):
+        for kind in range(4):
+            sm.set_lanes_per_ray(k, kind, 0)
+    sm.set_grid_addressing(0)
     return res
 
 

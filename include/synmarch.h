@@ -210,16 +210,21 @@ syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lan
 int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix);
 
 /* Grid reads of the forward march over a GRID field.
-   0 (default) = automatic: grids under 4 GiB whose cell indices along every
-     sightline of the geometry fit in 30 bits are read through buffer resources
-     with 32-bit byte offsets, each distinct cell of a wavefront loaded once into
-     LDS and shared by the lanes in it; larger grids through 64-bit addresses;
+   Grids under 4 GiB whose cell indices along every sightline of the geometry
+   fit in 30 bits can be read through buffer resources with 32-bit byte offsets,
+   either each lane reading its own cell or each distinct cell of a wavefront
+   loaded once into LDS and shared by the lanes in it; other grids are read
+   through 64-bit addresses.
+   0 (default) = automatic: shared reads from 2^18 sightlines on, per-lane
+     buffer reads below;
    1 = always 64-bit addresses, each lane reading its own cell;
-   2 = 32-bit buffer offsets, each lane reading its own cell (where allowed).
+   2 = buffer reads, each lane its own cell (where allowed);
+   3 = buffer reads shared through LDS (where allowed).
    All read the same node values and agree to FP32 rounding (the compiler may
    fuse the interpolation sums differently per variant).  Process-wide;
    SYN_EINVAL for any other mode. */
 syn_status syn_set_grid_addressing(int32_t mode);
+int32_t syn_get_grid_addressing(void);
 
 const char* syn_last_error(void);
 int32_t syn_version(void);

@@ -81,6 +81,7 @@ syn_batch_destroy = _sig("syn_batch_destroy", None, [_vp])
 syn_set_lanes_per_ray = _sig("syn_set_lanes_per_ray", _i32, [_i32, _i32, _i32])
 syn_get_lanes_per_ray = _sig("syn_get_lanes_per_ray", _i32, [_i32, _i32, _i64])
 syn_set_grid_addressing = _sig("syn_set_grid_addressing", _i32, [_i32])
+syn_get_grid_addressing = _sig("syn_get_grid_addressing", _i32, [])
 syn_host_nest_pixel = _sig("syn_host_nest_pixel", _i32,
                            [_i32, _i64, ctypes.POINTER(_i64), _dp, _dp])
 
@@ -277,9 +278,13 @@ def eval_fields(field: Field, xyz: torch.Tensor, stream=None) -> torch.Tensor:
 
 
 def set_grid_addressing(mode: int) -> None:
-    """0: automatic (buffer reads shared through LDS where the grid allows),
-    1: 64-bit addresses per lane, 2: buffer reads per lane."""
+    """0: automatic, 1: 64-bit addresses per lane, 2: buffer reads per lane,
+    3: buffer reads shared through LDS (2 and 3 where the grid allows)."""
     check(syn_set_grid_addressing(mode), "syn_set_grid_addressing")
+
+
+def get_grid_addressing() -> int:
+    return int(syn_get_grid_addressing())
 
 
 def set_lanes_per_ray(kernel: int, kind: int, lanes: int) -> None:

@@ -61,7 +61,7 @@ double digamma_host(double x) {
 
 // ---- launch shapes ----------------------------------------------------------
 std::atomic<int> g_lanes[3][4];  // [kernel family][field kind], 0 = default
-std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 64-bit, 2 buffer unshared
+std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 64-bit, 2 buffer per lane, 3 shared
 
 // Built-in lanes per sightline, from autotuner runs on MI355X: small maps need
 // many lanes per sightline to fill 256 CUs; large maps prefer fewer (less scan
@@ -74,6 +74,8 @@ int default_lanes(int kernel, int kind, int64_t npix) {
     return npix < (1 << 14) ? 16 : 4;
   }
   if (npix < (1 << 14)) return 64;
+  // gridded fields share cell reads across the 16 steps of a sightline chunk
+  if (kind == SYN_FIELD_GRID) return 16;
   return npix < (1 << 22) ? 16 : 4;
 }
 
@@ -344,9 +346,13 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
     const int S = lanes_for(SYN_KERNEL_FORWARD, field->kind, ga.npix);
     if (field->kind == SYN_FIELD_GRID) {
       const int mode = g_grid_addressing.load();
+      // automatic: shared cell reads pay off once there are enough wavefronts
+      // to hide their longer dependency chain (measured: N_side 256 gains 1.3x,
+      // N_side 64 loses 10%)
+      const bool shared = mode == 3 || (mode == 0 && ga.npix >= (1 << 18));
       fp.grid_path = (mode == 1 || !grid_buffer_ok(ga, fp.grid)) ? sm::kGridGlobal
-                     : mode == 2                                 ? sm::kGridBuffer
-                                                                 : sm::kGridShared;
+                     : shared                                    ? sm::kGridShared
+                                                                 : sm::kGridBuffer;
     }
     e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, stream);
   }
@@ -463,10 +469,12 @@ syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lan
 }
 
 syn_status syn_set_grid_addressing(int32_t mode) {
-  if (mode < 0 || mode > 2) return fail(SYN_EINVAL, "grid addressing mode must be 0, 1 or 2");
+  if (mode < 0 || mode > 3) return fail(SYN_EINVAL, "grid addressing mode must be 0, 1, 2 or 3");
   g_grid_addressing.store(mode);
   return SYN_OK;
 }
+
+int32_t syn_get_grid_addressing(void) { return g_grid_addressing.load(); }
 
 int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix) {
   return lanes_for(kernel, field_kind, npix);

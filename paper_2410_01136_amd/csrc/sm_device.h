@@ -647,6 +647,7 @@ struct GridL : GridB {
   static constexpr int kSlots = 32;      // distinct cells per wavefront and step chunk
   static constexpr int kRecFloats = 44;  // 8 x 4 corners + 4 x 2 N0 + 4 padding (bank spread)
   static constexpr int kRoundsB = kSlots / 8, kRoundsC = kSlots / 16;
+  static_assert(kSlots % 16 == 0, "whole load rounds of both kinds");
 
   template <int S>
   __device__ inline bool load_shared(uint32_t node, Corners& k) const {
@@ -663,12 +664,15 @@ struct GridL : GridB {
       prev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)node, 0x111 /* row_shr:1 */, 0xf, 0xf,
                                                    true);
     const bool start = ((lane & (S - 1)) == 0) || (prev != node);
-    const uint64_t m = __ballot(start);
-    const int nsl = __popcll(m);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(start);
+    const int nsl = __builtin_popcountll(m);
     if (nsl > kSlots) return false;
-    const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    const int slot = start ? below : below - 1;
+    // slot = runs starting at or below this lane, minus one; lane 0 always
+    // starts a run, so that is the count of starts among lanes 1..lane, i.e.
+    // the set bits of m >> 1 below this lane
+    const uint64_t m1 = m >> 1;
+    const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
     if (start) s_node[w][slot] = node;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -681,7 +685,7 @@ struct GridL : GridB {
     const uint32_t offc = (row & 1u) * p.sy4 + (row >> 1) * p.sz4;
     const bool with_c = p.c != nullptr;
     // (slot indices stay below kSlots, so the node reads are unconditional;
-    // only the loads of slots in use are issued)
+    // only the loads of slots in use are issued; kSlots is a multiple of 16)
     uint32_t nb[kRoundsB], nc[kRoundsC];
 #pragma unroll
     for (int r = 0; r < kRoundsB; ++r) nb[r] = s_node[w][(lane >> 3) + 8 * r];

@@ -23,6 +23,9 @@ import torch
 from . import binding as sm
 
 CANDIDATES = (1, 4, 16, 64)
+# grid read modes tried for gridded forwards (syn_set_grid_addressing):
+# 2 = per-lane buffer reads, 3 = cell reads shared through LDS
+GRID_MODES = (2, 3)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -44,12 +47,20 @@ def _key(kernel: int, kind: int, npix: int, n_steps: int, n_freq: int) -> str:
     return f"{dev}|{source_hash()}|k{kernel}|f{kind}|p{npix}|n{n_steps}|q{n_freq}"
 
 
-def load_cache(path: Optional[str] = None) -> Dict[str, int]:
+def _valid(v) -> bool:
+    # a lane count, or [lane count, grid read mode]
+    if isinstance(v, int):
+        return v in CANDIDATES
+    return (isinstance(v, list) and len(v) == 2 and v[0] in CANDIDATES
+            and v[1] in GRID_MODES)
+
+
+def load_cache(path: Optional[str] = None) -> Dict[str, object]:
     path = path or cache_path()
     try:
         with open(path) as f:
             d = json.load(f)
-        return {k: int(v) for k, v in d.items() if int(v) in CANDIDATES}
+        return {k: v for k, v in d.items() if _valid(v)}
     except (OSError, ValueError, TypeError):
         return {}
 
@@ -81,37 +92,52 @@ def time_candidate(run: Callable[[], None], reps: int = 5) -> float:
 
 def tune(kernel: int, kind: int, shape, run: Callable[[], None],
          candidates: Iterable[int] = CANDIDATES, reps: int = 5, use_cache: bool = True,
-         write_cache: bool = True) -> Dict[str, object]:
-    """Times `run` for every lane count and applies the fastest.
+         write_cache: bool = True, grid_modes: Optional[Iterable[int]] = None) -> Dict[str, object]:
+    """Times `run` for every lane count (and, given grid_modes, every grid read
+    mode) and applies the fastest.
 
     shape: (npix, n_steps, n_freq) of the workload, for the cache key.
-    Returns {"lanes": best, "ms": {S: ms}, "cached": bool}.
+    Returns {"lanes": best S, "grid_mode": best mode or None, "ms": {label: ms},
+    "cached": bool}.
     """
-    key = _key(kernel, kind, *shape)
+    modes = list(grid_modes) if grid_modes is not None else [None]
+    key = _key(kernel, kind, *shape) + ("|g" if grid_modes is not None else "")
     cache = load_cache() if use_cache else {}
-    if key in cache:
-        sm.set_lanes_per_ray(kernel, kind, cache[key])
-        return {"lanes": cache[key], "ms": {}, "cached": True}
-    ms = {}
-    for S in candidates:
+
+    def apply(S, mode):
         sm.set_lanes_per_ray(kernel, kind, S)
-        ms[S] = time_candidate(run, reps)
+        if mode is not None:
+            sm.set_grid_addressing(mode)
+
+    if key in cache:
+        v = cache[key]
+        S, mode = (v, None) if isinstance(v, int) else (v[0], v[1])
+        apply(S, mode)
+        return {"lanes": S, "grid_mode": mode, "ms": {}, "cached": True}
+    ms = {}
+    for mode in modes:
+        for S in candidates:
+            apply(S, mode)
+            ms[(S, mode)] = time_candidate(run, reps)
     best = min(ms, key=ms.get)
-    sm.set_lanes_per_ray(kernel, kind, best)
+    apply(*best)
     if write_cache:
         cache = load_cache()
-        cache[key] = best
+        cache[key] = best[0] if best[1] is None else [best[0], best[1]]
         try:
             save_cache(cache)
         except OSError:
             pass
-    return {"lanes": best, "ms": ms, "cached": False}
+    label = {(S if m is None else f"{S}/mode{m}"): round(t, 4) for (S, m), t in ms.items()}
+    return {"lanes": best[0], "grid_mode": best[1], "ms": label, "cached": False}
 
 
 def tune_forward(geom, field, maps=None, ws=None, **kw):
     npix = 12 * geom.nside ** 2
     if maps is None:
         maps = torch.empty((geom.n_freq, 3, npix), dtype=torch.float32, device="cuda")
+    if field.s.kind == sm.FIELD_GRID and "grid_modes" not in kw:
+        kw["grid_modes"] = GRID_MODES
     return tune(sm.KERNEL_FORWARD, field.s.kind, (npix, geom.n_steps, geom.n_freq),
                 lambda: sm.forward(geom, field, maps=maps, ws=ws), **kw)
 

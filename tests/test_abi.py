@@ -30,7 +30,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(sm):
     names = declared_functions()
-    assert len(names) >= 20
+    assert len(names) >= 21
     for n in names:
         assert hasattr(sm._lib, n), n
 
@@ -143,12 +143,14 @@ def test_chi2_checks_on_host(sm):
 def test_lane_setting(sm):
     assert sm.syn_set_lanes_per_ray(0, 0, 3) == sm.SYN_EINVAL
     assert sm.syn_set_lanes_per_ray(5, 0, 4) == sm.SYN_EINVAL
-    assert sm.syn_set_grid_addressing(3) == sm.SYN_EINVAL
-    assert sm.syn_set_grid_addressing(0) == sm.SYN_OK
+    assert sm.syn_set_grid_addressing(4) == sm.SYN_EINVAL
+    assert sm.syn_set_grid_addressing(3) == sm.SYN_OK and sm.get_grid_addressing() == 3
+    assert sm.syn_set_grid_addressing(0) == sm.SYN_OK and sm.get_grid_addressing() == 0
     sm.set_lanes_per_ray(0, 1, 16)
     assert sm.get_lanes_per_ray(0, 1, 10 ** 6) == 16
     sm.set_lanes_per_ray(0, 1, 0)
-    assert sm.get_lanes_per_ray(0, 1, 10 ** 7) == 4
+    assert sm.get_lanes_per_ray(0, 1, 10 ** 7) == 16
+    assert sm.get_lanes_per_ray(0, 0, 10 ** 7) == 4
     assert sm.get_lanes_per_ray(0, 1, 786432) == 16
     assert sm.get_lanes_per_ray(0, 1, 3072) == 64
     assert sm.get_lanes_per_ray(1, 1, 49152) == 1

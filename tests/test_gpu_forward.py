@@ -201,7 +201,7 @@ def test_grid_read_paths_agree(sm, orc, lanes, S, with_c):
                     torch.from_numpy(c).cuda() if with_c else None, I.BOX_LO, I.BOX_HI)
         out = []
         try:
-            for mode in (0, 1, 2):
+            for mode in (3, 1, 2):
                 sm.set_grid_addressing(mode)
                 out.append(run_gpu(sm, g, f))
         finally:
