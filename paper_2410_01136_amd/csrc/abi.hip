@@ -385,19 +385,6 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   const int S = lanes_for(SYN_KERNEL_ADJOINT, field->kind, ga.npix);
   double* phi_end = static_cast<double*>(ws);
   double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + ws_phi_bytes(ga.npix));
-  if (field->kind == SYN_FIELD_GRID) {
-    // LDS accumulation box of the grid adjoint: kAdjBox nodes per axis around
-    // the observer's cell, kept inside the grid where it is large enough
-    for (int k = 0; k < 3; ++k) {
-      double u = (geom->r_obs_kpc[k] - fp.grid.lo[k]) * fp.grid.inv_h[k];
-      u = fmin(fmax(u, -1.0e6), 1.0e6);  // an observer far off the grid: any box will do
-      int b = (int)floor(u) - sm::kAdjBox / 2 + 1;
-      const int bmax = fp.grid.n[k] - sm::kAdjBox;
-      if (b > bmax) b = bmax;
-      if (b < 0) b = 0;
-      fp.grid.box0[k] = b;
-    }
-  }
   hipError_t e = sm::launch_adjoint(ga, fa, emit_args(field->theta[12]), fp, S, dmaps, phi_end,
                                     partials, dtheta, dgrid_bn, dgrid_c, stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");

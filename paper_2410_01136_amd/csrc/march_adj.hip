@@ -16,12 +16,80 @@
 
 namespace sm {
 
+// Reaches (kpc from the observer) tried for a workgroup's LDS box: 64 / 2^c.
+constexpr int kBoxReaches = 10;
+
+// The LDS accumulation box of one workgroup of the grid adjoint: the bounding
+// box of the first D kpc of all its sightlines (every sightline starts at the
+// observer, and a workgroup's sightlines form a compact sky patch, so this cone
+// section is where its gradients pile up), for the largest D = 64 / 2^c whose
+// box holds at most `cap` nodes.  Collective over the workgroup; zeroes the box.
+template <class F>
+__device__ inline AdjBox workgroup_box(const GeomArgs& g, const F& fld, int64_t q, float* lds,
+                                       int cap) {
+  __shared__ int s_rng[kBoxReaches][6];  // per reach: lowest node, highest node + 1 per axis
+  __shared__ int s_box[7];               // b0[3], d[3], in use
+  for (int j = threadIdx.x; j < kBoxReaches * 6; j += blockDim.x)
+    (&s_rng[0][0])[j] = (j % 6) < 3 ? INT_MAX : INT_MIN;
+  __syncthreads();
+  const Ray r = make_ray(g, q);
+  const double L = r.dkpc * (double)g.n_steps;
+  const double n3[3] = {r.nx, r.ny, r.nz};
+  for (int c = 0; c < kBoxReaches; ++c) {
+    const double D = fmin(64.0 / (double)(1 << c), L);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double u0 = (g.r_obs[k] - fld.p.lo[k]) * fld.p.inv_h[k];
+      const double u1 = u0 + D * n3[k] * fld.p.inv_h[k];
+      // clamped to just outside the grid, so the conversions are defined
+      const double a = fmax(fmin(u0, u1), -1.0), b = fmin(fmax(u0, u1), fld.p.umax[k] + 1.0);
+      atomicMin(&s_rng[c][k], (int)floor(a));
+      atomicMax(&s_rng[c][3 + k], (int)floor(b) + 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_box[6] = 0;
+    for (int c = 0; c < kBoxReaches; ++c) {
+      int lo[3], d[3];
+      int64_t cnt = 1;
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = min(max(s_rng[c][k], 0), fld.p.n[k] - 1);
+        const int hi = min(s_rng[c][3 + k], fld.p.n[k] - 1);
+        d[k] = max(hi - lo[k] + 1, 1);
+        cnt *= d[k];
+      }
+      if (cnt <= cap) {
+        for (int k = 0; k < 3; ++k) {
+          s_box[k] = lo[k];
+          s_box[3 + k] = d[k];
+        }
+        s_box[6] = 1;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  AdjBox B;
+  if (s_box[6]) {
+    for (int k = 0; k < 3; ++k) {
+      B.b0[k] = s_box[k];
+      B.d[k] = s_box[3 + k];
+    }
+    B.lds = lds;
+    const int nf = 5 * B.d[0] * B.d[1] * B.d[2];
+    for (int j = threadIdx.x; j < nf; j += blockDim.x) lds[j] = 0.0f;
+  }
+  __syncthreads();
+  return B;
+}
+
 template <class F, int S, int MF, bool THETA, bool GRID>
 __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitArgs ea, F fld,
                                                  const float* __restrict__ dmaps,
                                                  const double* __restrict__ phi_end,
                                                  double* __restrict__ partials, float* gbn,
-                                                 float* gc) {
+                                                 float* gc, int box_cap) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t tid = blk * 256 + threadIdx.x;
   const int sub = (int)(threadIdx.x & (S - 1));
@@ -31,15 +99,13 @@ __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitAr
   double tb[THETA ? kNParam : 1];
 #pragma unroll
   for (int k = 0; k < (THETA ? kNParam : 1); ++k) tb[k] = 0.0;
-  float* box = nullptr;
+  AdjBox box;
   if constexpr (GRID) {
-    __shared__ float lds_box[kAdjBoxFloats];
-    for (int j = threadIdx.x; j < kAdjBoxFloats; j += 256) lds_box[j] = 0.0f;
-    __syncthreads();
-    box = lds_box;
+    extern __shared__ float lds_box[];  // box_cap nodes x 5 floats
+    box = workgroup_box(g, fld, q, lds_box, box_cap);
   }
   adj_lane<F, S, MF, THETA, GRID>(g, fa, ea, fld, q, sub, valid, dmaps, MapAddr{g.npix, 0}, phi_end,
-                                  tb, gbn, gc, box);
+                                  tb, gbn, gc, &box);
   if constexpr (GRID) {
     __syncthreads();
     fld.flush_box(box, gbn, gc, threadIdx.x, 256);
@@ -72,8 +138,33 @@ static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
                          const float* dm, const double* pe, double* part, double* dth, float* gbn,
                          float* gc, hipStream_t st) {
   const int64_t nb = march_blocks(g.npix, S);
-  k_adjoint<F, S, MF, TH, GR><<<dim3((unsigned)nb), dim3(256), 0, st>>>(g, fa, ea, f, dm, pe, part,
-                                                                         gbn, gc);
+  int cap = 0;
+  size_t lds = 0;
+  if (GR) {
+    // one workgroup per CU or fewer: the box may take all of the CU's LDS;
+    // otherwise a quarter, so that four workgroups fit
+    static int n_cu = 0;
+    if (n_cu == 0) {
+      int dev = 0, v = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        n_cu = v;
+      else
+        n_cu = 256;
+    }
+    cap = nb <= n_cu ? kAdjBoxNodesMax : kAdjBoxNodesMax / 4;
+    lds = (size_t)cap * 5 * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+      hipError_t ea2 = hipFuncSetAttribute(
+          reinterpret_cast<const void*>(&k_adjoint<F, S, MF, TH, GR>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)((size_t)kAdjBoxNodesMax * 5 * sizeof(float)));
+      if (ea2 != hipSuccess) return ea2;
+      attr_set = true;
+    }
+  }
+  k_adjoint<F, S, MF, TH, GR><<<dim3((unsigned)nb), dim3(256), lds, st>>>(g, fa, ea, f, dm, pe, part,
+                                                                           gbn, gc, cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (TH) {
@@ -88,9 +179,13 @@ static hipError_t adj_flags(const GeomArgs& g, const FreqArgs& fa, const EmitArg
                             const float* dm, const double* pe, double* part, double* dth,
                             float* gbn, float* gc, hipStream_t st) {
   const bool th = dth != nullptr, gr = (gbn != nullptr || gc != nullptr);
-  if (th && gr) return adj_go<F, S, MF, true, true>(g, fa, ea, f, dm, pe, part, dth, gbn, gc, st);
+  if constexpr (std::is_same_v<F, Grid>) {
+    if (th && gr) return adj_go<F, S, MF, true, true>(g, fa, ea, f, dm, pe, part, dth, gbn, gc, st);
+    if (gr) return adj_go<F, S, MF, false, true>(g, fa, ea, f, dm, pe, part, dth, gbn, gc, st);
+  } else {
+    if (gr) return hipErrorInvalidValue;  // only gridded fields have grid gradients
+  }
   if (th) return adj_go<F, S, MF, true, false>(g, fa, ea, f, dm, pe, part, dth, gbn, gc, st);
-  if (gr) return adj_go<F, S, MF, false, true>(g, fa, ea, f, dm, pe, part, dth, gbn, gc, st);
   return hipSuccess;
 }
 
@@ -119,12 +214,12 @@ static hipError_t adj_s(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& e
 // Model16 fields have no grid to scatter into.
 struct Model16NoGrid : Model16 {
   struct Acc {
-    float* lds = nullptr;
+    AdjBox box;
   };
   __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
                                        float*) const {}
   __device__ inline void flush(Acc&, float*, float*) const {}
-  __device__ inline void flush_box(const float*, float*, float*, int, int) const {}
+  __device__ inline void flush_box(const AdjBox&, float*, float*, int, int) const {}
 };
 
 hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,

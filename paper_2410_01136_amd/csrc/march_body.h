@@ -9,6 +9,8 @@
 // results dropped.
 #pragma once
 
+#include <type_traits>
+
 #include "sm_device.h"
 
 namespace sm {
@@ -25,12 +27,26 @@ struct MapAddr {
 };
 
 // Forward march of NESTED pixel q.  FA provides n_freq, sI[], sP[], kappa[].
+// Whether a field type returns zero fields (hence zero emission and Faraday
+// increment) for the steps past the end of the path, so the march need not
+// mask them.
+template <class F, class = void>
+struct ZeroBeyondPath : std::false_type {};
+template <class F>
+struct ZeroBeyondPath<F, std::void_t<decltype(F::kZeroBeyondPath)>>
+    : std::bool_constant<F::kZeroBeyondPath> {};
+template <class F>
+constexpr bool zero_beyond_path() {
+  return ZeroBeyondPath<F>::value;
+}
+
 template <class F, int S, int MF, class FA>
 __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, float* __restrict__ maps,
                                 MapAddr ma, double* __restrict__ phi_end) {
   const Ray ray = make_ray(g, q);
   const auto rctx = fld.ray_ctx(g, ray);
+  constexpr bool zero_beyond = zero_beyond_path<F>();
   double carry = 0.0;  // Faraday sum (n_e B_par, uG cm^-3) of all earlier chunks
   double accI = 0.0;
   double accQ[MF], accU[MF];
@@ -45,7 +61,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     const float bl = v.bx * ray.elx + v.by * ray.ely;
     const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
     const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);
-    const double cn = act ? (double)v.ne * bpar : 0.0;
+    const double cn = (zero_beyond || act) ? (double)v.ne * bpar : 0.0;
     double psi;  // Faraday sum at the midpoint: earlier segments + half of this one
     if constexpr (S == 1) {
       psi = carry + 0.5 * cn;
@@ -56,7 +72,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       carry += group_last<S>(incl);
     }
     Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
-    if (!act) e.u = e.zr = e.zi = 0.0f;
+    if (!zero_beyond && !act) e.u = e.zr = e.zi = 0.0f;
     accI += (double)e.u;
     const double psid = psi * ray.dkpc;
 #pragma unroll
@@ -98,7 +114,7 @@ template <class F, int S, int MF, bool THETA, bool GRID, class FA>
 __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, const float* __restrict__ dmaps,
                                 MapAddr ma, const double* __restrict__ phi_end, double* tb,
-                                float* gbn, float* gc, float* lds_box = nullptr) {
+                                float* gbn, float* gc, const AdjBox* lds_box = nullptr) {
   const Ray ray = make_ray(g, q);
   const double dk = ray.dkpc;
 
@@ -123,7 +139,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   }
 
   typename F::Acc acc;                                 // grid-gradient accumulator
-  if constexpr (GRID) acc.lds = lds_box;
+  if constexpr (GRID) acc.box = *lds_box;
   double E = valid ? phi_end[ma.off + ray.ring] : 0.0;  // sum over steps before the chunk end
   double suf = 0.0;                                    // phase cotangents of later chunks
   double accI = 0.0, accPr[MF], accPi[MF];

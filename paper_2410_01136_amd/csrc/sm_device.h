@@ -398,19 +398,21 @@ struct Grid {
     int64_t base = -1;
     int ix = 0, iy = 0, iz = 0;
     float a[8][5];
-    float* lds = nullptr;  // kAdjBoxFloats floats, or nullptr
+    AdjBox box;  // the workgroup's LDS accumulation box
   };
 
   __device__ inline void flush(Acc& A, float* gbn, float* gc) const {
     if (A.base < 0) return;
-    const int lx = A.ix - p.box0[0], ly = A.iy - p.box0[1], lz = A.iz - p.box0[2];
-    if (A.lds != nullptr && lx >= 0 && lx < kAdjBox - 1 && ly >= 0 && ly < kAdjBox - 1 && lz >= 0 &&
-        lz < kAdjBox - 1) {
+    const AdjBox& B = A.box;
+    const int lx = A.ix - B.b0[0], ly = A.iy - B.b0[1], lz = A.iz - B.b0[2];
+    // the cell's 8 corners all inside the box: unsigned compares take lx >= 0 too
+    if (B.lds != nullptr && (unsigned)lx < (unsigned)(B.d[0] - 1) &&
+        (unsigned)ly < (unsigned)(B.d[1] - 1) && (unsigned)lz < (unsigned)(B.d[2] - 1)) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const int j = ((lz + (k >> 2)) * kAdjBox + (ly + ((k >> 1) & 1))) * kAdjBox + lx + (k & 1);
+        const int j = ((lz + (k >> 2)) * B.d[1] + (ly + ((k >> 1) & 1))) * B.d[0] + lx + (k & 1);
 #pragma unroll
-        for (int ch = 0; ch < 5; ++ch) atomicAdd(A.lds + 5 * j + ch, A.a[k][ch]);
+        for (int ch = 0; ch < 5; ++ch) atomicAdd(B.lds + 5 * j + ch, A.a[k][ch]);
       }
       A.base = -1;
       return;
@@ -432,21 +434,20 @@ struct Grid {
 
   // Adds a workgroup's LDS box to memory (after a barrier); nodes of the box
   // that lie outside the grid hold zeros and are skipped.
-  __device__ inline void flush_box(const float* box, float* gbn, float* gc, int tid,
+  __device__ inline void flush_box(const AdjBox& B, float* gbn, float* gc, int tid,
                                    int nthreads) const {
-    for (int j = tid; j < kAdjBox * kAdjBox * kAdjBox; j += nthreads) {
-      const int gx = p.box0[0] + j % kAdjBox;
-      const int gy = p.box0[1] + (j / kAdjBox) % kAdjBox;
-      const int gz = p.box0[2] + j / (kAdjBox * kAdjBox);
-      if (gx >= p.n[0] || gy >= p.n[1] || gz >= p.n[2]) continue;
+    if (B.lds == nullptr) return;
+    const int nb = B.d[0] * B.d[1] * B.d[2];
+    for (int j = tid; j < nb; j += nthreads) {
+      const int gx = B.b0[0] + j % B.d[0];
+      const int gy = B.b0[1] + (j / B.d[0]) % B.d[1];
+      const int gz = B.b0[2] + j / (B.d[0] * B.d[1]);
       const int64_t v = (int64_t)gx + (int64_t)p.n[0] * ((int64_t)gy + (int64_t)p.n[1] * gz);
+      const float* e = B.lds + 5 * j;
       if (gbn != nullptr)
-        for (int ch = 0; ch < 4; ++ch) {
-          const float val = box[5 * j + ch];
-          if (val != 0.0f) unsafeAtomicAdd(gbn + 4 * v + ch, val);
-        }
-      if (gc != nullptr && p.c != nullptr && box[5 * j + 4] != 0.0f)
-        unsafeAtomicAdd(gc + v, box[5 * j + 4]);
+        for (int ch = 0; ch < 4; ++ch)
+          if (e[ch] != 0.0f) unsafeAtomicAdd(gbn + 4 * v + ch, e[ch]);
+      if (gc != nullptr && p.c != nullptr && e[4] != 0.0f) unsafeAtomicAdd(gc + v, e[4]);
     }
   }
 
@@ -489,6 +490,10 @@ struct Grid {
 // this form only where the cell coordinate of every midpoint of the geometry
 // fits an int and (nz * ny) < 2^24 (24-bit multiplies).
 struct GridB : Grid {
+  // every step n >= n_steps lies outside [n_lo, n_hi), so its B and n_e are
+  // zero and so are its emission and Faraday increment
+  static constexpr bool kZeroBeyondPath = true;
+
   // Steps [n_lo, n_hi) of the sightline have their midpoint inside the grid box:
   // the box's slab interval along the ray in distance, converted to step indices
   // once per sightline instead of six comparisons per step.
@@ -539,7 +544,9 @@ struct GridB : Grid {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double u = s * (n3[k] * p.inv_h[k]) + (g.r_obs[k] - p.lo[k]) * p.inv_h[k];
-      const int ik = min(max((int)floor(u), 0), p.n[k] - 2);
+      // truncation equals floor for u >= 0 and clamps to cell 0 like it below
+      // (|u| < 2^30 is checked on the host, so the conversion is defined)
+      const int ik = min(max((int)u, 0), p.n[k] - 2);
       i3[k] = ik;
       t3[k] = (float)(u - (double)ik);
     }

@@ -32,17 +32,23 @@ struct GridArgs {
   const float* c;    // [nz][ny][nx] N0 or nullptr
   int32_t n[3];
   double lo[3], inv_h[3], umax[3];  // umax = n - 1
-  int32_t box0[3];   // first node of the adjoint's LDS accumulation box
   // 32-bit buffer addressing (grids under 4 GiB): sizes in bytes and the byte
   // strides of one y row and one z plane in the float4 grid and in the N0 grid
   uint32_t bn_bytes, c_bytes;
   uint32_t sy16, sz16, sy4, sz4;
 };
 
-// Nodes per axis of the box around the observer in which the grid adjoint
-// accumulates gradients in LDS (every sightline starts there).
-constexpr int kAdjBox = 12;
-constexpr int kAdjBoxFloats = kAdjBox * kAdjBox * kAdjBox * 5;
+// Box of grid nodes in which one workgroup of the grid adjoint accumulates its
+// gradients in LDS (5 floats per node, x fastest) before adding them to memory
+// once; nodes outside it get global atomic adds.
+// Largest LDS box of one workgroup: 8000 nodes x 5 floats = 160,000 bytes.
+constexpr int kAdjBoxNodesMax = 8000;
+
+struct AdjBox {
+  float* lds = nullptr;  // [d[2]][d[1]][d[0]][5], or nullptr (no box)
+  int b0[3] = {0, 0, 0};  // first node
+  int d[3] = {0, 0, 0};   // nodes per axis
+};
 
 struct SphereArgs {
   float b[3];
