@@ -120,8 +120,9 @@ def main() -> int:
     ap.add_argument("--surrogate-steps", type=int, default=2000, help="training steps of the surrogate")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample")
-    ap.add_argument("--only", choices=("c1", "copy"), default=None,
+    ap.add_argument("--only", choices=("c1", "c2", "copy"), default=None,
                     help="profiling aids: 'c1' runs only the timed headline forward launches; "
+                         "'c2' only the N_side 64 adjoint workloads (analytic and 128^3 grid); "
                          "'copy' runs one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -148,6 +149,10 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         log("copied 1 GiB")
+        return 0
+
+    if args.only == "c2":
+        bench_adjoint(sm, I, np, torch, tune, args)
         return 0
 
     # ---------------------------------------------------------------- C1 inputs
