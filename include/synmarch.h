@@ -136,6 +136,23 @@ syn_status syn_chi2(int64_t n_pix, int32_t n_maps, const float* maps, const floa
                     const double* inv_sigma2, float* dmaps, double* chi2, void* ws,
                     size_t ws_bytes, hipStream_t stream);
 
+/* One step of the Adam optimiser (Kingma & Ba 2015, arXiv:1412.6980,
+   Algorithm 1) in place on n FP32 parameters, as used to fit a gridded field
+   to observed maps in Sec. 3.3 (the gradient comes from syn_adjoint):
+     m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+     params -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+   params, m, v (device, FP32, n each) are updated in place; grads (device)
+   is read; m and v start at zero and t counts updates from 1.  Element i
+   takes part iff bit (i % period) of mask is set (period in [1, 32]; e.g.
+   period 4, mask 0x7 updates the B components of a (B_x, B_y, B_z, n_e)
+   grid and leaves n_e alone); the others are not touched.  Arithmetic in
+   FP32, bias corrections on the host in FP64.  SYN_EINVAL for n < 0,
+   t < 1, betas outside [0, 1), eps < 0, a non-finite lr, a period outside
+   [1, 32] or NULL/misaligned pointers; no launch for n = 0. */
+syn_status syn_adam_step(int64_t n, int32_t period, uint32_t mask, float* params,
+                         const float* grads, float* m, float* v, int32_t t, double lr,
+                         double beta1, double beta2, double eps, hipStream_t stream);
+
 /* The MODEL16 fields sampled on the nodes of a grid: out_bn (device) float
    [nz][ny][nx][4] = (Bx, By, Bz, n_e) and out_c (device) float [nz][ny][nx]
    = N0 (either may be NULL).  n = (nx, ny, nz), each >= 2. */
@@ -151,8 +168,8 @@ syn_status syn_eval_fields(const syn_field* field, int64_t n, const float* xyz, 
 /* ---- coordinate-MLP surrogate of the fields ------------------------------ */
 /* Network: x^ = 2 (r - lo) / (hi - lo) - 1; features sin(2 pi b_k . x^),
    cos(2 pi b_k . x^) for 16 frequency vectors b_k; 4 hidden layers of width
-   128 with exact-erf GELU; a linear output of 5 = (Bx, By, Bz [uG],
-   ln n_e, ln N0).  Weights are BF16 with FP32 biases; products accumulate in
+   128 with tanh-form GELU, x sigmoid(2y) with y = sqrt(2/pi)(x + 0.044715 x^3);
+   a linear output of 5 = (Bx, By, Bz [uG], ln n_e, ln N0).  Weights are BF16 with FP32 biases; products accumulate in
    FP32 on the matrix cores.  syn_mlp_pack converts host FP32 arrays
    (w_in [128][32], b_in [128], w_h [3][128][128], b_h [3][128], w_out
    [5][128], b_out [5], fourier [16][3]) into the packed device layout;

@@ -81,6 +81,9 @@ syn_batch_destroy = _sig("syn_batch_destroy", None, [_vp])
 syn_set_lanes_per_ray = _sig("syn_set_lanes_per_ray", _i32, [_i32, _i32, _i32])
 syn_get_lanes_per_ray = _sig("syn_get_lanes_per_ray", _i32, [_i32, _i32, _i64])
 syn_set_grid_addressing = _sig("syn_set_grid_addressing", _i32, [_i32])
+syn_adam_step = _sig("syn_adam_step", _i32, [_i64, _i32, ctypes.c_uint32, _vp, _vp, _vp, _vp,
+                                             _i32, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, _vp])
 syn_get_grid_addressing = _sig("syn_get_grid_addressing", _i32, [])
 syn_host_nest_pixel = _sig("syn_host_nest_pixel", _i32,
                            [_i32, _i64, ctypes.POINTER(_i64), _dp, _dp])
@@ -275,6 +278,20 @@ def eval_fields(field: Field, xyz: torch.Tensor, stream=None) -> torch.Tensor:
     check(syn_eval_fields(ctypes.byref(field.s), n, xyz.data_ptr(), out.data_ptr(),
                           _stream(stream)), "syn_eval_fields")
     return out
+
+
+def adam_step(params, grads, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8, period: int = 1, mask: int = 1) -> None:
+    """syn_adam_step on contiguous FP32 CUDA tensors of equal size (in place)."""
+    import torch
+    for x in (params, grads, m, v):
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+            raise ValueError("adam_step needs contiguous float32 CUDA tensors")
+        if x.numel() != params.numel():
+            raise ValueError("adam_step tensors differ in size")
+    check(syn_adam_step(params.numel(), period, mask, params.data_ptr(), grads.data_ptr(),
+                        m.data_ptr(), v.data_ptr(), t, lr, beta1, beta2, eps, _stream()),
+          "syn_adam_step")
 
 
 def set_grid_addressing(mode: int) -> None:

@@ -455,6 +455,25 @@ syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lan
   return SYN_OK;
 }
 
+syn_status syn_adam_step(int64_t n, int32_t period, uint32_t mask, float* params,
+                         const float* grads, float* m, float* v, int32_t t, double lr,
+                         double beta1, double beta2, double eps, hipStream_t stream) {
+  if (n < 0) return fail(SYN_EINVAL, "n must be >= 0");
+  if (period < 1 || period > 32) return fail(SYN_EINVAL, "period must be in [1, 32]");
+  if (t < 1) return fail(SYN_EINVAL, "t counts updates from 1");
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
+    return fail(SYN_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+  if (!(eps >= 0.0) || !isfinite(lr)) return fail(SYN_EINVAL, "eps must be >= 0 and lr finite");
+  if (n == 0) return SYN_OK;
+  for (const void* ptr : {(const void*)params, (const void*)grads, (const void*)m, (const void*)v})
+    if (ptr == nullptr || ((uintptr_t)ptr & 3) != 0)
+      return fail(SYN_EINVAL, "params, grads, m, v must be 4-byte aligned device pointers");
+  hipError_t e = sm::launch_adam(n, period, mask, params, grads, m, v, t, lr, beta1, beta2, eps,
+                                 stream);
+  if (e != hipSuccess) return hip_fail(e, "adam launch");
+  return SYN_OK;
+}
+
 syn_status syn_set_grid_addressing(int32_t mode) {
   if (mode < 0 || mode > 3) return fail(SYN_EINVAL, "grid addressing mode must be 0, 1, 2 or 3");
   g_grid_addressing.store(mode);

@@ -72,6 +72,87 @@ hipError_t launch_chi2(int64_t n_pix, int n_maps, const float* maps, const float
   return e;
 }
 
+// One Adam update (Kingma & Ba 2015, Algorithm 1), elementwise; the bias
+// corrections c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t) come from the host.
+// Element i takes part iff bit (i % period) of mask is set.  The float4 form
+// takes four consecutive elements per thread (period divides 4, arrays 16-byte
+// aligned, n a multiple of 4); the scalar form takes any layout.
+struct AdamArgs {
+  float b1, b2, omb1, omb2;  // beta1, beta2, 1 - beta1, 1 - beta2
+  float c1, c2, lr, eps;
+  int period;
+  uint32_t mask;
+};
+
+__device__ inline void adam_one(const AdamArgs& a, float& p, float g, float& m, float& v) {
+  m = a.b1 * m + a.omb1 * g;
+  v = a.b2 * v + a.omb2 * (g * g);
+  p = p - a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+}
+
+__global__ __launch_bounds__(256) void k_adam4(int64_t n4, AdamArgs a, float4* __restrict__ p,
+                                               const float4* __restrict__ g, float4* __restrict__ m,
+                                               float4* __restrict__ v) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const bool on0 = (a.mask >> (0 % a.period)) & 1u, on1 = (a.mask >> (1 % a.period)) & 1u;
+  const bool on2 = (a.mask >> (2 % a.period)) & 1u, on3 = (a.mask >> (3 % a.period)) & 1u;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+    float4 pp = p[i], mm = m[i], vv = v[i];
+    const float4 gg = g[i];
+    if (on0) adam_one(a, pp.x, gg.x, mm.x, vv.x);
+    if (on1) adam_one(a, pp.y, gg.y, mm.y, vv.y);
+    if (on2) adam_one(a, pp.z, gg.z, mm.z, vv.z);
+    if (on3) adam_one(a, pp.w, gg.w, mm.w, vv.w);
+    p[i] = pp;
+    m[i] = mm;
+    v[i] = vv;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adam1(int64_t n, AdamArgs a, float* __restrict__ p,
+                                               const float* __restrict__ g, float* __restrict__ m,
+                                               float* __restrict__ v) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    if (!((a.mask >> (int)(i % a.period)) & 1u)) continue;
+    float pp = p[i], mm = m[i], vv = v[i];
+    adam_one(a, pp, g[i], mm, vv);
+    p[i] = pp;
+    m[i] = mm;
+    v[i] = vv;
+  }
+}
+
+hipError_t launch_adam(int64_t n, int period, uint32_t mask, float* p, const float* g, float* m,
+                       float* v, int t, double lr, double b1, double b2, double eps,
+                       hipStream_t st) {
+  AdamArgs a;
+  a.b1 = (float)b1;
+  a.b2 = (float)b2;
+  a.omb1 = (float)(1.0 - b1);
+  a.omb2 = (float)(1.0 - b2);
+  a.c1 = (float)(1.0 / (1.0 - pow(b1, (double)t)));
+  a.c2 = (float)(1.0 / (1.0 - pow(b2, (double)t)));
+  a.lr = (float)lr;
+  a.eps = (float)eps;
+  a.period = period;
+  a.mask = mask;
+  const bool vec = (n % 4 == 0) && (4 % period == 0) &&
+                   ((((uintptr_t)p | (uintptr_t)g | (uintptr_t)m | (uintptr_t)v) & 15) == 0);
+  const int64_t work = vec ? n / 4 : n;
+  int64_t nb = (work + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  if (vec)
+    k_adam4<<<dim3((unsigned)nb), dim3(256), 0, st>>>(n / 4, a, reinterpret_cast<float4*>(p),
+                                                      reinterpret_cast<const float4*>(g),
+                                                      reinterpret_cast<float4*>(m),
+                                                      reinterpret_cast<float4*>(v));
+  else
+    k_adam1<<<dim3((unsigned)nb), dim3(256), 0, st>>>(n, a, p, g, m, v);
+  return hipGetLastError();
+}
+
 struct NodeGrid {
   int32_t n[3];
   double lo[3], h[3];

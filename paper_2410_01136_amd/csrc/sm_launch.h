@@ -45,6 +45,10 @@ hipError_t launch_chi2(int64_t n_pix, int n_maps, const float* maps, const float
                        int64_t n_partials, hipStream_t st);
 int64_t chi2_partials(int64_t n_pix, int n_maps);
 
+hipError_t launch_adam(int64_t n, int period, uint32_t mask, float* p, const float* g, float* m,
+                       float* v, int t, double lr, double b1, double b2, double eps,
+                       hipStream_t st);
+
 hipError_t launch_sample_model16(const M16Args& m, const int32_t n[3], const double lo[3],
                                  const double hi[3], float* out_bn, float* out_c, hipStream_t st);
 

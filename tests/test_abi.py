@@ -30,7 +30,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(sm):
     names = declared_functions()
-    assert len(names) >= 21
+    assert len(names) >= 22
     for n in names:
         assert hasattr(sm._lib, n), n
 
@@ -189,3 +189,22 @@ def test_batch_create_rejects_bad_input_on_host(sm):
         st = sm.syn_batch_create(ctypes.byref(desc), ctypes.byref(plan))
         assert st == (sm.SYN_EINVAL if nfreq_ok else sm.SYN_EUNSUPPORTED)
         assert not plan.value
+
+
+def test_adam_arguments_rejected_on_host(sm):
+    p = 0x1000
+    ok = dict(n=16, period=4, mask=7, t=1, lr=0.1, b1=0.9, b2=0.999, eps=1e-8)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return sm.syn_adam_step(a["n"], a["period"], a["mask"], p, p, p, p, a["t"], a["lr"],
+                                a["b1"], a["b2"], a["eps"], None)
+
+    assert call(n=-1) == sm.SYN_EINVAL
+    assert call(period=0) == sm.SYN_EINVAL and call(period=33) == sm.SYN_EINVAL
+    assert call(t=0) == sm.SYN_EINVAL
+    assert call(b1=1.0) == sm.SYN_EINVAL and call(b2=-0.1) == sm.SYN_EINVAL
+    assert call(eps=-1.0) == sm.SYN_EINVAL and call(lr=float("nan")) == sm.SYN_EINVAL
+    assert call(n=0) == sm.SYN_OK  # nothing to do, no launch
+    assert sm.syn_adam_step(16, 4, 7, 0x1002, p, p, p, 1, 0.1, 0.9, 0.999, 1e-8, None) == sm.SYN_EINVAL
+    assert sm.syn_adam_step(16, 4, 7, p, None, p, p, 1, 0.1, 0.9, 0.999, 1e-8, None) == sm.SYN_EINVAL
