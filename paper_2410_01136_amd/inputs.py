@@ -80,6 +80,11 @@ class Geometry:
         return self.npix * self.n_steps * len(self.freqs_hz)
 
 
+FIT_BOX_LO = (-20.0, -20.0, -5.0)
+FIT_BOX_HI = (20.0, 20.0, 5.0)
+FIT_GRID = (128, 128, 32)  # nodes (x, y, z) of the fitted B grid
+
+
 def geometry(name: str, **over) -> Geometry:
     """The geometry of a named configuration (keyword overrides allowed)."""
     base = {
@@ -93,6 +98,10 @@ def geometry(name: str, **over) -> Geometry:
         # 2.4 GHz, box (40, 40, 10) kpc
         "E1": dict(nside=64, n_steps=1024, freqs_hz=(2.4e9,), r_obs=(-8.3, 0.0, 0.006),
                    box_lo=(-20.0, -20.0, -5.0), box_hi=(20.0, 20.0, 5.0)),
+        # grid fitting of Sec. 3.3: B on 128 x 128 x 32 voxels over a (40, 40, 10)
+        # kpc box, N_side 64 with 512 steps at 2.4 GHz (the Sec. 3.1 map setup)
+        "G1": dict(nside=64, n_steps=512, freqs_hz=(2.4e9,), box_lo=FIT_BOX_LO,
+                   box_hi=FIT_BOX_HI),
     }[name]
     base.update(over)
     return Geometry(**base)

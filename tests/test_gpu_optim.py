@@ -2,8 +2,8 @@
 loop of Sec. 3.3 (forward, chi^2, grid adjoint, Adam) against the oracle's loop.
 
 Tolerances: Adam runs in FP32, so parameters and moments after each step agree
-with the FP64 reference to a few FP32 roundings (1e-6 relative to the step or
-moment scale).  In the loop the first chi^2 is the map parity; later ones also
+with the FP64 reference to a few FP32 roundings (1e-5 of the step taken; 1e-6
+of the largest gradient, or its square, for the moments).  In the loop the first chi^2 is the map parity; later ones also
 carry the FP32-vs-FP64 gradient difference through Adam's normalised steps, so
 they are compared to 1e-3 relative.
 """
@@ -49,8 +49,12 @@ def test_adam_steps_match_reference(sm, n, period, mask):
     assert np.all(gm[~sel] == 0) and np.all(gv[~sel] == 0)
     step = np.abs(rp - p0)
     assert np.all(np.abs(gp - rp) <= 1e-5 * step + 2e-7 * np.abs(p0) + 1e-12)
-    np.testing.assert_allclose(gm, rm, rtol=2e-6, atol=1e-30)
-    np.testing.assert_allclose(gv, rv, rtol=2e-6, atol=1e-30)
+    # moments are weighted sums of the gradients: compare on the scale of the
+    # largest gradient each element saw (cancellation makes relative errors of
+    # small moments meaningless)
+    gmax = np.max(np.abs(np.stack(grads)), axis=0).astype(np.float64)
+    assert np.all(np.abs(gm - rm) <= 1e-6 * gmax)
+    assert np.all(np.abs(gv - rv) <= 1e-6 * gmax ** 2)
 
 
 def test_grid_fit_loop_matches_oracle_loop(sm, orc):
