@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sync_oracle.c")
 _LIB = os.path.join(_HERE, "libsync_oracle.so")
 
-MODEL16, GRID, SPHERE = 0, 1, 2
+MODEL16, GRID, SPHERE, WMAP = 0, 1, 2, 4
 NPARAM = 16
 MAX_FREQ = 16
 

@@ -53,7 +53,7 @@ static const double OR_PI = 3.14159265358979323846;
 #define OR_NPARAM 16
 #define OR_MAX_FREQ 16
 
-enum { OR_MODEL16 = 0, OR_GRID = 1, OR_SPHERE = 2 };
+enum { OR_MODEL16 = 0, OR_GRID = 1, OR_SPHERE = 2, OR_WMAP = 4 };
 
 /* Geometry and step schedule. */
 typedef struct {
@@ -279,6 +279,79 @@ static void or_model16_vjp(const double* th, const double r[3], const double Bb[
   tb[15] += neb * (-ne * dR);
 }
 
+/*
+ * The WMAP field and cosmic-ray density of Sec. 3.1 (after Page et al. 2007):
+ *   B = b0 [cos psi cos chi rho^ + sin psi cos chi phi^ + sin chi z^] for
+ *   rho_in <= rho <= rho_out, with psi = psi0 + psi1 ln(rho / 8 kpc) and
+ *   chi = chi0 tanh(z / 1 kpc); N0 = C0 exp(-rho / h_r) sech^2(z / h_z).
+ * Outside the ring the paper sets psi and chi to zero; that would leave a
+ * radial field of full strength at every other radius, so B is read as zero
+ * there.  The paper's n_e (YMW16) is not available; the exponential disk of
+ * the 16-parameter model stands in for it.
+ * theta: 0 b0 [uG] 1 psi0 2 psi1 3 chi0 4 rho_in 5 rho_out [kpc] 9 C0 [cm^-3]
+ *        10 h_r 11 h_z [kpc] 12 alpha 13 n0 [cm^-3] 14 hz_ne 15 kappa_ne
+ */
+static const double OR_WMAP_RREF = 8.0;
+
+static void or_wmap(const double* th, const double r[3], double B[3], double* ne, double* n0) {
+  const double x = r[0], y = r[1], z = r[2];
+  const double rho = sqrt(x * x + y * y);
+  B[0] = B[1] = B[2] = 0.0;
+  if (rho >= th[4] && rho <= th[5] && rho > 0.0) {
+    const double rhat[3] = {x / rho, y / rho, 0.0};
+    const double fhat[3] = {-y / rho, x / rho, 0.0};
+    const double psi = th[1] + th[2] * log(rho / OR_WMAP_RREF);
+    const double chi = th[3] * tanh(z / 1.0);
+    for (int k = 0; k < 3; ++k)
+      B[k] = th[0] * (cos(psi) * cos(chi) * rhat[k] + sin(psi) * cos(chi) * fhat[k]);
+    B[2] += th[0] * sin(chi);
+  }
+  const double ch = cosh(z / th[11]);
+  *n0 = th[9] * exp(-rho / th[10]) / (ch * ch);
+  *ne = th[13] * exp(-fabs(z) / th[14] - th[15] * (rho - OR_RSUN));
+}
+
+/* Vector-Jacobian product of or_wmap with respect to theta (adds into tb;
+   the ring radii get none: the field is discontinuous there). */
+static void or_wmap_vjp(const double* th, const double r[3], const double Bb[3], double neb,
+                        double n0b, double* tb) {
+  const double x = r[0], y = r[1], z = r[2];
+  const double rho = sqrt(x * x + y * y);
+  if (rho >= th[4] && rho <= th[5] && rho > 0.0) {
+    const double rhat[3] = {x / rho, y / rho, 0.0};
+    const double fhat[3] = {-y / rho, x / rho, 0.0};
+    const double zhat[3] = {0.0, 0.0, 1.0};
+    const double lnr = log(rho / OR_WMAP_RREF);
+    const double psi = th[1] + th[2] * lnr;
+    const double tz = tanh(z / 1.0);
+    const double chi = th[3] * tz;
+    const double sp = sin(psi), cp = cos(psi), sc = sin(chi), cc = cos(chi);
+    double bd = 0.0, bp = 0.0, bc = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      bd += Bb[k] * (cp * cc * rhat[k] + sp * cc * fhat[k] + sc * zhat[k]);
+      bp += Bb[k] * (-sp * cc * rhat[k] + cp * cc * fhat[k]);
+      bc += Bb[k] * (-cp * sc * rhat[k] - sp * sc * fhat[k] + cc * zhat[k]);
+    }
+    tb[0] += bd;
+    tb[1] += th[0] * bp;
+    tb[2] += th[0] * bp * lnr;
+    tb[3] += th[0] * bc * tz;
+  }
+  const double u = z / th[11];
+  const double ch = cosh(u);
+  const double E = exp(-rho / th[10]) / (ch * ch);
+  const double n0 = th[9] * E;
+  tb[9] += n0b * E;
+  tb[10] += n0b * n0 * rho / (th[10] * th[10]);
+  tb[11] += n0b * n0 * 2.0 * tanh(u) * z / (th[11] * th[11]);
+  const double dR = rho - OR_RSUN;
+  const double En = exp(-fabs(z) / th[14] - th[15] * dR);
+  const double ne = th[13] * En;
+  tb[13] += neb * En;
+  tb[14] += neb * ne * fabs(z) / (th[14] * th[14]);
+  tb[15] += neb * (-ne * dR);
+}
+
 /* Homogeneous sphere (Sec. 2.4 test): uniform fields within radius R0 of a
    centre, zero outside.  theta: 0-2 B [uG], 3 n_e, 4 N0, 5 R0 [kpc] (<= 0 means
    everywhere), 6-8 centre [kpc], 12 alpha. */
@@ -331,6 +404,8 @@ static int64_t or_corner(int64_t base, const int64_t s[3], int c) {
 void or_fields(const or_field* f, const double r[3], double B[3], double* ne, double* n0) {
   if (f->kind == OR_MODEL16) {
     or_model16(f->theta, r, B, ne, n0);
+  } else if (f->kind == OR_WMAP) {
+    or_wmap(f->theta, r, B, ne, n0);
   } else if (f->kind == OR_SPHERE) {
     or_sphere(f->theta, r, B, ne, n0);
   } else {
@@ -538,7 +613,8 @@ static double or_march_pixel(const or_geom* g, const or_field* f, int64_t p, dou
 
 static int or_check(const or_geom* g, const or_field* f) {
   if (g->nside < 1 || g->n_steps < 1 || g->n_freq < 1 || g->n_freq > OR_MAX_FREQ) return -1;
-  if (f->kind != OR_MODEL16 && f->kind != OR_GRID && f->kind != OR_SPHERE) return -1;
+  if (f->kind != OR_MODEL16 && f->kind != OR_GRID && f->kind != OR_SPHERE && f->kind != OR_WMAP)
+    return -1;
   if (f->kind == OR_GRID && (f->grid_bn == NULL || f->grid_n[0] < 2 || f->grid_n[1] < 2 ||
                              f->grid_n[2] < 2))
     return -1;
@@ -695,6 +771,8 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
     or_midpoint(g, &ray, n, r);
     if (f->kind == OR_MODEL16) {
       or_model16_vjp(f->theta, r, Bb, neb_seg, n0b, tb);
+    } else if (f->kind == OR_WMAP) {
+      or_wmap_vjp(f->theta, r, Bb, neb_seg, n0b, tb);
     } else if (f->kind == OR_GRID) {
       if (f->grid_c == NULL) {
         const double zero3[3] = {0, 0, 0};

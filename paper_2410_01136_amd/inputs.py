@@ -124,6 +124,26 @@ def sphere_theta(B_uG=(6.0, 0.0, 0.0), ne=0.01, n0=4.01e-5, R0_kpc=4.0,
     return th
 
 
+def wmap_theta(b0_uG=1.2, psi0=0.4712, psi1=0.0157, chi0=0.4363, n0_earth=4.0e-5,
+               earth=(-8.5, 0.0, 0.0), h_r=5.0, h_z=1.0, ring=(3.0, 20.0), alpha=3.0,
+               ne=(0.03, 1.0, 0.0)) -> np.ndarray:
+    """Parameter vector of the WMAP field of Sec. 3.1 (the paper's true values by
+    default; b0 = 1.2e-6 gauss).  C0 is set so that N0 at `earth` is n0_earth.
+    n_e = (n0, h_z, kappa) of the exponential disk standing in for YMW16.
+
+    Layout: 0 b0 [uG], 1 psi0, 2 psi1, 3 chi0 [rad], 4-5 ring radii [kpc],
+    9 C0 [cm^-3], 10 h_r, 11 h_z [kpc], 12 alpha, 13-15 n_e disk.
+    """
+    th = np.zeros(16)
+    th[0:4] = (b0_uG, psi0, psi1, chi0)
+    th[4:6] = ring
+    rho_e = float(np.hypot(earth[0], earth[1]))
+    th[9] = n0_earth * np.exp(rho_e / h_r) * np.cosh(earth[2] / h_z) ** 2
+    th[10], th[11], th[12] = h_r, h_z, alpha
+    th[13:16] = ne
+    return th
+
+
 def perturbed_thetas(n: int, seed: int) -> np.ndarray:
     """n parameter vectors drawn from N(THETA0, THETA_SIGMA^2), seeded."""
     rng = np.random.default_rng(seed)
