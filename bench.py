@@ -339,7 +339,7 @@ def bench_adjoint(sm, I, np, torch, tune, args):
     res["grid"]["forward_read_path"] = grid_read_path(sm, g.npix)
     # later workloads start from the library's own launch choices
     for k in range(3):
-        for kind in range(4):
+        for kind in range(5):
             sm.set_lanes_per_ray(k, kind, 0)
     sm.set_grid_addressing(0)
     return res

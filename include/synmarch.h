@@ -54,7 +54,8 @@ enum {
   SYN_FIELD_MODEL16 = 0, /* 16-parameter analytic spiral-disk model         */
   SYN_FIELD_GRID = 1,    /* trilinear interpolation of node-centred grids   */
   SYN_FIELD_SPHERE = 2,  /* homogeneous sphere (Sec. 2.4 test)              */
-  SYN_FIELD_MLP = 3      /* coordinate-MLP surrogate of the fields          */
+  SYN_FIELD_MLP = 3,     /* coordinate-MLP surrogate of the fields          */
+  SYN_FIELD_WMAP = 4     /* WMAP field and CR density of Sec. 3.1           */
 };
 
 enum { SYN_NPARAM = 16, SYN_MAX_FREQ = 16, SYN_MAX_NSIDE = 8192 };
@@ -90,7 +91,16 @@ typedef struct syn_geom {
    SPHERE theta: 0-2 B[uG] 3 n_e 4 N0 5 radius[kpc] (<= 0: everywhere)
      6-8 centre[kpc]; fields are uniform inside, zero outside.
    MLP: mlp (device) packed weights from syn_mlp_pack; grid_lo/hi give the box
-     the network's input coordinates are normalised to. */
+     the network's input coordinates are normalised to.
+   WMAP theta (Sec. 3.1, after Page et al. 2007): 0 b0[uG] 1 psi0 2 psi1
+     3 chi0 [rad] 4 rho_in 5 rho_out [kpc] 9 C0[cm^-3] 10 h_r 11 h_z [kpc]
+     12 alpha 13 n0[cm^-3] 14 hz_ne[kpc] 15 kappa_ne[1/kpc]; 6-8 unused.
+       B = b0 (cos psi cos chi rho^ + sin psi cos chi phi^ + sin chi z^) for
+           rho_in <= R <= rho_out, zero elsewhere; psi = psi0 + psi1 ln(R/8),
+           chi = chi0 tanh(z),
+       N0 = C0 e^{-R/h_r} sech^2(z/h_z),  n_e as for MODEL16 (an exponential
+       disk standing in for the paper's YMW16).  theta-gradients of every
+       entry but the ring radii. */
 typedef struct syn_field {
   int32_t kind;
   double theta[SYN_NPARAM];

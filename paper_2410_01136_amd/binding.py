@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsynmarch.so")
 
 SYN_OK, SYN_EINVAL, SYN_EUNSUPPORTED, SYN_ENOMEM, SYN_EHIP, SYN_EWORKSPACE = 0, -1, -2, -3, -4, -5
-FIELD_MODEL16, FIELD_GRID, FIELD_SPHERE, FIELD_MLP = 0, 1, 2, 3
+FIELD_MODEL16, FIELD_GRID, FIELD_SPHERE, FIELD_MLP, FIELD_WMAP = 0, 1, 2, 3, 4
 KERNEL_FORWARD, KERNEL_ADJOINT, KERNEL_BATCH = 0, 1, 2
 NPARAM, MAX_FREQ = 16, 16
 
@@ -189,6 +189,11 @@ def grid(theta, grid_bn: torch.Tensor, grid_c: Optional[torch.Tensor], lo, hi) -
 
 def sphere(theta) -> Field:
     return Field(FIELD_SPHERE, theta)
+
+
+def wmap(theta) -> Field:
+    """The WMAP field and cosmic-ray density of Sec. 3.1 (theta as inputs.wmap_theta)."""
+    return Field(FIELD_WMAP, theta)
 
 
 # --------------------------------------------------------------------------- calls

@@ -60,7 +60,7 @@ double digamma_host(double x) {
 }
 
 // ---- launch shapes ----------------------------------------------------------
-std::atomic<int> g_lanes[3][4];  // [kernel family][field kind], 0 = default
+std::atomic<int> g_lanes[3][5];  // [kernel family][field kind], 0 = default
 std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 64-bit, 2 buffer per lane, 3 shared
 
 // Built-in lanes per sightline, from autotuner runs on MI355X: small maps need
@@ -80,7 +80,7 @@ int default_lanes(int kernel, int kind, int64_t npix) {
 }
 
 int lanes_for(int kernel, int kind, int64_t npix) {
-  const int s = (kernel >= 0 && kernel < 3 && kind >= 0 && kind < 4) ? g_lanes[kernel][kind].load()
+  const int s = (kernel >= 0 && kernel < 3 && kind >= 0 && kind < 5) ? g_lanes[kernel][kind].load()
                                                                       : 0;
   return s > 0 ? s : default_lanes(kernel, kind, npix);
 }
@@ -210,6 +210,28 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
       ga.sz16 = (uint32_t)std::min<uint64_t>(nxy * 16, 0xFFFFFFFFull);
       ga.sy4 = (uint32_t)(nx * 4);
       ga.sz4 = (uint32_t)std::min<uint64_t>(nxy * 4, 0xFFFFFFFFull);
+      return SYN_OK;
+    }
+    case SYN_FIELD_WMAP: {
+      const double* th = f->theta;
+      for (int k : {10, 11, 14})
+        if (!(th[k] > 0.0)) return fail(SYN_EINVAL, "WMAP scale lengths (theta 10, 11, 14) must be > 0");
+      if (!(th[4] >= 0.0 && th[4] < th[5]))
+        return fail(SYN_EINVAL, "WMAP ring radii need 0 <= theta[4] < theta[5]");
+      sm::WmapArgs& w = fp->wmap;
+      w.b0 = (float)th[0];
+      w.psi0 = (float)th[1];
+      w.psi1 = (float)th[2];
+      w.chi0 = (float)th[3];
+      w.rin = (float)th[4];
+      w.rout = (float)th[5];
+      w.C0 = (float)th[9];
+      w.invhr = (float)(1.0 / th[10]);
+      w.invhz = (float)(1.0 / th[11]);
+      w.n0 = (float)th[13];
+      w.invhne = (float)(1.0 / th[14]);
+      w.l2_invhne = (float)(1.4426950408889634 / th[14]);
+      w.l2_kappa = (float)(1.4426950408889634 * th[15]);
       return SYN_OK;
     }
     case SYN_FIELD_SPHERE: {
@@ -447,7 +469,7 @@ syn_status syn_eval_fields(const syn_field* field, int64_t n, const float* xyz, 
 }
 
 syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lanes) {
-  if (kernel < 0 || kernel > 2 || field_kind < 0 || field_kind > 3)
+  if (kernel < 0 || kernel > 2 || field_kind < 0 || field_kind > 4)
     return fail(SYN_EINVAL, "unknown kernel family or field kind");
   if (!(lanes == 0 || lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64))
     return fail(SYN_EINVAL, "lanes per sightline must be 0, 1, 4, 16 or 64");

@@ -222,6 +222,17 @@ struct Model16NoGrid : Model16 {
   __device__ inline void flush_box(const AdjBox&, float*, float*, int, int) const {}
 };
 
+// The WMAP field has no grid to scatter into either.
+struct WmapNoGrid : Wmap {
+  struct Acc {
+    AdjBox box;
+  };
+  __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
+                                       float*) const {}
+  __device__ inline void flush(Acc&, float*, float*) const {}
+  __device__ inline void flush_box(const AdjBox&, float*, float*, int, int) const {}
+};
+
 hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                           const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
                           double* partials, double* dtheta, float* gbn, float* gc,
@@ -233,6 +244,9 @@ hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs&
     case kGrid:
       return adj_s(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, dmaps, phi_end, partials, dtheta,
                    gbn, gc, st);
+    case kWmap:
+      return adj_s(g, fa, ea, WmapNoGrid{Wmap{fp.wmap}}, S, dmaps, phi_end, partials, dtheta,
+                   nullptr, nullptr, st);
     default: return hipErrorInvalidValue;
   }
 }

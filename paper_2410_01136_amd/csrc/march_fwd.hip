@@ -62,6 +62,7 @@ hipError_t launch_forward(const GeomArgs& g, const FreqArgs& fa, const EmitArgs&
         return fwd_s(g, fa, ea, GridB{fp.grid, Model16{fp.m16}}, S, maps, phi_end, st);
       return fwd_s(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, maps, phi_end, st);
     case kSphere: return fwd_s(g, fa, ea, Sphere{fp.sph}, S, maps, phi_end, st);
+    case kWmap: return fwd_s(g, fa, ea, Wmap{fp.wmap}, S, maps, phi_end, st);
     default: return hipErrorInvalidValue;
   }
 }

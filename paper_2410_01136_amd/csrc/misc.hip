@@ -211,6 +211,7 @@ hipError_t launch_eval_fields(const FieldPack& fp, int64_t n, const float* xyz, 
       k_eval_fields<<<grid, block, 0, st>>>(Grid{fp.grid, Model16{fp.m16}}, n, xyz, out);
       break;
     case kSphere: k_eval_fields<<<grid, block, 0, st>>>(Sphere{fp.sph}, n, xyz, out); break;
+    case kWmap: k_eval_fields<<<grid, block, 0, st>>>(Wmap{fp.wmap}, n, xyz, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

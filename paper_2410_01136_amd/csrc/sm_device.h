@@ -746,6 +746,96 @@ struct GridL : GridB {
   }
 };
 
+// The WMAP field and cosmic-ray density of Sec. 3.1 (after Page et al. 2007):
+// B = b0 [cos psi cos chi rho^ + sin psi cos chi phi^ + sin chi z^] inside the
+// ring rho_in <= rho <= rho_out (zero elsewhere), psi = psi0 + psi1 ln(rho/8),
+// chi = chi0 tanh(z); N0 = C0 e^{-rho/h_r} sech^2(z/h_z); n_e an exponential
+// disk.  tanh and sech^2 come from one exp2 each.
+struct Wmap {
+  WmapArgs p;
+
+  __device__ inline FV eval(float x, float y, float z) const {
+    const float rho = __builtin_sqrtf(x * x + y * y);
+    const bool ring = rho >= p.rin && rho <= p.rout && rho > 0.0f;
+    const float ir = frcp(fmaxf(rho, 1e-30f));
+    const float rhx = x * ir, rhy = y * ir;
+    float sp, cp, sc, cc;
+    __sincosf(p.psi0 + p.psi1 * (flog2(fmaxf(rho, 1e-30f)) - 3.0f) * 0.6931471805599453f, &sp,
+              &cp);
+    const float e2 = fexp2(-2.0f * kLog2e * fabsf(z));
+    const float tz = copysignf((1.0f - e2) / (1.0f + e2), z);
+    __sincosf(p.chi0 * tz, &sc, &cc);
+    const float b = ring ? p.b0 : 0.0f;
+    const float ar = b * cp * cc, af = b * sp * cc;
+    FV v;
+    v.bx = ar * rhx - af * rhy;
+    v.by = ar * rhy + af * rhx;
+    v.bz = b * sc;
+    const float ez = fexp2(-2.0f * kLog2e * fabsf(z) * p.invhz);  // sech^2 = 4 ez / (1 + ez)^2
+    const float opz = 1.0f + ez;
+    v.n0 = p.C0 * fexp2(-rho * p.invhr * kLog2e) * 4.0f * ez * frcp(opz * opz);
+    v.ne = p.n0 * fexp2(-(fabsf(z) * p.l2_invhne + (rho - kRsun) * p.l2_kappa));
+    return v;
+  }
+  __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
+    return eval((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
+                (float)(g.r_obs[2] + s * r.nz));
+  }
+  __device__ inline FV eval_point(float x, float y, float z) const { return eval(x, y, z); }
+  struct RayCtx {};
+  __device__ inline RayCtx ray_ctx(const GeomArgs&, const Ray&) const { return {}; }
+  template <int S>
+  __device__ inline FV eval_step(const GeomArgs& g, const Ray& r, const RayCtx&, double s,
+                                 int) const {
+    return eval_at(g, r, s);
+  }
+
+  // Adds dL/dtheta given dL/d(B, n_e, N0) at (x, y, z); tb[16] in FP64.
+  __device__ inline void vjp(float x, float y, float z, const FV& g, double* tb) const {
+    const float rho = __builtin_sqrtf(x * x + y * y);
+    if (rho >= p.rin && rho <= p.rout && rho > 0.0f) {
+      const float ir = frcp(rho);
+      const float rhx = x * ir, rhy = y * ir;
+      const float lnr = (flog2(rho) - 3.0f) * 0.6931471805599453f;
+      float sp, cp, sc, cc;
+      __sincosf(p.psi0 + p.psi1 * lnr, &sp, &cp);
+      const float e2 = fexp2(-2.0f * kLog2e * fabsf(z));
+      const float tz = copysignf((1.0f - e2) / (1.0f + e2), z);
+      __sincosf(p.chi0 * tz, &sc, &cc);
+      const float gr = g.bx * rhx + g.by * rhy;
+      const float gf = -g.bx * rhy + g.by * rhx;
+      const float gz = g.bz;
+      const float bd = cp * cc * gr + sp * cc * gf + sc * gz;
+      const float bp = -sp * cc * gr + cp * cc * gf;
+      const float bc = -cp * sc * gr - sp * sc * gf + cc * gz;
+      tb[0] += (double)bd;
+      tb[1] += (double)(p.b0 * bp);
+      tb[2] += (double)(p.b0 * bp * lnr);
+      tb[3] += (double)(p.b0 * bc * tz);
+    }
+    const float az = fabsf(z);
+    const float ez = fexp2(-2.0f * kLog2e * az * p.invhz);
+    const float opz = 1.0f + ez;
+    const float E = fexp2(-rho * p.invhr * kLog2e) * 4.0f * ez * frcp(opz * opz);
+    const float n0 = p.C0 * E;
+    const float th = copysignf((1.0f - ez) * frcp(opz), z);  // tanh(z / h_z)
+    tb[9] += (double)(g.n0 * E);
+    tb[10] += (double)(g.n0 * n0 * rho * p.invhr * p.invhr);
+    tb[11] += (double)(g.n0 * n0 * 2.0f * th * z * p.invhz * p.invhz);
+    const float dR = rho - kRsun;
+    const float En = fexp2(-(az * p.l2_invhne + dR * p.l2_kappa));
+    const float ne = p.n0 * En;
+    tb[13] += (double)(g.ne * En);
+    tb[14] += (double)(g.ne * ne * az * p.invhne * p.invhne);
+    tb[15] += (double)(-g.ne * ne * dR);
+  }
+  __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
+                                double* tb) const {
+    vjp((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
+        (float)(g.r_obs[2] + s * r.nz), gv, tb);
+  }
+};
+
 // Homogeneous sphere (Sec. 2.4 test).
 struct Sphere {
   SphereArgs p;

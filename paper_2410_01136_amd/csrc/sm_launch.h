@@ -7,7 +7,7 @@
 
 namespace sm {
 
-enum FieldKind { kModel16 = 0, kGrid = 1, kSphere = 2, kMlp = 3 };
+enum FieldKind { kModel16 = 0, kGrid = 1, kSphere = 2, kMlp = 3, kWmap = 4 };
 
 // How the gridded forward reads the grid: 64-bit addresses, 32-bit buffer
 // offsets per lane, or buffer reads of each distinct cell shared through LDS.
@@ -25,6 +25,7 @@ struct FieldPack {
   int grid_path = 0;  // forward's grid reads: GridPath
   SphereArgs sph;
   MlpArgs mlp;
+  WmapArgs wmap;
 };
 
 // Number of 256-thread blocks a launch with S lanes per sightline uses.

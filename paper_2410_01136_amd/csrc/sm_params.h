@@ -27,6 +27,14 @@ struct M16Args {
   float log2_rsun;
 };
 
+// WMAP field of Sec. 3.1 (FP32 constants derived on the host).
+struct WmapArgs {
+  float b0, psi0, psi1, chi0;
+  float rin, rout;
+  float C0, invhr, invhz;
+  float n0, invhne, l2_invhne, l2_kappa;
+};
+
 struct GridArgs {
   const float4* bn;  // [nz][ny][nx] x (Bx, By, Bz, n_e)
   const float* c;    // [nz][ny][nx] N0 or nullptr

@@ -208,3 +208,14 @@ def test_adam_arguments_rejected_on_host(sm):
     assert call(n=0) == sm.SYN_OK  # nothing to do, no launch
     assert sm.syn_adam_step(16, 4, 7, 0x1002, p, p, p, 1, 0.1, 0.9, 0.999, 1e-8, None) == sm.SYN_EINVAL
     assert sm.syn_adam_step(16, 4, 7, p, None, p, p, 1, 0.1, 0.9, 0.999, 1e-8, None) == sm.SYN_EINVAL
+
+
+def test_wmap_descriptor_rejected_on_host(sm):
+    from paper_2410_01136_amd import inputs as I
+    g = sm.geom_from(I.geometry("G1", nside=2, n_steps=8))
+    for k, val in ((10, 0.0), (11, -1.0), (14, 0.0), (4, 25.0)):
+        th = I.wmap_theta()
+        th[k] = val
+        f = sm.wmap(th)
+        st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, None)
+        assert st == sm.SYN_EINVAL and "WMAP" in sm.syn_last_error().decode()

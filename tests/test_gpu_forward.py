@@ -27,7 +27,7 @@ def lanes(sm):
         sm.set_lanes_per_ray(kernel, kind, S)
     yield set_
     for k in range(3):
-        for kind in range(4):
+        for kind in range(5):
             sm.set_lanes_per_ray(k, kind, 0)
 
 
