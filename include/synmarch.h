@@ -201,6 +201,8 @@ typedef struct syn_batch_desc {
   syn_geom geom;               /* nside ignored; exactly one frequency          */
   int32_t use_graph;           /* 1: capture the launch sequence once as a HIP
                                   graph and replay it; 0: launch directly     */
+  int32_t kind;                /* field of every set: SYN_FIELD_MODEL16 (0) or
+                                  SYN_FIELD_WMAP; theta as for syn_field       */
 } syn_batch_desc;
 
 typedef struct syn_batch syn_batch;
@@ -220,6 +222,13 @@ int64_t syn_batch_offset(const syn_batch* plan, int32_t set);
    `stream`; a call with different pointers or weights captures again.  Calls
    on one plan must not overlap (they share the plan's work counters).  The
    plan is bound to the device current at creation. */
+/* Replaces the parameters of every set (host double [n_sets][16], same kind
+   and checks as at creation) for the following runs -- the sampler's case,
+   where chains move every step.  Waits for earlier work on `stream` (which
+   may still read the set table), then copies the new table synchronously; a
+   captured graph stays valid.  On an error nothing changes. */
+syn_status syn_batch_set_theta(syn_batch* plan, const double* theta, hipStream_t stream);
+
 syn_status syn_batch_run(syn_batch* plan, const float* target, const double* inv_sigma2,
                          float* maps, float* dmaps, double* chi2, double* dtheta,
                          hipStream_t stream);

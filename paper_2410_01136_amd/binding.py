@@ -45,7 +45,7 @@ class SynField(ctypes.Structure):
 class SynBatchDesc(ctypes.Structure):
     _fields_ = [("n_sets", ctypes.c_int32), ("nside", ctypes.POINTER(ctypes.c_int32)),
                 ("theta", ctypes.POINTER(ctypes.c_double)), ("geom", SynGeom),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("kind", ctypes.c_int32)]
 
 
 _vp, _i32, _i64, _sz, _dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, \
@@ -77,6 +77,7 @@ syn_batch_create = _sig("syn_batch_create", _i32,
 syn_batch_total_pixels = _sig("syn_batch_total_pixels", _i64, [_vp])
 syn_batch_offset = _sig("syn_batch_offset", _i64, [_vp, _i32])
 syn_batch_run = _sig("syn_batch_run", _i32, [_vp, _vp, _dp, _vp, _vp, _vp, _vp, _vp])
+syn_batch_set_theta = _sig("syn_batch_set_theta", _i32, [_vp, _dp, _vp])
 syn_batch_destroy = _sig("syn_batch_destroy", None, [_vp])
 syn_set_lanes_per_ray = _sig("syn_set_lanes_per_ray", _i32, [_i32, _i32, _i32])
 syn_get_lanes_per_ray = _sig("syn_get_lanes_per_ray", _i32, [_i32, _i32, _i64])

@@ -525,6 +525,9 @@ syn_status syn_host_nest_pixel(int32_t nside, int64_t q, int64_t* ring, double* 
 struct syn_batch {
   sm::BatchLaunch L{};
   std::vector<int64_t> offsets;
+  std::vector<sm::BatchSet> h_sets;  // host copy of the device set table
+  int32_t kind = SYN_FIELD_MODEL16;
+  double freq_hz = 0.0;
   int device = 0;
   int use_graph = 1;
   hipStream_t cap = nullptr;
@@ -553,6 +556,32 @@ void batch_free(syn_batch* b) {
 
 extern "C" {
 
+namespace {
+
+// The field, emission and frequency constants of one set from its theta.
+syn_status fill_set_field(sm::BatchSet* B, const syn_geom* g, int32_t kind, const double* theta) {
+  syn_field f{};
+  f.kind = kind;
+  memcpy(f.theta, theta, sizeof(f.theta));
+  sm::FieldPack fp;
+  syn_status st = check_field(&f, &fp, true);
+  if (st != SYN_OK) return st;
+  B->m = fp.m16;
+  B->w = fp.wmap;
+  sm::FreqArgs fa;
+  freq_args(g, f.theta[12], &fa);
+  B->fa.n_freq = 1;
+  B->fa.sI[0] = fa.sI[0];
+  B->fa.sP[0] = fa.sP[0];
+  B->fa.kappa[0] = fa.kappa[0];
+  B->fa.dlnsI[0] = fa.dlnsI[0];
+  B->fa.dlnsP[0] = fa.dlnsP[0];
+  B->ea = emit_args(f.theta[12]);
+  return SYN_OK;
+}
+
+}  // namespace
+
 syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
   if (plan == nullptr) return fail(SYN_EINVAL, "plan is NULL");
   *plan = nullptr;
@@ -560,6 +589,8 @@ syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
     return fail(SYN_EINVAL, "desc, nside and theta are required");
   if (desc->n_sets < 1 || desc->n_sets > 65536) return fail(SYN_EINVAL, "n_sets must be in [1, 65536]");
   if (desc->geom.n_freq != 1) return fail(SYN_EUNSUPPORTED, "batches use exactly one frequency");
+  if (desc->kind != SYN_FIELD_MODEL16 && desc->kind != SYN_FIELD_WMAP)
+    return fail(SYN_EUNSUPPORTED, "batches take MODEL16 or WMAP fields");
   int64_t all_pix = 0;
   for (int s = 0; s < desc->n_sets; ++s) {
     syn_geom g = desc->geom;
@@ -569,7 +600,7 @@ syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
     if (st != SYN_OK) return st;
     all_pix += ga.npix;
   }
-  const int S = lanes_for(SYN_KERNEL_BATCH, SYN_FIELD_MODEL16, all_pix);
+  const int S = lanes_for(SYN_KERNEL_BATCH, desc->kind, all_pix);
   std::vector<sm::BatchSet> sets(desc->n_sets);
   std::vector<int64_t> offsets(desc->n_sets);
   int64_t total = 0, items = 0;
@@ -580,22 +611,8 @@ syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
     memset(&B, 0, sizeof(B));
     syn_status st = check_geom(&g, &B.g);
     if (st != SYN_OK) return st;
-    syn_field f{};
-    f.kind = SYN_FIELD_MODEL16;
-    memcpy(f.theta, desc->theta + 16 * (int64_t)s, sizeof(f.theta));
-    sm::FieldPack fp;
-    st = check_field(&f, &fp, true);
+    st = fill_set_field(&B, &g, desc->kind, desc->theta + 16 * (int64_t)s);
     if (st != SYN_OK) return st;
-    B.m = fp.m16;
-    sm::FreqArgs fa;
-    freq_args(&g, f.theta[12], &fa);
-    B.fa.n_freq = 1;
-    B.fa.sI[0] = fa.sI[0];
-    B.fa.sP[0] = fa.sP[0];
-    B.fa.kappa[0] = fa.kappa[0];
-    B.fa.dlnsI[0] = fa.dlnsI[0];
-    B.fa.dlnsP[0] = fa.dlnsP[0];
-    B.ea = emit_args(f.theta[12]);
     B.map_off = total;
     offsets[s] = total;
     const int64_t ni = sm::march_blocks(B.g.npix, S);
@@ -607,6 +624,9 @@ syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
   }
   syn_batch* b = new syn_batch();
   b->offsets = offsets;
+  b->h_sets = sets;
+  b->kind = desc->kind;
+  b->freq_hz = desc->geom.freq_hz[0];
   b->use_graph = desc->use_graph != 0;
   hipError_t e = hipGetDevice(&b->device);
   if (e != hipSuccess) {
@@ -615,6 +635,7 @@ syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
   }
   sm::BatchLaunch& L = b->L;
   L.S = S;
+  L.wmap = desc->kind == SYN_FIELD_WMAP;
   L.n_sets = desc->n_sets;
   L.n_items = (int)items;
   L.total = total;
@@ -635,8 +656,8 @@ syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
   if (e != hipSuccess || cus < 1) cus = 256;
-  L.blocks_fwd = cus * sm::batch_blocks_per_cu(S, false);
-  L.blocks_adj = cus * sm::batch_blocks_per_cu(S, true);
+  L.blocks_fwd = cus * sm::batch_blocks_per_cu(S, false, L.wmap);
+  L.blocks_adj = cus * sm::batch_blocks_per_cu(S, true, L.wmap);
   if (b->use_graph) {
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -653,6 +674,39 @@ int64_t syn_batch_total_pixels(const syn_batch* plan) { return plan ? plan->L.to
 int64_t syn_batch_offset(const syn_batch* plan, int32_t set) {
   if (plan == nullptr || set < 0 || set >= plan->L.n_sets) return -1;
   return plan->offsets[set];
+}
+
+syn_status syn_batch_set_theta(syn_batch* plan, const double* theta, hipStream_t stream) {
+  if (plan == nullptr || theta == nullptr) return fail(SYN_EINVAL, "plan and theta are required");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != plan->device) return fail(SYN_EINVAL, "plan belongs to another device");
+  std::vector<sm::BatchSet> sets = plan->h_sets;
+  for (size_t s = 0; s < sets.size(); ++s) {
+    // the set's geometry (one frequency) is rebuilt from its stored arguments
+    syn_geom g{};
+    g.nside = sets[s].g.nside;
+    g.n_steps = sets[s].g.n_steps;
+    for (int k = 0; k < 3; ++k) {
+      g.r_obs_kpc[k] = sets[s].g.r_obs[k];
+      g.box_lo_kpc[k] = sets[s].g.box_lo[k];
+      g.box_hi_kpc[k] = sets[s].g.box_hi[k];
+    }
+    g.r_max_kpc = sets[s].g.r_max;
+    g.n_freq = 1;
+    g.freq_hz[0] = plan->freq_hz;
+    syn_status st = fill_set_field(&sets[s], &g, plan->kind, theta + 16 * (int64_t)s);
+    if (st != SYN_OK) return st;  // nothing changed
+  }
+  // earlier work on `stream` may still read the table
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  e = hipMemcpy(const_cast<sm::BatchSet*>(plan->L.sets), sets.data(),
+                sizeof(sm::BatchSet) * sets.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy of the set table");
+  plan->h_sets = sets;
+  return SYN_OK;
 }
 
 syn_status syn_batch_run(syn_batch* plan, const float* target, const double* inv_sigma2,

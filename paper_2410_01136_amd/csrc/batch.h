@@ -16,7 +16,8 @@ struct BatchSet {
   GeomArgs g;
   FreqArgs1 fa;
   EmitArgs ea;
-  M16Args m;
+  M16Args m;         // field of a MODEL16 plan
+  WmapArgs w;        // field of a WMAP plan
   int64_t map_off;   // ragged offset of this set's pixel 0
   int32_t item0;     // first work item of this set
   int32_t n_items;
@@ -28,6 +29,7 @@ struct BatchChi2Args {
 
 struct BatchLaunch {
   int S;
+  bool wmap;             // the sets' field: WMAP (true) or MODEL16
   const BatchSet* sets;  // device
   int n_sets, n_items;
   int64_t total;
@@ -44,6 +46,6 @@ struct BatchLaunch {
 };
 
 hipError_t launch_batch(const BatchLaunch& L, hipStream_t st);
-int batch_blocks_per_cu(int S, bool adjoint);
+int batch_blocks_per_cu(int S, bool adjoint, bool wmap);
 
 }  // namespace sm

@@ -36,11 +36,39 @@ __global__ void k_batch_reset(unsigned int* counters) {
   if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
 }
 
-template <int S>
+// Analytic fields of the sets, without a grid to scatter gradients into.
+struct Model16NoScatter : Model16 {
+  struct Acc {
+    AdjBox box;
+  };
+  __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
+                                       float*) const {}
+  __device__ inline void flush(Acc&, float*, float*) const {}
+};
+struct WmapNoScatter : Wmap {
+  struct Acc {
+    AdjBox box;
+  };
+  __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
+                                       float*) const {}
+  __device__ inline void flush(Acc&, float*, float*) const {}
+};
+
+// The field of set B in a plan of the given kind.
+template <bool WM>
+__device__ inline auto set_field(const BatchSet& B) {
+  if constexpr (WM)
+    return WmapNoScatter{Wmap{B.w}};
+  else
+    return Model16NoScatter{Model16{B.m}};
+}
+
+template <int S, bool WM>
 __global__ __launch_bounds__(256) void k_batch_fwd(const BatchSet* __restrict__ sets, int n_sets,
                                                    int n_items, unsigned int* counter,
                                                    int64_t total, float* __restrict__ maps,
                                                    double* __restrict__ phi_end) {
+  using F = decltype(set_field<WM>(sets[0]));
   for (;;) {
     const int item = next_item(counter);
     if (item >= n_items) return;
@@ -49,26 +77,18 @@ __global__ __launch_bounds__(256) void k_batch_fwd(const BatchSet* __restrict__ 
     int64_t q = (int64_t)(item - B.item0) * (256 / S) + threadIdx.x / S;
     const bool valid = q < B.g.npix;
     if (!valid) q = B.g.npix - 1;
-    fwd_lane<Model16, S, 1>(B.g, B.fa, B.ea, Model16{B.m}, q, sub, valid, maps,
-                            MapAddr{total, B.map_off}, phi_end);
+    fwd_lane<F, S, 1>(B.g, B.fa, B.ea, set_field<WM>(B), q, sub, valid, maps,
+                      MapAddr{total, B.map_off}, phi_end);
   }
 }
 
-struct Model16NoScatter : Model16 {
-  struct Acc {
-    float* lds = nullptr;
-  };
-  __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
-                                       float*) const {}
-  __device__ inline void flush(Acc&, float*, float*) const {}
-};
-
-template <int S>
+template <int S, bool WM>
 __global__ __launch_bounds__(256) void k_batch_adj(const BatchSet* __restrict__ sets, int n_sets,
                                                    int n_items, unsigned int* counter,
                                                    int64_t total, const float* __restrict__ dmaps,
                                                    const double* __restrict__ phi_end,
                                                    double* __restrict__ partials) {
+  using F = decltype(set_field<WM>(sets[0]));
   for (;;) {
     const int item = next_item(counter);
     if (item >= n_items) return;
@@ -80,9 +100,8 @@ __global__ __launch_bounds__(256) void k_batch_adj(const BatchSet* __restrict__ 
     double tb[kNParam];
 #pragma unroll
     for (int k = 0; k < kNParam; ++k) tb[k] = 0.0;
-    adj_lane<Model16NoScatter, S, 1, true, false>(B.g, B.fa, B.ea, Model16NoScatter{Model16{B.m}},
-                                                  q, sub, valid, dmaps, MapAddr{total, B.map_off},
-                                                  phi_end, tb, nullptr, nullptr);
+    adj_lane<F, S, 1, true, false>(B.g, B.fa, B.ea, set_field<WM>(B), q, sub, valid, dmaps,
+                                   MapAddr{total, B.map_off}, phi_end, tb, nullptr, nullptr);
     const double r = block_reduce16(tb, threadIdx.x);
     if (threadIdx.x < kNParam) partials[(int64_t)item * kNParam + threadIdx.x] = r;
   }
@@ -132,46 +151,57 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchSet* __restrict
   }
 }
 
-template <int S>
+template <int S, bool WM>
 static int occupancy_blocks(bool adjoint) {
   int per_cu = 0;
-  hipError_t e = adjoint ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_adj<S>, 256, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fwd<S>, 256, 0);
+  hipError_t e =
+      adjoint ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_adj<S, WM>, 256, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fwd<S, WM>, 256, 0);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return per_cu;
 }
 
-int batch_blocks_per_cu(int S, bool adjoint) {
+template <bool WM>
+static int blocks_per_cu(int S, bool adjoint) {
   switch (S) {
-    case 1: return occupancy_blocks<1>(adjoint);
-    case 4: return occupancy_blocks<4>(adjoint);
-    case 16: return occupancy_blocks<16>(adjoint);
-    case 64: return occupancy_blocks<64>(adjoint);
+    case 1: return occupancy_blocks<1, WM>(adjoint);
+    case 4: return occupancy_blocks<4, WM>(adjoint);
+    case 16: return occupancy_blocks<16, WM>(adjoint);
+    case 64: return occupancy_blocks<64, WM>(adjoint);
     default: return 1;
   }
 }
 
-template <int S>
+int batch_blocks_per_cu(int S, bool adjoint, bool wmap) {
+  return wmap ? blocks_per_cu<true>(S, adjoint) : blocks_per_cu<false>(S, adjoint);
+}
+
+template <int S, bool WM>
 static hipError_t batch_go(const BatchLaunch& L, hipStream_t st) {
   k_batch_reset<<<1, 64, 0, st>>>(L.counters);
-  k_batch_fwd<S><<<L.blocks_fwd, 256, 0, st>>>(L.sets, L.n_sets, L.n_items, L.counters, L.total,
-                                               L.maps, L.phi);
+  k_batch_fwd<S, WM><<<L.blocks_fwd, 256, 0, st>>>(L.sets, L.n_sets, L.n_items, L.counters,
+                                                   L.total, L.maps, L.phi);
   k_batch_chi2<<<L.n_sets, 256, 0, st>>>(L.sets, L.total, L.maps, L.target, L.chi2_args, L.dmaps,
                                          L.chi2);
-  k_batch_adj<S><<<L.blocks_adj, 256, 0, st>>>(L.sets, L.n_sets, L.n_items, L.counters + 1, L.total,
-                                               L.dmaps, L.phi, L.partials);
+  k_batch_adj<S, WM><<<L.blocks_adj, 256, 0, st>>>(L.sets, L.n_sets, L.n_items, L.counters + 1,
+                                                   L.total, L.dmaps, L.phi, L.partials);
   k_batch_reduce<<<L.n_sets, 256, 0, st>>>(L.sets, L.partials, L.dtheta);
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchLaunch& L, hipStream_t st) {
+template <bool WM>
+static hipError_t batch_s(const BatchLaunch& L, hipStream_t st) {
   switch (L.S) {
-    case 1: return batch_go<1>(L, st);
-    case 4: return batch_go<4>(L, st);
-    case 16: return batch_go<16>(L, st);
-    case 64: return batch_go<64>(L, st);
+    case 1: return batch_go<1, WM>(L, st);
+    case 4: return batch_go<4, WM>(L, st);
+    case 16: return batch_go<16, WM>(L, st);
+    case 64: return batch_go<64, WM>(L, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_batch(const BatchLaunch& L, hipStream_t st) {
+  return L.wmap ? batch_s<true>(L, st) : batch_s<false>(L, st);
 }
 
 }  // namespace sm

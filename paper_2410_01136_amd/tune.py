@@ -149,8 +149,9 @@ def tune_adjoint(geom, field, dmaps, ws, want_theta=True, dgrid_bn=None, dgrid_c
                                    dgrid_bn=dgrid_bn, dgrid_c=dgrid_c), **kw)
 
 
-def make_batch(thetas, nsides, geom, use_graph=True):
-    """Creates a batch plan (ctypes handle) for MODEL16 parameter sets."""
+def make_batch(thetas, nsides, geom, use_graph=True, kind=None):
+    """Creates a batch plan (ctypes handle) for MODEL16 (default) or WMAP
+    parameter sets."""
     import ctypes
     import numpy as np
     desc = sm.SynBatchDesc()
@@ -161,6 +162,7 @@ def make_batch(thetas, nsides, geom, use_graph=True):
     desc.theta = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     desc.geom = geom
     desc.use_graph = int(use_graph)
+    desc.kind = sm.FIELD_MODEL16 if kind is None else int(kind)
     plan = ctypes.c_void_p()
     sm.check(sm.syn_batch_create(ctypes.byref(desc), ctypes.byref(plan)), "syn_batch_create")
     return plan

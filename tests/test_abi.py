@@ -30,7 +30,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(sm):
     names = declared_functions()
-    assert len(names) >= 22
+    assert len(names) >= 23
     for n in names:
         assert hasattr(sm._lib, n), n
 
@@ -188,6 +188,15 @@ def test_batch_create_rejects_bad_input_on_host(sm):
         plan = ctypes.c_void_p()
         st = sm.syn_batch_create(ctypes.byref(desc), ctypes.byref(plan))
         assert st == (sm.SYN_EINVAL if nfreq_ok else sm.SYN_EUNSUPPORTED)
+        assert not plan.value
+    # only analytic fields batch
+    desc.geom = sm.geom_from(g)
+    ns = np.array([8, 8], dtype=np.int32)
+    desc.nside = ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    for kind in (sm.FIELD_GRID, sm.FIELD_SPHERE, sm.FIELD_MLP, 7):
+        desc.kind = kind
+        plan = ctypes.c_void_p()
+        assert sm.syn_batch_create(ctypes.byref(desc), ctypes.byref(plan)) == sm.SYN_EUNSUPPORTED
         assert not plan.value
 
 

@@ -31,8 +31,9 @@ def lanes(sm):
         sm.set_lanes_per_ray(k, sm.FIELD_MODEL16, 0)
 
 
-def make_plan(sm, thetas, nsides, g, use_graph=True):
+def make_plan(sm, thetas, nsides, g, use_graph=True, kind=0):
     desc = sm.SynBatchDesc()
+    desc.kind = kind
     desc.n_sets = len(nsides)
     ns = np.ascontiguousarray(nsides, dtype=np.int32)
     th = np.ascontiguousarray(thetas, dtype=np.float64)
@@ -147,3 +148,60 @@ def test_batch_without_graph_equals_graph(sm):
             sm.syn_batch_destroy(plan)
     for a, b in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, b)
+
+
+def test_wmap_batch_matches_single_sets_and_oracle(sm, orc):
+    """WMAP chains of a sampler: one plan, several parameter vectors, one target."""
+    import torch
+    nsides = [8, 4, 8, 8, 2]
+    rng = np.random.default_rng(3201)
+    thetas = np.array([I.wmap_theta(b0_uG=1.2 * (1 + 0.1 * rng.standard_normal()),
+                                    psi0=0.4712 + 0.1 * rng.standard_normal(),
+                                    psi1=0.0157 + 0.05 * rng.standard_normal(),
+                                    chi0=0.4363 + 0.1 * rng.standard_normal())
+                       for _ in nsides])
+    g = I.geometry("G1", nside=4, n_steps=80)
+    plan = make_plan(sm, thetas, nsides, g, kind=sm.FIELD_WMAP)
+    try:
+        total = sm.syn_batch_total_pixels(plan)
+        offs = [sm.syn_batch_offset(plan, s) for s in range(len(nsides))]
+        inv = np.array([0.0, 1e6, 1e6])  # Q and U with sigma = 1 mK
+        tgt = np.zeros((3, total), dtype=np.float32)
+        truth = I.wmap_theta()
+        for s, ns in enumerate(nsides):
+            gs = I.geometry("G1", nside=ns, n_steps=80)
+            tgt[:, offs[s]:offs[s] + 12 * ns * ns] = sm.forward(sm.geom_from(gs), sm.wmap(truth)).cpu().numpy()[0]
+        tgt_t = torch.from_numpy(tgt).cuda()
+        maps = torch.empty((3, total), dtype=torch.float32, device="cuda")
+        dmaps = torch.empty_like(maps)
+        chi2 = torch.empty(len(nsides), dtype=torch.float64, device="cuda")
+        dth = torch.empty((len(nsides), 16), dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            sm.check(sm.syn_batch_run(plan, tgt_t.data_ptr(), inv.ctypes.data_as(sm._dp), maps.data_ptr(),
+                                      dmaps.data_ptr(), chi2.data_ptr(), dth.data_ptr(), sm._stream()),
+                     "syn_batch_run")
+            torch.cuda.synchronize()
+        for s, ns in enumerate(nsides):
+            gs = I.geometry("G1", nside=ns, n_steps=80)
+            geom = sm.geom_from(gs)
+            f = sm.wmap(thetas[s])
+            ws = sm.alloc_workspace(geom, f)
+            m = sm.forward(geom, f, ws=ws)
+            c, dm = sm.chi2(m, tgt_t[:, offs[s]:offs[s] + 12 * ns * ns][None].contiguous(), inv[None])
+            d = sm.adjoint(geom, f, dm, ws)
+            assert chi2[s].item() == pytest.approx(c.item(), rel=1e-6)
+            np.testing.assert_allclose(dth[s].cpu().numpy(), d.cpu().numpy(), rtol=1e-5,
+                                       atol=1e-6 * np.abs(d.cpu().numpy()).max())
+        # one set against the oracle's gradient of the same chi^2
+        s = 1
+        gs = I.geometry("G1", nside=nsides[s], n_steps=80)
+        og = oracle_geom(orc, gs)
+        ref_maps = orc.forward(og, orc.Field(orc.WMAP, thetas[s]))
+        t_s = tgt[:, offs[s]:offs[s] + 12 * nsides[s] ** 2][None].astype(np.float64)
+        ref_dm = 2 * inv[None, :, None] * (ref_maps - t_s)
+        ref, _, _ = orc.adjoint(og, orc.Field(orc.WMAP, thetas[s]), ref_dm)
+        sk = np.maximum(np.abs(thetas[s]), 1e-2)
+        err = np.abs(dth[s].cpu().numpy() - ref) * sk
+        assert np.all(err <= 1e-3 * np.abs(ref * sk).max())
+    finally:
+        sm.syn_batch_destroy(plan)
