@@ -212,7 +212,7 @@ def main() -> int:
         "peak_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
         "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
         "kernel": f"sm::k_forward<{'GridL' if 'shared' in grid_read_path(sm, g.npix) else 'GridB'}, "
-                  f"S={lanes}, MF=4> ({grid_read_path(sm, g.npix)})",
+                  f"S={lanes}, MF={3 if len(g.freqs_hz) == 3 else 4}> ({grid_read_path(sm, g.npix)})",
         "flop_per_unit": FLOP_PER_PIX_STEP_C1 / len(g.freqs_hz),
         "units_per_launch": units,
         "launch_ms": round(ev_ms, 4),

@@ -40,6 +40,10 @@ constexpr bool zero_beyond_path() {
   return ZeroBeyondPath<F>::value;
 }
 
+// MF frequencies held in registers: 1 and 3 are exact counts (the frequency
+// loops need no test), 4 and 16 upper bounds.
+constexpr bool exact_freqs(int MF) { return MF == 1 || MF == 3; }
+
 template <class F, int S, int MF, class FA>
 __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, float* __restrict__ maps,
@@ -77,7 +81,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     const double psid = psi * ray.dkpc;
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
-      if (f < fa.n_freq) {
+      if (exact_freqs(MF) || f < fa.n_freq) {
         float sn, cs;
         sincos_turns(psid * fa.kappa[f], &sn, &cs);  // turns of 2 RM lambda^2
         accQ[f] += (double)(e.zr * cs - e.zi * sn);
@@ -97,7 +101,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   if (valid && sub == 0) {
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
-      if (f < fa.n_freq) {
+      if (exact_freqs(MF) || f < fa.n_freq) {
         maps[ma.at(f, 0, ray.ring)] = (float)(fa.sI[f] * ray.dkpc * accI);
         maps[ma.at(f, 1, ray.ring)] = (float)(fa.sP[f] * ray.dkpc * accQ[f]);
         maps[ma.at(f, 2, ray.ring)] = (float)(fa.sP[f] * ray.dkpc * accU[f]);

@@ -31,6 +31,8 @@ static hipError_t fwd_mf(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
   const int64_t nb = march_blocks(g.npix, S);
   if (fa.n_freq <= 1)
     k_forward<F, S, 1><<<dim3((unsigned)nb), dim3(256), 0, st>>>(g, fa, ea, f, maps, phi_end);
+  else if (std::is_same_v<F, GridL> && fa.n_freq == 3)  // the three-frequency gridded maps
+    k_forward<F, S, 3><<<dim3((unsigned)nb), dim3(256), 0, st>>>(g, fa, ea, f, maps, phi_end);
   else if (fa.n_freq <= 4)
     k_forward<F, S, 4><<<dim3((unsigned)nb), dim3(256), 0, st>>>(g, fa, ea, f, maps, phi_end);
   else
