@@ -240,8 +240,11 @@ enum { SYN_KERNEL_FORWARD = 0, SYN_KERNEL_ADJOINT = 1, SYN_KERNEL_BATCH = 2 };
 
 /* Lanes per sightline S (1, 4, 16 or 64): consecutive steps of one sightline
    are spread over S lanes and their Faraday sums are combined with a
-   wavefront prefix scan.  0 restores the built-in choice.  Applies to the
-   given (kernel, field kind) pair on the calling process. */
+   wavefront prefix scan.  An adjoint that returns a grid gradient instead
+   gives each of the S lanes a contiguous piece of ceil(n_steps / S) steps
+   (the pieces are joined by group scans of their Faraday sums and phase
+   cotangents).  0 restores the built-in choice.  Applies to the given
+   (kernel, field kind) pair on the calling process. */
 syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lanes);
 int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix);
 

@@ -70,7 +70,8 @@ std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 64-bit, 2 buffer per l
 int default_lanes(int kernel, int kind, int64_t npix) {
   if (kernel == SYN_KERNEL_BATCH) return 1;
   if (kernel == SYN_KERNEL_ADJOINT) {
-    if (kind == SYN_FIELD_GRID) return 1;
+    // grid gradients: four contiguous pieces per sightline
+    if (kind == SYN_FIELD_GRID) return 4;
     return npix < (1 << 14) ? 16 : 4;
   }
   if (npix < (1 << 14)) return 64;

@@ -41,17 +41,11 @@ struct Model16NoScatter : Model16 {
   struct Acc {
     AdjBox box;
   };
-  __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
-                                       float*) const {}
-  __device__ inline void flush(Acc&, float*, float*) const {}
 };
 struct WmapNoScatter : Wmap {
   struct Acc {
     AdjBox box;
   };
-  __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
-                                       float*) const {}
-  __device__ inline void flush(Acc&, float*, float*) const {}
 };
 
 // The field of set B in a plan of the given kind.

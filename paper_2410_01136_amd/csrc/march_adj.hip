@@ -11,6 +11,8 @@
 // Outputs: theta-gradients reduced per block in FP64 (fixed order, no atomics)
 // and finished by a second kernel; grid gradients scattered with FP32 atomic
 // adds onto the 8 corner nodes of each step's cell.
+#include <algorithm>
+
 #include "march_body.h"
 #include "sm_launch.h"
 
@@ -100,12 +102,15 @@ __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitAr
 #pragma unroll
   for (int k = 0; k < (THETA ? kNParam : 1); ++k) tb[k] = 0.0;
   AdjBox box;
+  float* stage = nullptr;
   if constexpr (GRID) {
-    extern __shared__ float lds_box[];  // box_cap nodes x 5 floats
-    box = workgroup_box(g, fld, q, lds_box, box_cap);
+    // box_cap nodes x 5 floats, then kStageRecs records per wavefront
+    extern __shared__ float lds_dyn[];
+    box = workgroup_box(g, fld, q, lds_dyn, box_cap);
+    stage = lds_dyn + 5 * box_cap + (threadIdx.x >> 6) * (kStageRecs * kStageFloats);
   }
   adj_lane<F, S, MF, THETA, GRID>(g, fa, ea, fld, q, sub, valid, dmaps, MapAddr{g.npix, 0}, phi_end,
-                                  tb, gbn, gc, &box);
+                                  tb, gbn, gc, &box, stage);
   if constexpr (GRID) {
     __syncthreads();
     fld.flush_box(box, gbn, gc, threadIdx.x, 256);
@@ -141,8 +146,8 @@ static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
   int cap = 0;
   size_t lds = 0;
   if (GR) {
-    // one workgroup per CU or fewer: the box may take all of the CU's LDS;
-    // otherwise a quarter, so that four workgroups fit
+    // the LDS of a CU is shared by the workgroups it runs at once (at most four
+    // here, fewer when registers or the grid size allow no more)
     static int n_cu = 0;
     if (n_cu == 0) {
       int dev = 0, v = 0;
@@ -152,16 +157,24 @@ static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
       else
         n_cu = 256;
     }
-    cap = nb <= n_cu ? kAdjBoxNodesMax : kAdjBoxNodesMax / 4;
-    lds = (size_t)cap * 5 * sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
+    // workgroups one CU can hold with the smallest box (registers permitting)
+    static int by_regs = 0;
+    if (by_regs == 0) {
+      const void* fn = reinterpret_cast<const void*>(&k_adjoint<F, S, MF, TH, GR>);
       hipError_t ea2 = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(&k_adjoint<F, S, MF, TH, GR>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)((size_t)kAdjBoxNodesMax * 5 * sizeof(float)));
+          fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+          (int)((size_t)kAdjBoxNodesMax * 5 * sizeof(float) + kStageBytesPerBlock));
       if (ea2 != hipSuccess) return ea2;
-      attr_set = true;
+      int nblk = 0;
+      ea2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nblk, fn, 256, (size_t)adj_box_cap(4) * 5 * sizeof(float) + kStageBytesPerBlock);
+      if (ea2 != hipSuccess) return ea2;
+      by_regs = std::min(std::max(nblk, 1), 4);
     }
+    // the box takes the LDS share of one of the workgroups that run on a CU at once
+    const int per_cu = (int)std::min<int64_t>(by_regs, (nb + n_cu - 1) / n_cu);
+    cap = adj_box_cap(per_cu);
+    lds = (size_t)cap * 5 * sizeof(float) + kStageBytesPerBlock;
   }
   k_adjoint<F, S, MF, TH, GR><<<dim3((unsigned)nb), dim3(256), lds, st>>>(g, fa, ea, f, dm, pe, part,
                                                                            gbn, gc, cap);
@@ -216,10 +229,6 @@ struct Model16NoGrid : Model16 {
   struct Acc {
     AdjBox box;
   };
-  __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
-                                       float*) const {}
-  __device__ inline void flush(Acc&, float*, float*) const {}
-  __device__ inline void flush_box(const AdjBox&, float*, float*, int, int) const {}
 };
 
 // The WMAP field has no grid to scatter into either.
@@ -227,10 +236,6 @@ struct WmapNoGrid : Wmap {
   struct Acc {
     AdjBox box;
   };
-  __device__ inline void accumulate_at(const GeomArgs&, const Ray&, double, const FV&, Acc&, float*,
-                                       float*) const {}
-  __device__ inline void flush(Acc&, float*, float*) const {}
-  __device__ inline void flush_box(const AdjBox&, float*, float*, int, int) const {}
 };
 
 hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,

@@ -4,6 +4,8 @@
 // A sightline is owned by S consecutive lanes (S = 1, 4, 16, 64).  Lanes take
 // consecutive steps in chunks of S; the Faraday increments of a chunk are
 // combined with a wavefront prefix scan and carried across chunks in FP64.
+// (The reverse march with a grid gradient splits the steps into contiguous
+// pieces instead; see adj_lane.)
 // Every lane of a group must call these bodies (the scans are collective);
 // idle lanes pass valid = false and march a real sightline with their
 // results dropped.
@@ -114,11 +116,24 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 // Reverse march of NESTED pixel q for L = sum(dmaps * maps).  Adds this
 // lane's share of dL/dtheta into tb (THETA) and scatters grid gradients
 // (GRID).  FA additionally provides dlnsI[], dlnsP[].
+//
+// With a grid gradient and S > 1 the S lanes of a sightline do not interleave
+// steps: lane k walks its own contiguous piece of ceil(N / S) steps, so that it
+// stays in one cell for as many steps as a single lane would and its register
+// accumulator flushes as rarely.  The piece needs two numbers from the pieces
+// beyond it: the Faraday sum before its end, and the sum of the phase
+// cotangents after it.  A pre-pass over the piece gets both with one march:
+// the Faraday sum of the piece, and per frequency the sum of z_n e^{2 pi i t_n}
+// with t_n counted from the piece start; once a group scan has given the
+// Faraday sum of the earlier pieces, a rotation by its phase turns the latter
+// into the piece's phase-cotangent total, and a suffix scan gives each piece
+// those of the pieces after it.
 template <class F, int S, int MF, bool THETA, bool GRID, class FA>
 __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, const float* __restrict__ dmaps,
                                 MapAddr ma, const double* __restrict__ phi_end, double* tb,
-                                float* gbn, float* gc, const AdjBox* lds_box = nullptr) {
+                                float* gbn, float* gc, const AdjBox* lds_box = nullptr,
+                                float* lds_stage = nullptr) {
   const Ray ray = make_ray(g, q);
   const double dk = ray.dkpc;
 
@@ -142,26 +157,79 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     }
   }
 
-  typename F::Acc acc;                                 // grid-gradient accumulator
-  if constexpr (GRID) acc.box = *lds_box;
-  double E = valid ? phi_end[ma.off + ray.ring] : 0.0;  // sum over steps before the chunk end
-  double suf = 0.0;                                    // phase cotangents of later chunks
+  typename F::Acc acc;  // grid-gradient accumulator
+  if constexpr (GRID) {
+    acc.box = *lds_box;
+    acc.stage = lds_stage;
+  }
+  // each lane walks a contiguous run [n_lo, n_hi) of steps (one lane per
+  // sightline, or one piece of it) rather than every S-th step
+  constexpr bool SPLIT = GRID && S > 1;
+  constexpr bool SERIAL = S == 1 || SPLIT;
+  int n_lo = 0, n_hi = g.n_steps;
+  double E = 0.0;    // Faraday sum over the steps before the current chunk's end
+  double suf = 0.0;  // phase cotangents of the steps after it
+  if constexpr (SPLIT) {
+    const int len = (g.n_steps + S - 1) / S;
+    n_lo = min(sub * len, g.n_steps);
+    n_hi = min(n_lo + len, g.n_steps);
+    double A = 0.0, Wr[MF], Wi[MF];
+#pragma unroll
+    for (int f = 0; f < MF; ++f) Wr[f] = Wi[f] = 0.0;
+    for (int n = n_lo; n < n_hi; ++n) {
+      const FV v = fld.eval_at(g, ray, ((double)n + 0.5) * dk);
+      const float bl = v.bx * ray.elx + v.by * ray.ely;
+      const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
+      const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);
+      const double cn = (double)v.ne * bpar;
+      const double psid = (A + 0.5 * cn) * dk;  // Faraday sum from the piece start
+      A += cn;
+      const Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
+#pragma unroll
+      for (int f = 0; f < MF; ++f) {
+        if (f < fa.n_freq) {
+          float sn, cs;
+          sincos_turns(psid * fa.kappa[f], &sn, &cs);
+          Wr[f] += (double)(e.zr * cs - e.zi * sn);
+          Wi[f] += (double)(e.zr * sn + e.zi * cs);
+        }
+      }
+    }
+    const double incl = group_inclusive_scan<S>(A, sub);
+    const double psid0 = (incl - A) * dk;  // Faraday sum of the earlier pieces
+    double Bk = 0.0;                       // sum of this piece's phase cotangents
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+      if (f < fa.n_freq) {
+        float sn, cs;
+        sincos_turns(psid0 * fa.kappa[f], &sn, &cs);
+        const double rr = kr[f] * cs - ki[f] * sn, ri = kr[f] * sn + ki[f] * cs;
+        Bk += rr * Wi[f] + ri * Wr[f];  // Im(k e^{2 pi i t0} W)
+      }
+    }
+    E = incl;
+    suf = group_suffix_scan<S>(Bk, sub) - Bk;
+  } else if (valid) {
+    E = phi_end[ma.off + ray.ring];
+  }
   double accI = 0.0, accPr[MF], accPi[MF];
 #pragma unroll
   for (int f = 0; f < MF; ++f) accPr[f] = accPi[f] = 0.0;
 
-  const int nchunk = (g.n_steps + S - 1) / S;
-  for (int ch = nchunk - 1; ch >= 0; --ch) {
-    const int n = ch * S + sub;
-    const bool act = valid && n < g.n_steps;
+  // every lane of a wavefront runs the same number of iterations (the grid
+  // scatter is collective); a short or empty last piece idles through the rest
+  const int n_iter = SPLIT ? (g.n_steps + S - 1) / S : SERIAL ? g.n_steps : (g.n_steps + S - 1) / S;
+  for (int it = n_iter - 1; it >= 0; --it) {
+    const int n = SERIAL ? n_lo + it : it * S + sub;
+    const bool act = valid && n < n_hi;
     const double s = ((double)n + 0.5) * dk;
     const FV v = fld.eval_at(g, ray, s);
     const float bl = v.bx * ray.elx + v.by * ray.ely;
     const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
     const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);
-    const double cn = (n < g.n_steps) ? (double)v.ne * bpar : 0.0;
+    const double cn = (n < n_hi) ? (double)v.ne * bpar : 0.0;
     double psi;
-    if constexpr (S == 1) {
+    if constexpr (SERIAL) {
       E -= cn;
       psi = E + 0.5 * cn;
     } else {
@@ -194,7 +262,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     // cotangent of the Faraday sum at this midpoint: Im(zc K)
     const double pb = (double)e.zr * Ki + (double)e.zi * Kr;
     double cbar;  // cotangent of this step's increment: later steps + half of its own
-    if constexpr (S == 1) {
+    if constexpr (SERIAL) {
       cbar = suf + 0.5 * pb;
       suf += pb;
     } else {
@@ -214,15 +282,15 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     gv.bz = eb.bb * ray.ebz - bparb * (float)ray.nz;
     gv.ne = neb;
     gv.n0 = eb.n0;
-    if (act) {
-      if constexpr (THETA) {
+    if constexpr (THETA) {
+      if (act) {
         fld.vjp_at(g, ray, s, gv, tb);
         tb[12] += (double)eb.alpha;
       }
-      if constexpr (GRID) fld.accumulate_at(g, ray, s, gv, acc, gbn, gc);
     }
+    if constexpr (GRID) fld.accumulate_step(g, ray, s, gv, act, acc, gbn, gc);
   }
-  if constexpr (GRID) fld.flush(acc, gbn, gc);
+  if constexpr (GRID) fld.flush_all(acc, gbn, gc);
 
   if constexpr (THETA) {
     // alpha also enters the per-frequency prefactors: d ln s / d alpha * this lane's share

@@ -393,43 +393,97 @@ struct Grid {
   // contributions are summed in registers and sent on only when the lane leaves
   // the cell: into the workgroup's LDS box when the cell lies in the box around
   // the observer (where all sightlines meet and global atomics would pile up on
-  // the same nodes), else straight to memory with atomic adds.
+  // the same nodes), else to memory with atomic adds.
   struct Acc {
     int64_t base = -1;
     int ix = 0, iy = 0, iz = 0;
     float a[8][5];
-    AdjBox box;  // the workgroup's LDS accumulation box
+    AdjBox box;            // the workgroup's LDS accumulation box
+    float* stage = nullptr;  // this wavefront's staging records in LDS
   };
 
-  __device__ inline void flush(Acc& A, float* gbn, float* gc) const {
-    if (A.base < 0) return;
-    const AdjBox& B = A.box;
-    const int lx = A.ix - B.b0[0], ly = A.iy - B.b0[1], lz = A.iz - B.b0[2];
+  // Adds value `val` of channel ch (0-3 B and n_e, 4 N0) of corner k of cell
+  // (ix, iy, iz) to the box or to memory.
+  __device__ inline void add_corner(const AdjBox& B, int ix, int iy, int iz, int k, int ch,
+                                    float val, float* gbn, float* gc) const {
+    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+    const int lx = ix - B.b0[0], ly = iy - B.b0[1], lz = iz - B.b0[2];
     // the cell's 8 corners all inside the box: unsigned compares take lx >= 0 too
     if (B.lds != nullptr && (unsigned)lx < (unsigned)(B.d[0] - 1) &&
         (unsigned)ly < (unsigned)(B.d[1] - 1) && (unsigned)lz < (unsigned)(B.d[2] - 1)) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int j = ((lz + (k >> 2)) * B.d[1] + (ly + ((k >> 1) & 1))) * B.d[0] + lx + (k & 1);
-#pragma unroll
-        for (int ch = 0; ch < 5; ++ch) atomicAdd(B.lds + 5 * j + ch, A.a[k][ch]);
-      }
-      A.base = -1;
+      atomicAdd(B.lds + 5 * (((lz + dz) * B.d[1] + ly + dy) * B.d[0] + lx + dx) + ch, val);
       return;
     }
-    const int64_t sy = p.n[0], sz = (int64_t)p.n[0] * p.n[1];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int64_t v = A.base + (k & 1) + ((k >> 1) & 1) * sy + (k >> 2) * sz;
-      if (gbn != nullptr) {
-        unsafeAtomicAdd(gbn + 4 * v + 0, A.a[k][0]);
-        unsafeAtomicAdd(gbn + 4 * v + 1, A.a[k][1]);
-        unsafeAtomicAdd(gbn + 4 * v + 2, A.a[k][2]);
-        unsafeAtomicAdd(gbn + 4 * v + 3, A.a[k][3]);
-      }
-      if (gc != nullptr && p.c != nullptr) unsafeAtomicAdd(gc + v, A.a[k][4]);
+    const int64_t v = (int64_t)(ix + dx) + (int64_t)p.n[0] * ((int64_t)(iy + dy) +
+                                                             (int64_t)p.n[1] * (iz + dz));
+    if (ch < 4) {
+      if (gbn != nullptr) unsafeAtomicAdd(gbn + 4 * v + ch, val);
+    } else if (gc != nullptr && p.c != nullptr) {
+      unsafeAtomicAdd(gc + v, val);
     }
-    A.base = -1;
+  }
+
+  // Sends on the accumulators of the lanes with `leave` set (the registers are
+  // left as they are).  Collective over the wavefront: the leaving lanes write
+  // their records to the wavefront's LDS staging area (up to kStageRecs per
+  // round), then every lane takes one value: for B and n_e, lanes 32 h + 4 k +
+  // ch carry channel ch of corner k of record 2 j + h, so that one atomic
+  // instruction covers two records and the four channels of a node (16
+  // contiguous bytes) and the x neighbours share a memory request; for N0,
+  // lanes 8 h + k carry corner k of record 8 j + h.
+  __device__ inline void flush_wave(const Acc& A, bool leave, float* gbn, float* gc) const {
+    const int lane = (int)__lane_id();
+    uint64_t m = __builtin_amdgcn_ballot_w64(leave);
+    while (m != 0) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      const int cnt = min(__popcll(m), kStageRecs);
+      const bool mine = leave && rank < kStageRecs;
+      if (mine) {
+        float4* row = reinterpret_cast<float4*>(A.stage + rank * kStageFloats);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+          const int e = 4 * j;
+          row[j] = make_float4(A.a[e / 5][e % 5], A.a[(e + 1) / 5][(e + 1) % 5],
+                               A.a[(e + 2) / 5][(e + 2) % 5], A.a[(e + 3) / 5][(e + 3) % 5]);
+        }
+        row[10] = make_float4(__int_as_float(A.ix), __int_as_float(A.iy), __int_as_float(A.iz), 0.0f);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (gbn != nullptr) {
+        const int k = (lane >> 2) & 7, ch = lane & 3;
+        for (int r0 = 0; r0 < cnt; r0 += 2) {
+          const int r = r0 + (lane >> 5);
+          if (r < cnt) {
+            const float* rec = A.stage + r * kStageFloats;
+            const float val = rec[5 * k + ch];
+            if (val != 0.0f)
+              add_corner(A.box, __float_as_int(rec[40]), __float_as_int(rec[41]),
+                         __float_as_int(rec[42]), k, ch, val, gbn, gc);
+          }
+        }
+      }
+      if (gc != nullptr && p.c != nullptr) {
+        const int k = lane & 7;
+        for (int r0 = 0; r0 < cnt; r0 += 8) {
+          const int r = r0 + (lane >> 3);
+          if (r < cnt) {
+            const float* rec = A.stage + r * kStageFloats;
+            const float val = rec[5 * k + 4];
+            if (val != 0.0f)
+              add_corner(A.box, __float_as_int(rec[40]), __float_as_int(rec[41]),
+                         __float_as_int(rec[42]), k, 4, val, gbn, gc);
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (mine) leave = false;
+      m = __builtin_amdgcn_ballot_w64(leave);
+    }
   }
 
   // Adds a workgroup's LDS box to memory (after a barrier); nodes of the box
@@ -451,13 +505,16 @@ struct Grid {
     }
   }
 
-  // Adds dL/d(field) at distance s, spread over the cell's 8 corner nodes.
-  __device__ inline void accumulate_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
-                                       Acc& A, float* gbn, float* gc) const {
+  // Adds dL/d(field) at distance s, spread over the cell's 8 corner nodes, for
+  // the lanes with act set.  Collective over the wavefront (every lane calls it
+  // at every step): the lanes that enter a new cell first send on the old one.
+  __device__ inline void accumulate_step(const GeomArgs& g, const Ray& r, double s, const FV& gv,
+                                         bool act, Acc& A, float* gbn, float* gc) const {
     const Cell c = cell_at(g, r, s);
-    if (!c.inside) return;
+    const bool use = act && c.inside;
+    flush_wave(A, use && A.base >= 0 && c.base != A.base, gbn, gc);
+    if (!use) return;
     if (c.base != A.base) {
-      flush(A, gbn, gc);
       A.base = c.base;
       A.ix = c.ix;
       A.iy = c.iy;
@@ -479,6 +536,11 @@ struct Grid {
       A.a[k][3] = fmaf(w, gv.ne, A.a[k][3]);
       A.a[k][4] = fmaf(w, gv.n0, A.a[k][4]);
     }
+  }
+
+  // Sends on every lane's remaining accumulator (collective).
+  __device__ inline void flush_all(const Acc& A, float* gbn, float* gc) const {
+    flush_wave(A, A.base >= 0, gbn, gc);
   }
 };
 

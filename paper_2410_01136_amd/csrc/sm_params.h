@@ -49,8 +49,23 @@ struct GridArgs {
 // Box of grid nodes in which one workgroup of the grid adjoint accumulates its
 // gradients in LDS (5 floats per node, x fastest) before adding them to memory
 // once; nodes outside it get global atomic adds.
-// Largest LDS box of one workgroup: 8000 nodes x 5 floats = 160,000 bytes.
-constexpr int kAdjBoxNodesMax = 8000;
+//
+// Each wavefront also has a staging area in LDS for the cell records (8 corners
+// x 5 channels plus the cell index) of the lanes that leave their cell in one
+// step, from which the whole wavefront adds them out.
+constexpr int kStageRecs = 16;    // records per wavefront and round
+constexpr int kStageFloats = 44;  // 40 values, 3 cell indices, 1 pad (16-byte rows)
+constexpr int kStageBytesPerBlock = 4 * kStageRecs * kStageFloats * 4;  // 4 wavefronts
+// LDS of a CU, and what the kernel's static LDS takes besides the box and the
+// staging areas.
+constexpr int kAdjLdsBytes = 160 * 1024;
+constexpr int kAdjStaticLds = 1024;
+// Box nodes of a workgroup that has 1/per_cu of the LDS, a multiple of 4 (so
+// the staging areas after the box stay 16-byte aligned).
+constexpr int adj_box_cap(int per_cu) {
+  return ((kAdjLdsBytes / per_cu - kAdjStaticLds - kStageBytesPerBlock) / 20) & ~3;
+}
+constexpr int kAdjBoxNodesMax = adj_box_cap(1);
 
 struct AdjBox {
   float* lds = nullptr;  // [d[2]][d[1]][d[0]][5], or nullptr (no box)

@@ -153,7 +153,7 @@ def test_lane_setting(sm):
     assert sm.get_lanes_per_ray(0, 0, 10 ** 7) == 4
     assert sm.get_lanes_per_ray(0, 1, 786432) == 16
     assert sm.get_lanes_per_ray(0, 1, 3072) == 64
-    assert sm.get_lanes_per_ray(1, 1, 49152) == 1
+    assert sm.get_lanes_per_ray(1, 1, 49152) == 4
     assert sm.get_lanes_per_ray(1, 0, 49152) == 4
     assert sm.get_lanes_per_ray(2, 0, 10 ** 7) == 1
 

@@ -81,11 +81,13 @@ def _grid(orc, n=(17, 17, 9), with_c=True):
     return bn, (reg_c if with_c else None)
 
 
-@pytest.mark.parametrize("S", [1, 16])
+# with a grid gradient, S > 1 splits each sightline into S contiguous pieces:
+# 83 steps leave a short last piece at S = 4 and 16, and empty pieces at 16 and 64
+@pytest.mark.parametrize("S", [1, 4, 16, 64])
 @pytest.mark.parametrize("with_c", [True, False])
 def test_grid_gradient(sm, orc, lanes, S, with_c):
     import torch
-    g = I.geometry("C2", nside=8, n_steps=80, freqs_hz=(1.0e9, 1.4e9))
+    g = I.geometry("C2", nside=8, n_steps=83, freqs_hz=(1.0e9, 1.4e9))
     bn, c = _grid(orc, with_c=with_c)
     dm = I.cotangents((2, 3, g.npix), seed=23)
     lanes(sm.FIELD_GRID, S)
@@ -174,7 +176,7 @@ def test_c2_full_size_theta_gradient(sm, orc):
     assert_theta_close(dth, ref, I.THETA0, "C2 full")
 
 
-@pytest.mark.parametrize("S", [1, 4])
+@pytest.mark.parametrize("S", [1, 4, 16])
 def test_grid_gradient_sub_box(sm, orc, lanes, S):
     # grid box smaller than the geometry box, fewer nodes than the LDS box on z
     import torch
@@ -199,3 +201,34 @@ def test_grid_gradient_sub_box(sm, orc, lanes, S):
         rel = np.linalg.norm(a - b) / np.linalg.norm(b)
         print(f"sub-box grid S={S}: rel L2 {rel:.2e}", flush=True)
         assert rel <= 1e-3
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("S", [0, 1])
+def test_c2_full_size_grid_gradient(sm, orc, lanes, S):
+    """C2 grid adjoint at full size (N_side 64, 768 steps, B and n_e on 128^3
+    nodes sampled from theta0, analytic N0) in the built-in launch shape (S = 0)
+    and with one lane per sightline, vs the oracle's gradient."""
+    import torch
+    g = I.geometry("C2")
+    reg_bn, _ = orc.sample_model16(I.THETA0, (128, 128, 128), I.BOX_LO, I.BOX_HI)
+    dm = I.cotangents((1, 3, g.npix), seed=27)
+    if S:
+        lanes(sm.FIELD_GRID, S)
+    bn_t = torch.from_numpy(reg_bn).cuda()
+    field = sm.grid(I.THETA0, bn_t, None, I.BOX_LO, I.BOX_HI)
+    geom = sm.geom_from(g)
+    ws = sm.alloc_workspace(geom, field)
+    sm.forward(geom, field, ws=ws)
+    dbn = torch.zeros_like(bn_t)
+    sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws, want_theta=False, dgrid_bn=dbn)
+    torch.cuda.synchronize()
+    ofield = orc.Field(orc.GRID, I.THETA0, grid_bn=reg_bn, grid_c=None, grid_lo=I.BOX_LO,
+                       grid_hi=I.BOX_HI)
+    _, rbn, _ = orc.adjoint(oracle_geom(orc, g), ofield, dm.astype(np.float64), want_grid=True)
+    a = dbn.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(a - rbn) / np.linalg.norm(rbn)
+    cos = (a * rbn).sum() / (np.linalg.norm(a) * np.linalg.norm(rbn))
+    print(f"C2 full grid S={sm.get_lanes_per_ray(1, sm.FIELD_GRID, g.npix)}: rel L2 {rel:.2e}, "
+          f"1-cos {1 - cos:.2e}", flush=True)
+    assert rel <= 1e-3 and cos >= 1 - 1e-6
