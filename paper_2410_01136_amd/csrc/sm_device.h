@@ -411,7 +411,10 @@ struct Grid {
     // the cell's 8 corners all inside the box: unsigned compares take lx >= 0 too
     if (B.lds != nullptr && (unsigned)lx < (unsigned)(B.d[0] - 1) &&
         (unsigned)ly < (unsigned)(B.d[1] - 1) && (unsigned)lz < (unsigned)(B.d[2] - 1)) {
-      atomicAdd(B.lds + 5 * (((lz + dz) * B.d[1] + ly + dy) * B.d[0] + lx + dx) + ch, val);
+      // the box lives in LDS: an LDS atomic rather than a flat one
+      using lds_float = __attribute__((address_space(3))) float;
+      lds_float* l = (lds_float*)(B.lds + 5 * (((lz + dz) * B.d[1] + ly + dy) * B.d[0] + lx + dx) + ch);
+      __hip_atomic_fetch_add(l, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       return;
     }
     const int64_t v = (int64_t)(ix + dx) + (int64_t)p.n[0] * ((int64_t)(iy + dy) +
