@@ -46,7 +46,8 @@ class _Field(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("theta", ctypes.c_double * NPARAM),
                 ("grid_n", ctypes.c_int32 * 3), ("grid_lo", ctypes.c_double * 3),
                 ("grid_hi", ctypes.c_double * 3),
-                ("grid_bn", ctypes.c_void_p), ("grid_c", ctypes.c_void_p)]
+                ("grid_bn", ctypes.c_void_p), ("grid_c", ctypes.c_void_p),
+                ("te_k", ctypes.c_double)]
 
 
 _lib = None
@@ -78,6 +79,8 @@ def _load():
     lib.or_k_rm.restype = ctypes.c_double
     lib.or_rj.argtypes = [ctypes.c_double]
     lib.or_rj.restype = ctypes.c_double
+    lib.or_kff.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.or_kff.restype = ctypes.c_double
     lib.or_fields.argtypes = [fp, dp, dp, dp, dp]
     lib.or_sample_model16.argtypes = [dp, ctypes.POINTER(ctypes.c_int32), dp, dp,
                                       ctypes.c_void_p, ctypes.c_void_p]
@@ -112,9 +115,11 @@ def make_geom(nside, n_steps, freqs_hz, r_obs=(-8.5, 0.0, 0.0), r_max=math.inf,
 class Field:
     """Field description; keeps the grid arrays alive while in use."""
 
-    def __init__(self, kind, theta, grid_bn=None, grid_c=None, grid_lo=None, grid_hi=None):
+    def __init__(self, kind, theta, grid_bn=None, grid_c=None, grid_lo=None, grid_hi=None,
+                 te_k=0.0):
         self.s = _Field()
         self.s.kind = int(kind)
+        self.s.te_k = float(te_k)  # > 0: free-free emission and absorption at T_e [K]
         th = np.asarray(theta, dtype=np.float64)
         if th.shape != (NPARAM,):
             raise ValueError("theta must have 16 entries")
@@ -243,6 +248,11 @@ def k_rm():
 
 def rayleigh_jeans(nu):
     return _load().or_rj(nu)
+
+
+def kff(nu, te_k):
+    """Free-free optical depth per pc per (n_e / cm^-3)^2."""
+    return _load().or_kff(nu, te_k)
 
 
 def num_threads():

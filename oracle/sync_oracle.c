@@ -33,6 +33,18 @@
  *     own segment (second-order midpoint prefix).
  *   - Units: cgs inside the physics (B in gauss, lengths in cm, N0 and n_e in
  *     cm^-3), positions in kpc, fields handed in as micro-gauss.
+ *
+ * Free-free emission and absorption (named as future work in Sec. 5; the paper
+ * gives no formulas, so this is a reading):
+ *   - opacity of a fully ionised hydrogen plasma at electron temperature T_e
+ *     in the approximation of Mezger & Henderson (1967, ApJ 147, 471):
+ *     d tau = 0.08235 T_e^-1.35 (nu / GHz)^-2.1 n_e^2 dl, dl in pc, n_e in cm^-3;
+ *   - the thermal source function in the Rayleigh-Jeans limit is T_e, so a
+ *     segment adds T_e d tau to the brightness temperature of I;
+ *   - everything a segment emits (synchrotron I, Q, U and free-free) reaches the
+ *     observer attenuated by e^-tau, tau the optical depth from the observer to
+ *     the segment's midpoint: all earlier segments plus half of its own (the
+ *     same midpoint prefix as the rotation measure).
  */
 #include <math.h>
 #include <stdint.h>
@@ -76,6 +88,7 @@ typedef struct {
   double grid_hi[3];
   const float* grid_bn; /* [nz][ny][nx][4] = Bx, By, Bz [uG], n_e [cm^-3]   */
   const float* grid_c;  /* [nz][ny][nx] N0 [cm^-3], or NULL -> analytic N0  */
+  double te_k;          /* electron temperature [K]; > 0 adds free-free      */
 } or_field;
 
 /* ========================================================================== */
@@ -483,6 +496,10 @@ double or_k_rm(void) { return pow(OR_QE, 3) / (2.0 * OR_PI * OR_ME * OR_ME * pow
 /* Rayleigh-Jeans conversion of a specific intensity to Kelvin. */
 double or_rj(double nu) { return OR_C * OR_C / (2.0 * OR_KB * nu * nu); }
 
+/* Free-free optical depth per pc per (n_e / cm^-3)^2 at frequency nu [Hz] and
+   electron temperature te [K] (Mezger & Henderson 1967 approximation). */
+double or_kff(double nu, double te) { return 0.08235 * pow(te, -1.35) * pow(nu / 1e9, -2.1); }
+
 /* ========================================================================== */
 /* One sightline                                                              */
 /* ========================================================================== */
@@ -569,13 +586,16 @@ static void or_local_eval(const or_field* f, const or_ray* ray, const double r[3
 
 /* Forward march of one pixel: out[f][3] = T_I, T_Q, T_U [K]; returns the
    total Faraday depth sum of the segment increments [rad cm^-2]. */
-static double or_march_source(const or_geom* g, const or_source* src, double alpha, int64_t p,
-                              double* out) {
+static double or_march_source(const or_geom* g, const or_source* src, double alpha, double te,
+                              int64_t p, double* out) {
   or_ray ray;
   or_make_ray(g, p, &ray);
   const double krm = or_k_rm();
+  const double dpc = ray.dkpc * 1e3;
   double I[OR_MAX_FREQ] = {0}, Q[OR_MAX_FREQ] = {0}, U[OR_MAX_FREQ] = {0};
-  double rm_before = 0.0; /* integral of n_e B_LOS over all earlier segments */
+  double F[OR_MAX_FREQ] = {0}; /* free-free: sum of e^-tau n_e^2 dl */
+  double rm_before = 0.0;      /* integral of n_e B_LOS over all earlier segments */
+  double em_before = 0.0;      /* emission measure of all earlier segments [pc cm^-6] */
   for (int n = 0; n < g->n_steps; ++n) {
     double r[3];
     or_midpoint(g, &ray, n, r);
@@ -586,20 +606,26 @@ static double or_march_source(const or_geom* g, const or_source* src, double alp
     const double seg = q.ne * q.blos * ray.dcm;
     const double RM = krm * (rm_before + 0.5 * seg);
     rm_before += seg;
+    const double em_seg = te > 0.0 ? q.ne * q.ne * dpc : 0.0;
+    const double EM = em_before + 0.5 * em_seg;
+    em_before += em_seg;
     for (int k = 0; k < g->n_freq; ++k) {
       const double nu = g->freq_hz[k];
       const double lam = OR_C / nu;
+      const double att = te > 0.0 ? exp(-or_kff(nu, te) * EM) : 1.0;
       const double jI = or_j_I(alpha, nu, q.Bt, q.n0);
       const double jP = or_j_P(alpha, nu, q.Bt, q.n0);
       const double chi = RM * lam * lam + q.chi0;
-      I[k] += jI * ray.dcm;
-      Q[k] += jP * cos(2.0 * chi) * ray.dcm;
-      U[k] += jP * sin(2.0 * chi) * ray.dcm;
+      I[k] += att * jI * ray.dcm;
+      Q[k] += att * jP * cos(2.0 * chi) * ray.dcm;
+      U[k] += att * jP * sin(2.0 * chi) * ray.dcm;
+      F[k] += att * em_seg;
     }
   }
   for (int k = 0; k < g->n_freq; ++k) {
     const double rj = or_rj(g->freq_hz[k]);
-    out[3 * k + 0] = rj * I[k];
+    const double tff = te > 0.0 ? te * or_kff(g->freq_hz[k], te) * F[k] : 0.0;
+    out[3 * k + 0] = rj * I[k] + tff;
     out[3 * k + 1] = rj * Q[k];
     out[3 * k + 2] = rj * U[k];
   }
@@ -608,7 +634,7 @@ static double or_march_source(const or_geom* g, const or_source* src, double alp
 
 static double or_march_pixel(const or_geom* g, const or_field* f, int64_t p, double* out) {
   const or_source src = {f, NULL};
-  return or_march_source(g, &src, f->theta[12], p, out);
+  return or_march_source(g, &src, f->theta[12], f->te_k, p, out);
 }
 
 static int or_check(const or_geom* g, const or_field* f) {
@@ -618,6 +644,7 @@ static int or_check(const or_geom* g, const or_field* f) {
   if (f->kind == OR_GRID && (f->grid_bn == NULL || f->grid_n[0] < 2 || f->grid_n[1] < 2 ||
                              f->grid_n[2] < 2))
     return -1;
+  if (!(f->te_k >= 0.0) || isinf(f->te_k)) return -1;
   return 0;
 }
 
@@ -675,7 +702,7 @@ int or_forward_tabulated(const or_geom* g, double alpha, const int64_t* pix, int
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t i = 0; i < n; ++i) {
     const or_source src = {NULL, fields + i * (int64_t)g->n_steps * 5};
-    or_march_source(g, &src, alpha, pix[i], out + i * 3 * g->n_freq);
+    or_march_source(g, &src, alpha, 0.0, pix[i], out + i * 3 * g->n_freq);
   }
   return 0;
 }
@@ -694,11 +721,16 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
   const int N = g->n_steps;
   const double alpha = f->theta[12];
   const double krm = or_k_rm();
+  const double te = f->te_k;
+  const double dpc = ray.dkpc * 1e3;
   or_local* q = (or_local*)malloc(sizeof(or_local) * (size_t)N);
   double* RM = (double*)malloc(sizeof(double) * (size_t)N);
   double* rmb = (double*)malloc(sizeof(double) * (size_t)N); /* dL/dRM_n */
+  double* EM = (double*)malloc(sizeof(double) * (size_t)N);  /* emission measure to midpoint n */
+  double* emb = (double*)malloc(sizeof(double) * (size_t)N); /* dL/dEM_n */
+  double* ffb = (double*)malloc(sizeof(double) * (size_t)N); /* dL/d(n_e^2 dl) of its own emission */
   /* forward sweep, keeping the per-step quantities */
-  double before = 0.0;
+  double before = 0.0, em_before = 0.0;
   for (int n = 0; n < N; ++n) {
     double r[3];
     or_midpoint(g, &ray, n, r);
@@ -706,36 +738,55 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
     const double seg = q[n].ne * q[n].blos * ray.dcm;
     RM[n] = krm * (before + 0.5 * seg);
     before += seg;
+    const double em_seg = te > 0.0 ? q[n].ne * q[n].ne * dpc : 0.0;
+    EM[n] = em_before + 0.5 * em_seg;
+    em_before += em_seg;
   }
-  /* local cotangents of j_I, j_P, chi at every step; dL/dRM_n */
+  /* local cotangents of j_I, j_P, chi at every step; dL/dRM_n, dL/dEM_n */
   double* jIb = (double*)calloc((size_t)N * OR_MAX_FREQ, sizeof(double));
   double* jPb = (double*)calloc((size_t)N * OR_MAX_FREQ, sizeof(double));
   double* chi0b = (double*)calloc((size_t)N, sizeof(double));
   for (int n = 0; n < N; ++n) {
     rmb[n] = 0.0;
+    emb[n] = 0.0;
+    ffb[n] = 0.0;
+    const double em_seg = te > 0.0 ? q[n].ne * q[n].ne * dpc : 0.0;
     for (int k = 0; k < g->n_freq; ++k) {
       const double nu = g->freq_hz[k];
       const double lam = OR_C / nu;
       const double rj = or_rj(nu);
+      const double kff = te > 0.0 ? or_kff(nu, te) : 0.0;
+      const double att = te > 0.0 ? exp(-kff * EM[n]) : 1.0;
+      const double jI = or_j_I(alpha, nu, q[n].Bt, q[n].n0);
       const double jP = or_j_P(alpha, nu, q[n].Bt, q[n].n0);
       const double chi = RM[n] * lam * lam + q[n].chi0;
       const double gI = dm[3 * k + 0] * rj * ray.dcm;
       const double gQ = dm[3 * k + 1] * rj * ray.dcm;
       const double gU = dm[3 * k + 2] * rj * ray.dcm;
-      jIb[n * OR_MAX_FREQ + k] = gI;
-      jPb[n * OR_MAX_FREQ + k] = gQ * cos(2.0 * chi) + gU * sin(2.0 * chi);
-      const double chib = jP * (-2.0 * gQ * sin(2.0 * chi) + 2.0 * gU * cos(2.0 * chi));
+      const double pol = gQ * cos(2.0 * chi) + gU * sin(2.0 * chi);
+      jIb[n * OR_MAX_FREQ + k] = gI * att;
+      jPb[n * OR_MAX_FREQ + k] = pol * att;
+      const double chib = att * jP * (-2.0 * gQ * sin(2.0 * chi) + 2.0 * gU * cos(2.0 * chi));
       chi0b[n] += chib;
       rmb[n] += chib * lam * lam;
+      if (te > 0.0) {
+        /* term_k = att (gI jI + jP pol + dI te kff em_seg); d att / d EM = -kff att */
+        const double ffI = dm[3 * k + 0] * te * kff;
+        emb[n] += -kff * att * (gI * jI + jP * pol + ffI * em_seg);
+        ffb[n] += ffI * att;
+      }
     }
   }
-  /* RM_n = krm (sum_{m<n} seg_m + seg_n / 2): dL/dseg_m */
-  double suffix = 0.0; /* sum over n > m of dL/dRM_n */
+  /* RM_n = krm (sum_{m<n} seg_m + seg_n / 2): dL/dseg_m; the same for EM */
+  double suffix = 0.0;    /* sum over n > m of dL/dRM_n */
+  double em_suffix = 0.0; /* sum over n > m of dL/dEM_n */
   for (int n = N - 1; n >= 0; --n) {
     const double segb = krm * (suffix + 0.5 * rmb[n]);
     suffix += rmb[n];
-    /* seg = ne * blos * dcm */
-    const double neb_seg = segb * q[n].blos * ray.dcm;
+    const double em_segb = ffb[n] + em_suffix + 0.5 * emb[n];
+    em_suffix += emb[n];
+    /* seg = ne * blos * dcm; em_seg = ne^2 dpc */
+    const double neb_seg = segb * q[n].blos * ray.dcm + (te > 0.0 ? em_segb * 2.0 * q[n].ne * dpc : 0.0);
     const double blosb = segb * q[n].ne * ray.dcm;
     /* j_I, j_P depend on Bt, n0 (and alpha); chi0 = atan2(num, den) */
     double Btb = 0.0, n0b = 0.0, ab = 0.0;
@@ -802,6 +853,9 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
   free(q);
   free(RM);
   free(rmb);
+  free(EM);
+  free(emb);
+  free(ffb);
   free(jIb);
   free(jPb);
   free(chi0b);
