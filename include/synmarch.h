@@ -110,11 +110,24 @@ typedef struct syn_field {
   const float* grid_bn;         /* (device)                                   */
   const float* grid_c;          /* (device) or NULL                           */
   const void* mlp;              /* (device)                                   */
+  double te_k;                  /* thermal electron temperature [K]; 0 = off  */
 } syn_field;
+/* Free-free emission and absorption (te_k > 0; the paper names both as future
+   work in Sec. 5 and gives no formulas, so this follows the textbook radio
+   treatment): the thermal electrons n_e, taken as a fully ionised hydrogen
+   plasma at temperature te_k, have the optical depth
+     d tau = 0.08235 te_k^-1.35 (nu / GHz)^-2.1 n_e^2 dl   (dl in pc; Mezger &
+   Henderson 1967), emit d T_I = te_k d tau (Rayleigh-Jeans source function),
+   and attenuate everything a segment emits (I, Q, U) by e^-tau, tau being the
+   depth from the observer to the segment's midpoint (earlier segments plus
+   half of its own, as for the rotation measure).  Not available for the MLP
+   surrogate (SYN_EUNSUPPORTED) or in batch plans; te_k must be finite and
+   >= 0 (SYN_EINVAL).  Gradients flow through n_e; te_k itself gets none. */
 
 /* Bytes of workspace syn_forward needs; with_adjoint != 0 adds what the
    matching syn_adjoint reads (the Faraday sum of every sightline, 8 B per
-   pixel, plus per-block gradient partials).  Returns 0 for invalid input. */
+   pixel, with free-free also its emission measure, 8 B per pixel, plus
+   per-block gradient partials).  Returns 0 for invalid input. */
 size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t with_adjoint);
 
 /* Forward march: maps (device) float [n_freq][3][npix] in K.  ws (device) may

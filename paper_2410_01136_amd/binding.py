@@ -39,7 +39,8 @@ class SynField(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("theta", ctypes.c_double * NPARAM),
                 ("grid_n", ctypes.c_int32 * 3), ("grid_lo_kpc", ctypes.c_double * 3),
                 ("grid_hi_kpc", ctypes.c_double * 3), ("grid_bn", ctypes.c_void_p),
-                ("grid_c", ctypes.c_void_p), ("mlp", ctypes.c_void_p)]
+                ("grid_c", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
+                ("te_k", ctypes.c_double)]
 
 
 class SynBatchDesc(ctypes.Structure):
@@ -145,9 +146,10 @@ class Field:
 
     def __init__(self, kind: int, theta, grid_bn: Optional[torch.Tensor] = None,
                  grid_c: Optional[torch.Tensor] = None, lo=None, hi=None,
-                 mlp: Optional[torch.Tensor] = None):
+                 mlp: Optional[torch.Tensor] = None, te_k: float = 0.0):
         self.s = SynField()
         self.s.kind = int(kind)
+        self.s.te_k = float(te_k)  # > 0: free-free emission and absorption at T_e [K]
         th = np.asarray(theta, dtype=np.float64).reshape(-1)
         if th.size != NPARAM:
             raise ValueError("theta must have 16 entries")
@@ -177,7 +179,12 @@ class Field:
 
     def with_theta(self, theta) -> "Field":
         return Field(self.s.kind, theta, self.grid_bn, self.grid_c,
-                     self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp)
+                     self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, self.s.te_k)
+
+    def with_te(self, te_k: float) -> "Field":
+        """The same field with free-free emission and absorption at T_e = te_k [K]."""
+        return Field(self.s.kind, self.theta, self.grid_bn, self.grid_c,
+                     self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, te_k)
 
 
 def model16(theta) -> Field:

@@ -167,6 +167,11 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
     return fail(SYN_EINVAL, "alpha (theta[12]) must exceed 1/3, the pole of Gamma(alpha/4 - 1/12)");
   memset(fp, 0, sizeof(*fp));
   fp->kind = f->kind;
+  if (!(isfinite(f->te_k) && f->te_k >= 0.0))
+    return fail(SYN_EINVAL, "te_k must be finite and >= 0");
+  fp->ff = f->te_k > 0.0;
+  if (fp->ff && f->kind == SYN_FIELD_MLP)
+    return fail(SYN_EUNSUPPORTED, "free-free (te_k > 0) is not available for the MLP surrogate");
   switch (f->kind) {
     case SYN_FIELD_MODEL16: {
       syn_status s = check_m16_theta(f->theta);
@@ -267,8 +272,11 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
   }
 }
 
-// Per-frequency prefactors of the sums (Eqs. ji, jp, rm and Rayleigh-Jeans).
-void freq_args(const syn_geom* g, double alpha, sm::FreqArgs* fa) {
+// Per-frequency prefactors of the sums (Eqs. ji, jp, rm and Rayleigh-Jeans),
+// and with te_k > 0 those of free-free absorption and emission: optical depth
+// 0.08235 T_e^-1.35 (nu / GHz)^-2.1 per pc per (n_e / cm^-3)^2 (Mezger &
+// Henderson 1967), source function T_e (Rayleigh-Jeans).
+void freq_args(const syn_geom* g, double alpha, double te_k, sm::FreqArgs* fa) {
   memset(fa, 0, sizeof(*fa));
   fa->n_freq = g->n_freq;
   const double krm = kQe * kQe * kQe / (2.0 * kPi * kMe * kMe * kC * kC * kC * kC);
@@ -289,6 +297,11 @@ void freq_args(const syn_geom* g, double alpha, sm::FreqArgs* fa) {
     fa->kappa[f] = krm * 1e-6 * kKpcCm * lam * lam / kPi;       // turns of 2 RM lambda^2
     fa->dlnsI[f] = -0.5 * log(base) + 0.5 * log(2.0) - 1.0 / (alpha + 1.0) + dig + 0.5 * log(1e-6);
     fa->dlnsP[f] = fa->dlnsI[f] + 1.0 / (alpha + 1.0) - 1.0 / (alpha + 7.0 / 3.0);
+    if (te_k > 0.0) {
+      const double kff_kpc = 1e3 * 0.08235 * pow(te_k, -1.35) * pow(nu / 1e9, -2.1);
+      fa->kffl2[f] = kff_kpc / log(2.0);
+      fa->tff[f] = te_k * kff_kpc;
+    }
   }
 }
 
@@ -301,9 +314,12 @@ sm::EmitArgs emit_args(double alpha) {
 
 size_t ws_phi_bytes(int64_t npix) { return (size_t)((npix * 8 + 255) / 256 * 256); }
 
-size_t ws_bytes_for(int64_t npix, bool adjoint) {
+// Workspace: the Faraday sum of every sightline, with free-free also its
+// emission-measure sum, then the per-block theta partials.
+size_t ws_bytes_for(int64_t npix, bool adjoint, bool ff) {
   if (!adjoint) return 0;
-  return ws_phi_bytes(npix) + (size_t)sm::march_blocks(npix, 64) * sm::kNParam * sizeof(double);
+  return ws_phi_bytes(npix) * (ff ? 2 : 1) +
+         (size_t)sm::march_blocks(npix, 64) * sm::kNParam * sizeof(double);
 }
 
 }  // namespace
@@ -319,7 +335,7 @@ size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t
   sm::FieldPack fp;
   if (check_geom(geom, &ga) != SYN_OK) return 0;
   if (check_field(field, &fp, false) != SYN_OK) return 0;
-  return ws_bytes_for(ga.npix, with_adjoint != 0);
+  return ws_bytes_for(ga.npix, with_adjoint != 0, fp.ff);
 }
 
 // Whether the forward may read this grid with 32-bit buffer offsets: the float4
@@ -355,13 +371,15 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
   if (s != SYN_OK) return s;
   if (maps == nullptr || ((uintptr_t)maps & 3) != 0) return fail(SYN_EINVAL, "maps must be a 4-byte aligned device pointer");
   double* phi_end = nullptr;
+  double* em_end = nullptr;
   if (ws != nullptr) {
-    if (ws_bytes < ws_bytes_for(ga.npix, true) || ((uintptr_t)ws & 7) != 0)
+    if (ws_bytes < ws_bytes_for(ga.npix, true, fp.ff) || ((uintptr_t)ws & 7) != 0)
       return fail(SYN_EWORKSPACE, "workspace smaller than syn_workspace_bytes(...,1) or misaligned");
     phi_end = static_cast<double*>(ws);
+    if (fp.ff) em_end = reinterpret_cast<double*>(static_cast<char*>(ws) + ws_phi_bytes(ga.npix));
   }
   sm::FreqArgs fa;
-  freq_args(geom, field->theta[12], &fa);
+  freq_args(geom, field->theta[12], field->te_k, &fa);
   hipError_t e;
   if (field->kind == SYN_FIELD_MLP) {
     e = sm::launch_forward_mlp(ga, fa, emit_args(field->theta[12]), fp.mlp, maps, phi_end, stream);
@@ -372,12 +390,14 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
       // automatic: shared cell reads pay off once there are enough wavefronts
       // to hide their longer dependency chain (measured: N_side 256 gains 1.3x,
       // N_side 64 loses 10%)
-      const bool shared = mode == 3 || (mode == 0 && ga.npix >= (1 << 18));
+      // (free-free is built for the per-lane reads only)
+      const bool shared = !fp.ff && (mode == 3 || (mode == 0 && ga.npix >= (1 << 18)));
       fp.grid_path = (mode == 1 || !grid_buffer_ok(ga, fp.grid)) ? sm::kGridGlobal
                      : shared                                    ? sm::kGridShared
                                                                  : sm::kGridBuffer;
     }
-    e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, stream);
+    e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, em_end,
+                           stream);
   }
   if (e != hipSuccess) return hip_fail(e, "forward launch");
   return SYN_OK;
@@ -393,7 +413,7 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   s = check_field(field, &fp, true);
   if (s != SYN_OK) return s;
   if (dmaps == nullptr || ((uintptr_t)dmaps & 3) != 0) return fail(SYN_EINVAL, "dmaps must be a 4-byte aligned device pointer");
-  if (ws == nullptr || ws_bytes < ws_bytes_for(ga.npix, true) || ((uintptr_t)ws & 7) != 0)
+  if (ws == nullptr || ws_bytes < ws_bytes_for(ga.npix, true, fp.ff) || ((uintptr_t)ws & 7) != 0)
     return fail(SYN_EWORKSPACE, "adjoint needs the workspace of the matching forward");
   if (field->kind != SYN_FIELD_GRID && (dgrid_bn != nullptr || dgrid_c != nullptr))
     return fail(SYN_EINVAL, "grid gradients need a GRID field");
@@ -404,12 +424,14 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   if (dtheta == nullptr && dgrid_bn == nullptr && dgrid_c == nullptr) return SYN_OK;
   if (dtheta != nullptr && ((uintptr_t)dtheta & 7) != 0) return fail(SYN_EINVAL, "dtheta misaligned");
   sm::FreqArgs fa;
-  freq_args(geom, field->theta[12], &fa);
+  freq_args(geom, field->theta[12], field->te_k, &fa);
   const int S = lanes_for(SYN_KERNEL_ADJOINT, field->kind, ga.npix);
-  double* phi_end = static_cast<double*>(ws);
-  double* partials = reinterpret_cast<double*>(static_cast<char*>(ws) + ws_phi_bytes(ga.npix));
+  char* w = static_cast<char*>(ws);
+  double* phi_end = reinterpret_cast<double*>(w);
+  double* em_end = fp.ff ? reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix)) : nullptr;
+  double* partials = reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix) * (fp.ff ? 2 : 1));
   hipError_t e = sm::launch_adjoint(ga, fa, emit_args(field->theta[12]), fp, S, dmaps, phi_end,
-                                    partials, dtheta, dgrid_bn, dgrid_c, stream);
+                                    em_end, partials, dtheta, dgrid_bn, dgrid_c, stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return SYN_OK;
 }
@@ -570,7 +592,7 @@ syn_status fill_set_field(sm::BatchSet* B, const syn_geom* g, int32_t kind, cons
   B->m = fp.m16;
   B->w = fp.wmap;
   sm::FreqArgs fa;
-  freq_args(g, f.theta[12], &fa);
+  freq_args(g, f.theta[12], 0.0, &fa);  // batch plans march without free-free
   B->fa.n_freq = 1;
   B->fa.sI[0] = fa.sI[0];
   B->fa.sP[0] = fa.sP[0];

@@ -18,6 +18,7 @@
 namespace sm {
 
 constexpr double kTwoPi = 6.283185307179586;
+constexpr double kLn2 = 0.6931471805599453;
 
 // Map addressing: element (f, stokes, ring) of a map set sits at
 // map[(3 f + stokes) * stride + off + ring].
@@ -46,18 +47,28 @@ constexpr bool zero_beyond_path() {
 // loops need no test), 4 and 16 upper bounds.
 constexpr bool exact_freqs(int MF) { return MF == 1 || MF == 3; }
 
-template <class F, int S, int MF, class FA>
+// Free-free emission and absorption (FF): every segment's emission reaches
+// the observer attenuated by e^-tau_f, tau_f = kff_f dkpc EM with EM the sum of
+// n_e^2 over the earlier segments plus half of this one (a second prefix sum,
+// carried like the Faraday sum), and the segment adds T_e dtau_f to I.
+template <class F, int S, int MF, bool FF = false, class FA>
 __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, float* __restrict__ maps,
-                                MapAddr ma, double* __restrict__ phi_end) {
+                                MapAddr ma, double* __restrict__ phi_end,
+                                double* __restrict__ em_end = nullptr) {
   const Ray ray = make_ray(g, q);
   const auto rctx = fld.ray_ctx(g, ray);
   constexpr bool zero_beyond = zero_beyond_path<F>();
+  constexpr int MFF = FF ? MF : 1;
   double carry = 0.0;  // Faraday sum (n_e B_par, uG cm^-3) of all earlier chunks
+  double emc = 0.0;    // FF: sum of n_e^2 (cm^-6) of all earlier chunks
   double accI = 0.0;
   double accQ[MF], accU[MF];
+  double accIf[MFF], accF[MFF];  // FF: attenuated synchrotron I and free-free sums
 #pragma unroll
   for (int f = 0; f < MF; ++f) accQ[f] = accU[f] = 0.0;
+#pragma unroll
+  for (int f = 0; f < MFF; ++f) accIf[f] = accF[f] = 0.0;
 
   for (int c0 = 0; c0 < g.n_steps; c0 += S) {
     const int n = c0 + sub;
@@ -77,17 +88,39 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       psi = carry + incl - 0.5 * cn;
       carry += group_last<S>(incl);
     }
+    float w = 0.0f, emd = 0.0f;  // FF: n_e^2 of this segment, emission measure * dkpc
+    if constexpr (FF) {
+      w = (zero_beyond || act) ? v.ne * v.ne : 0.0f;
+      double em;
+      if constexpr (S == 1) {
+        em = emc + 0.5 * (double)w;
+        emc += (double)w;
+      } else {
+        const double incl = group_inclusive_scan<S>((double)w, sub);
+        em = emc + incl - 0.5 * (double)w;
+        emc += group_last<S>(incl);
+      }
+      emd = (float)(em * ray.dkpc);
+    }
     Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
     if (!zero_beyond && !act) e.u = e.zr = e.zi = 0.0f;
-    accI += (double)e.u;
+    if constexpr (!FF) accI += (double)e.u;
     const double psid = psi * ray.dkpc;
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
       if (exact_freqs(MF) || f < fa.n_freq) {
         float sn, cs;
         sincos_turns(psid * fa.kappa[f], &sn, &cs);  // turns of 2 RM lambda^2
-        accQ[f] += (double)(e.zr * cs - e.zi * sn);
-        accU[f] += (double)(e.zr * sn + e.zi * cs);
+        float zr = e.zr, zi = e.zi;
+        if constexpr (FF) {
+          const float att = exp2f(-(float)fa.kffl2[f] * emd);
+          zr *= att;
+          zi *= att;
+          accIf[f] += (double)(att * e.u);
+          accF[f] += (double)(att * w);
+        }
+        accQ[f] += (double)(zr * cs - zi * sn);
+        accU[f] += (double)(zr * sn + zi * cs);
       }
     }
   }
@@ -99,17 +132,31 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       accQ[f] = group_sum<S>(accQ[f]);
       accU[f] = group_sum<S>(accU[f]);
     }
+    if constexpr (FF) {
+#pragma unroll
+      for (int f = 0; f < MF; ++f) {
+        accIf[f] = group_sum<S>(accIf[f]);
+        accF[f] = group_sum<S>(accF[f]);
+      }
+    }
   }
   if (valid && sub == 0) {
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
       if (exact_freqs(MF) || f < fa.n_freq) {
-        maps[ma.at(f, 0, ray.ring)] = (float)(fa.sI[f] * ray.dkpc * accI);
+        double tI;
+        if constexpr (FF)
+          tI = fa.sI[f] * ray.dkpc * accIf[f] + fa.tff[f] * ray.dkpc * accF[f];
+        else
+          tI = fa.sI[f] * ray.dkpc * accI;
+        maps[ma.at(f, 0, ray.ring)] = (float)tI;
         maps[ma.at(f, 1, ray.ring)] = (float)(fa.sP[f] * ray.dkpc * accQ[f]);
         maps[ma.at(f, 2, ray.ring)] = (float)(fa.sP[f] * ray.dkpc * accU[f]);
       }
     }
     if (phi_end != nullptr) phi_end[ma.off + ray.ring] = carry;
+    if constexpr (FF)
+      if (em_end != nullptr) em_end[ma.off + ray.ring] = emc;
   }
 }
 
@@ -128,18 +175,21 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 // Faraday sum of the earlier pieces, a rotation by its phase turns the latter
 // into the piece's phase-cotangent total, and a suffix scan gives each piece
 // those of the pieces after it.
-template <class F, int S, int MF, bool THETA, bool GRID, class FA>
+template <class F, int S, int MF, bool THETA, bool GRID, bool FF = false, class FA>
 __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, const float* __restrict__ dmaps,
                                 MapAddr ma, const double* __restrict__ phi_end, double* tb,
                                 float* gbn, float* gc, const AdjBox* lds_box = nullptr,
-                                float* lds_stage = nullptr) {
+                                float* lds_stage = nullptr,
+                                const double* __restrict__ em_end = nullptr) {
   const Ray ray = make_ray(g, q);
   const double dk = ray.dkpc;
+  constexpr int MFF = FF ? MF : 1;
 
   // per-sightline cotangent constants
   double GI = 0.0;
   double hr[MF], hi[MF], kr[MF], ki[MF], gi_f[MF];
+  double cf[MFF], kd[MFF];  // FF: dI T_e kff dkpc, and d tau / d EM = kff dkpc
 #pragma unroll
   for (int f = 0; f < MF; ++f) {
     hr[f] = hi[f] = kr[f] = ki[f] = gi_f[f] = 0.0;
@@ -154,7 +204,11 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       const double a = -kTwoPi * fa.kappa[f] * dk;  // d(phase)/d(Faraday sum), with the 2 pi i
       kr[f] = a * hr[f];
       ki[f] = a * hi[f];
+      if constexpr (FF) cf[f] = dI * fa.tff[f] * dk;
+    } else if constexpr (FF) {
+      cf[f] = 0.0;
     }
+    if constexpr (FF) kd[f] = fa.kffl2[f] * kLn2 * dk;
   }
 
   typename F::Acc acc;  // grid-gradient accumulator
@@ -167,15 +221,21 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   constexpr bool SPLIT = GRID && S > 1;
   constexpr bool SERIAL = S == 1 || SPLIT;
   int n_lo = 0, n_hi = g.n_steps;
-  double E = 0.0;    // Faraday sum over the steps before the current chunk's end
-  double suf = 0.0;  // phase cotangents of the steps after it
+  double E = 0.0;     // Faraday sum over the steps before the current chunk's end
+  double suf = 0.0;   // phase cotangents of the steps after it
+  double EM = 0.0;    // FF: sum of n_e^2 over the steps before the current chunk's end
+  double sufE = 0.0;  // FF: cotangents of the emission measure after it
   if constexpr (SPLIT) {
     const int len = (g.n_steps + S - 1) / S;
     n_lo = min(sub * len, g.n_steps);
     n_hi = min(n_lo + len, g.n_steps);
-    double A = 0.0, Wr[MF], Wi[MF];
+    // per frequency: W = sum z a e^{2 pi i t}, U = sum u a, V = sum w a, with the
+    // phase t and the attenuation a counted from the piece start
+    double A = 0.0, Ak = 0.0, Wr[MF], Wi[MF], Uf[MFF], Vf[MFF];
 #pragma unroll
     for (int f = 0; f < MF; ++f) Wr[f] = Wi[f] = 0.0;
+#pragma unroll
+    for (int f = 0; f < MFF; ++f) Uf[f] = Vf[f] = 0.0;
     for (int n = n_lo; n < n_hi; ++n) {
       const FV v = fld.eval_at(g, ray, ((double)n + 0.5) * dk);
       const float bl = v.bx * ray.elx + v.by * ray.ely;
@@ -184,37 +244,70 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       const double cn = (double)v.ne * bpar;
       const double psid = (A + 0.5 * cn) * dk;  // Faraday sum from the piece start
       A += cn;
+      float w = 0.0f, emd = 0.0f;
+      if constexpr (FF) {
+        w = v.ne * v.ne;
+        emd = (float)((Ak + 0.5 * (double)w) * dk);
+        Ak += (double)w;
+      }
       const Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
 #pragma unroll
       for (int f = 0; f < MF; ++f) {
         if (f < fa.n_freq) {
           float sn, cs;
           sincos_turns(psid * fa.kappa[f], &sn, &cs);
-          Wr[f] += (double)(e.zr * cs - e.zi * sn);
-          Wi[f] += (double)(e.zr * sn + e.zi * cs);
+          float zr = e.zr, zi = e.zi;
+          if constexpr (FF) {
+            const float att = exp2f(-(float)fa.kffl2[f] * emd);
+            zr *= att;
+            zi *= att;
+            Uf[f] += (double)(att * e.u);
+            Vf[f] += (double)(att * w);
+          }
+          Wr[f] += (double)(zr * cs - zi * sn);
+          Wi[f] += (double)(zr * sn + zi * cs);
         }
       }
     }
     const double incl = group_inclusive_scan<S>(A, sub);
     const double psid0 = (incl - A) * dk;  // Faraday sum of the earlier pieces
-    double Bk = 0.0;                       // sum of this piece's phase cotangents
+    double emincl = 0.0, emd0 = 0.0;
+    if constexpr (FF) {
+      emincl = group_inclusive_scan<S>(Ak, sub);
+      emd0 = (emincl - Ak) * dk;  // emission measure of the earlier pieces
+    }
+    double Bk = 0.0;  // sum of this piece's phase cotangents
+    double Xk = 0.0;  // FF: sum of this piece's emission-measure cotangents
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
       if (f < fa.n_freq) {
         float sn, cs;
         sincos_turns(psid0 * fa.kappa[f], &sn, &cs);
+        double a0 = 1.0;
+        if constexpr (FF) a0 = (double)exp2f(-(float)(fa.kffl2[f] * emd0));
         const double rr = kr[f] * cs - ki[f] * sn, ri = kr[f] * sn + ki[f] * cs;
-        Bk += rr * Wi[f] + ri * Wr[f];  // Im(k e^{2 pi i t0} W)
+        Bk += a0 * (rr * Wi[f] + ri * Wr[f]);  // Im(k e^{2 pi i t0} a0 W)
+        if constexpr (FF) {
+          const double Rr = hr[f] * cs - hi[f] * sn, Ri = hr[f] * sn + hi[f] * cs;
+          Xk -= kd[f] * a0 * (gi_f[f] * Uf[f] + cf[f] * Vf[f] + Rr * Wr[f] - Ri * Wi[f]);
+        }
       }
     }
     E = incl;
     suf = group_suffix_scan<S>(Bk, sub) - Bk;
+    if constexpr (FF) {
+      EM = emincl;
+      sufE = group_suffix_scan<S>(Xk, sub) - Xk;
+    }
   } else if (valid) {
     E = phi_end[ma.off + ray.ring];
+    if constexpr (FF) EM = em_end[ma.off + ray.ring];
   }
-  double accI = 0.0, accPr[MF], accPi[MF];
+  double accI = 0.0, accPr[MF], accPi[MF], accIf[MFF];
 #pragma unroll
   for (int f = 0; f < MF; ++f) accPr[f] = accPi[f] = 0.0;
+#pragma unroll
+  for (int f = 0; f < MFF; ++f) accIf[f] = 0.0;
 
   // every lane of a wavefront runs the same number of iterations (the grid
   // scatter is collective); a short or empty last piece idles through the rest
@@ -238,27 +331,66 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       psi = E - tot + incl - 0.5 * cn;
       E -= tot;
     }
+    float w = 0.0f, emd = 0.0f;
+    if constexpr (FF) {
+      w = (n < n_hi) ? v.ne * v.ne : 0.0f;
+      double em;
+      if constexpr (SERIAL) {
+        EM -= (double)w;
+        em = EM + 0.5 * (double)w;
+      } else {
+        const double incl = group_inclusive_scan<S>((double)w, sub);
+        const double tot = group_last<S>(incl);
+        em = EM - tot + incl - 0.5 * (double)w;
+        EM -= tot;
+      }
+      emd = (float)(em * dk);
+    }
     Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
     if (!act) e.u = e.zr = e.zi = 0.0f;
-    // H = sum_f h_f e^{2 pi i t_f};  K = sum_f k_f e^{2 pi i t_f}
+    // H = sum_f a_f h_f e^{2 pi i t_f};  K = sum_f a_f k_f e^{2 pi i t_f}
+    // (a_f the free-free attenuation, 1 without)
     double Hr = 0.0, Hi = 0.0, Kr = 0.0, Ki = 0.0;
+    double GIe = GI;  // FF: sum_f a_f gi_f
+    double Cw = 0.0;  // FF: d L / d w of this segment's own free-free emission
+    double X = 0.0;   // FF: d L / d EM at this midpoint
+    if constexpr (FF) GIe = 0.0;
     const double psid = psi * dk;
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
       if (f < fa.n_freq) {
         float sn, cs;
         sincos_turns(psid * fa.kappa[f], &sn, &cs);
-        Hr += hr[f] * cs - hi[f] * sn;
-        Hi += hr[f] * sn + hi[f] * cs;
-        Kr += kr[f] * cs - ki[f] * sn;
-        Ki += kr[f] * sn + ki[f] * cs;
-        if constexpr (THETA) {
-          accPr[f] += (double)(e.zr * cs - e.zi * sn);
-          accPi[f] += (double)(e.zr * sn + e.zi * cs);
+        const double hrf = hr[f] * cs - hi[f] * sn, hif = hr[f] * sn + hi[f] * cs;
+        const double krf = kr[f] * cs - ki[f] * sn, kif = kr[f] * sn + ki[f] * cs;
+        if constexpr (FF) {
+          const double att = (double)exp2f(-(float)fa.kffl2[f] * emd);
+          Hr += att * hrf;
+          Hi += att * hif;
+          Kr += att * krf;
+          Ki += att * kif;
+          GIe += att * gi_f[f];
+          Cw += att * cf[f];
+          X -= kd[f] * att * (gi_f[f] * (double)e.u + cf[f] * (double)w +
+                              hrf * (double)e.zr - hif * (double)e.zi);
+          if constexpr (THETA) {
+            accIf[f] += att * (double)e.u;
+            accPr[f] += att * (double)(e.zr * cs - e.zi * sn);
+            accPi[f] += att * (double)(e.zr * sn + e.zi * cs);
+          }
+        } else {
+          Hr += hrf;
+          Hi += hif;
+          Kr += krf;
+          Ki += kif;
+          if constexpr (THETA) {
+            accPr[f] += (double)(e.zr * cs - e.zi * sn);
+            accPi[f] += (double)(e.zr * sn + e.zi * cs);
+          }
         }
       }
     }
-    if constexpr (THETA) accI += (double)e.u;
+    if constexpr (THETA && !FF) accI += (double)e.u;
     // cotangent of the Faraday sum at this midpoint: Im(zc K)
     const double pb = (double)e.zr * Ki + (double)e.zi * Kr;
     double cbar;  // cotangent of this step's increment: later steps + half of its own
@@ -271,10 +403,26 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       cbar = suf + sincl - 0.5 * pb;
       suf += stot;
     }
+    double wbar = 0.0;  // FF: cotangent of this segment's n_e^2
+    if constexpr (FF) {
+      if (!act) X = Cw = 0.0;
+      double ebar;  // through the emission measure: later midpoints + half of its own
+      if constexpr (SERIAL) {
+        ebar = sufE + 0.5 * X;
+        sufE += X;
+      } else {
+        const double sincl = group_suffix_scan<S>(X, sub);
+        const double stot = group_first<S>(sincl);
+        ebar = sufE + sincl - 0.5 * X;
+        sufE += stot;
+      }
+      wbar = Cw + ebar;
+    }
     // local reverse of the emission and projections
-    const EmitBar eb = emission_vjp(v.n0, bl, bb, ea.alpha3 != 0, ea.eI, (float)GI, (float)Hr,
+    const EmitBar eb = emission_vjp(v.n0, bl, bb, ea.alpha3 != 0, ea.eI, (float)GIe, (float)Hr,
                                     (float)(-Hi));
-    const float neb = (float)(cbar * bpar);
+    float neb = (float)(cbar * bpar);
+    if constexpr (FF) neb += (float)(2.0 * wbar) * v.ne;
     const float bparb = (float)(cbar * (double)v.ne);
     FV gv;
     gv.bx = eb.bl * ray.elx + eb.bb * ray.ebx - bparb * (float)ray.nx;
@@ -295,9 +443,14 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   if constexpr (THETA) {
     // alpha also enters the per-frequency prefactors: d ln s / d alpha * this lane's share
 #pragma unroll
-    for (int f = 0; f < MF; ++f)
-      if (f < fa.n_freq)
-        tb[12] += fa.dlnsI[f] * gi_f[f] * accI + fa.dlnsP[f] * (hr[f] * accPr[f] - hi[f] * accPi[f]);
+    for (int f = 0; f < MF; ++f) {
+      if (f < fa.n_freq) {
+        double aI;
+        if constexpr (FF) aI = accIf[f];
+        else aI = accI;
+        tb[12] += fa.dlnsI[f] * gi_f[f] * aI + fa.dlnsP[f] * (hr[f] * accPr[f] - hi[f] * accPi[f]);
+      }
+    }
   }
 }
 

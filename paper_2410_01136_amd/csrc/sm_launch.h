@@ -26,20 +26,30 @@ struct FieldPack {
   SphereArgs sph;
   MlpArgs mlp;
   WmapArgs wmap;
+  bool ff = false;  // free-free emission and absorption (constants in FreqArgs)
 };
 
 // Number of 256-thread blocks a launch with S lanes per sightline uses.
 inline int64_t march_blocks(int64_t npix, int S) { return (npix * S + 255) / 256; }
 
+// phi_end, em_end: per-sightline Faraday sum and (free-free) emission-measure
+// sum the adjoint starts from, or nullptr when no adjoint follows
 hipError_t launch_forward(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                           const FieldPack& fp, int S, float* maps, double* phi_end,
-                          hipStream_t st);
+                          double* em_end, hipStream_t st);
+hipError_t launch_forward_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                             const FieldPack& fp, int S, float* maps, double* phi_end,
+                             double* em_end, hipStream_t st);
 
 // partials: [march_blocks(npix, S)][16] doubles; dtheta: device double[16]
 hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                           const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
-                          double* partials, double* dtheta, float* gbn, float* gc,
-                          hipStream_t st);
+                          const double* em_end, double* partials, double* dtheta, float* gbn,
+                          float* gc, hipStream_t st);
+hipError_t launch_adjoint_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                             const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
+                             const double* em_end, double* partials, double* dtheta, float* gbn,
+                             float* gc, hipStream_t st);
 
 hipError_t launch_chi2(int64_t n_pix, int n_maps, const float* maps, const float* target,
                        const double* inv_s2, float* dmaps, double* chi2, double* partials,

@@ -90,6 +90,10 @@ struct FreqArgs {
   // d ln sI / d alpha, d ln sP / d alpha (adjoint only)
   double dlnsI[kMaxFreq];
   double dlnsP[kMaxFreq];
+  // free-free: tau = kffl2 ln 2 * dkpc * (emission-measure sum of n_e^2 in
+  // cm^-6), and the free-free term of T_I = tff * dkpc * sum e^-tau n_e^2
+  double kffl2[kMaxFreq];
+  double tff[kMaxFreq];
 };
 
 struct EmitArgs {

@@ -228,3 +228,22 @@ def test_wmap_descriptor_rejected_on_host(sm):
         f = sm.wmap(th)
         st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, None)
         assert st == sm.SYN_EINVAL and "WMAP" in sm.syn_last_error().decode()
+
+
+def test_free_free_arguments_checked_on_host(sm):
+    g = _geom(sm)
+    for te in (-1.0, math.nan, math.inf):
+        f = sm.model16(I.THETA0).with_te(te)
+        st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, None)
+        assert st == sm.SYN_EINVAL and "te_k" in sm.syn_last_error().decode()
+    plain, ff = sm.model16(I.THETA0), sm.model16(I.THETA0).with_te(8000.0)
+    need_plain, need_ff = sm.workspace_bytes(g, plain, True), sm.workspace_bytes(g, ff, True)
+    assert need_ff > need_plain  # the emission-measure sums of the sightlines
+    st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(ff.s), 0x1000, 0x2000, need_plain, None)
+    assert st == sm.SYN_EWORKSPACE
+    st = sm.syn_adjoint(sm.ctypes.byref(g), sm.ctypes.byref(ff.s), 0x1000, 0x2000, need_plain,
+                        0x3000, None, None, None)
+    assert st == sm.SYN_EWORKSPACE
+    mlp = sm.Field(sm.FIELD_MLP, I.THETA0, te_k=8000.0)
+    st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(mlp.s), 0x1000, None, 0, None)
+    assert st == sm.SYN_EUNSUPPORTED
