@@ -124,11 +124,11 @@ def main() -> int:
     ap.add_argument("--fit-lr", type=float, default=0.05, help="Adam step size of the grid fit [uG]")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample")
-    ap.add_argument("--only", choices=("c1", "c2", "fit", "wmap", "hmc", "copy"), default=None,
+    ap.add_argument("--only", choices=("c1", "c2", "fit", "wmap", "hmc", "ff", "copy"), default=None,
                     help="profiling aids: 'c1' runs only the timed headline forward launches; "
                          "'c2' only the N_side 64 adjoint workloads (analytic and 128^3 grid); "
                          "'fit' only the grid fit; 'wmap' only the Sec. 3.1 replay; "
-                         "'hmc' only the Sec. 3.2 sampler; "
+                         "'hmc' only the Sec. 3.2 sampler; 'ff' only the free-free workloads; "
                          "'copy' runs one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -190,6 +190,9 @@ def main() -> int:
     def fwd():
         sm.forward(geom, field, maps=maps)
 
+    if args.only == "ff":
+        bench_free_free(sm, I, np, torch, args, field)
+        return 0
     if not args.no_tune and args.only is None:
         t = tune.tune_forward(geom, field, maps=maps, use_cache=False, write_cache=False)
         log("tuned C1 forward:", t)
@@ -253,6 +256,7 @@ def main() -> int:
         out["grid_fit"] = bench_grid_fit(sm, I, np, torch, args)
         out["wmap"] = bench_wmap(sm, I, np, torch, tune, args)
         out["hmc"] = bench_hmc(sm, I, np, torch, args)
+        out["free_free"] = bench_free_free(sm, I, np, torch, args, field)
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(sm, I, np, torch, args, field)
 
@@ -399,6 +403,51 @@ def bench_wmap(sm, I, np, torch, tune, args):
     log("WMAP likelihood + gradient:", res)
     for k in range(3):
         sm.set_lanes_per_ray(k, 4, 0)
+    return res
+
+
+def bench_free_free(sm, I, np, torch, args, grid_field):
+    """Free-free emission and absorption (T_e = 8000 K, the thermal electrons of
+    the fields): the headline gridded workload (N_side 256, 512 steps, 256^3
+    nodes) moved to {150, 300, 600} MHz, and the N_side 64 / 768 step analytic
+    theta-gradient workload (forward + adjoint) at the same frequencies, each
+    timed with and without free-free."""
+    freqs = (0.15e9, 0.3e9, 0.6e9)
+    te = 8000.0
+    g = I.geometry("C1", freqs_hz=freqs)
+    geom = sm.geom_from(g)
+    maps = torch.empty((len(freqs), 3, g.npix), dtype=torch.float32, device="cuda")
+    grid_ms = {}
+    for t in (0.0, te):
+        f = grid_field.with_te(t)
+        _, ev = time_launches(lambda: sm.forward(geom, f, maps=maps), args.steps, args.warmup)
+        grid_ms["free_free" if t else "plain"] = round(ev, 4)
+    g2 = I.geometry("C2", freqs_hz=freqs)
+    geom2 = sm.geom_from(g2)
+    dm = torch.from_numpy(I.cotangents((len(freqs), 3, g2.npix), seed=7001)).cuda()
+    maps2 = torch.empty((len(freqs), 3, g2.npix), dtype=torch.float32, device="cuda")
+    theta_ms = {}
+    for t in (0.0, te):
+        f = sm.model16(I.THETA0).with_te(t)
+        ws = sm.alloc_workspace(geom2, f)
+
+        def fwd_adj():
+            sm.forward(geom2, f, maps=maps2, ws=ws)
+            sm.adjoint(geom2, f, dm, ws)
+
+        wall, _ = time_launches(fwd_adj, args.steps, args.warmup)
+        theta_ms["free_free" if t else "plain"] = round(wall, 4)
+    res = {
+        "workload": "T_e 8000 K; 256^3 grid at N_side 256 x 512 steps and analytic model at "
+                    "N_side 64 x 768 steps (forward + theta-adjoint), both at {150, 300, 600} MHz",
+        "grid_forward_ms": grid_ms,
+        "grid_forward_ff_sightline_steps_per_s": float(f"{g.units / (grid_ms['free_free'] * 1e-3):.4e}"),
+        "grid_read_path": grid_read_path(sm, g.npix),
+        "theta_fwd_adj_ms": theta_ms,
+        "ff_over_plain": {"grid_forward": round(grid_ms["free_free"] / grid_ms["plain"], 3),
+                          "theta_fwd_adj": round(theta_ms["free_free"] / theta_ms["plain"], 3)},
+    }
+    log("free-free:", res)
     return res
 
 

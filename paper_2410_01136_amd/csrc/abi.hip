@@ -390,8 +390,7 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
       // automatic: shared cell reads pay off once there are enough wavefronts
       // to hide their longer dependency chain (measured: N_side 256 gains 1.3x,
       // N_side 64 loses 10%)
-      // (free-free is built for the per-lane reads only)
-      const bool shared = !fp.ff && (mode == 3 || (mode == 0 && ga.npix >= (1 << 18)));
+      const bool shared = mode == 3 || (mode == 0 && ga.npix >= (1 << 18));
       fp.grid_path = (mode == 1 || !grid_buffer_ok(ga, fp.grid)) ? sm::kGridGlobal
                      : shared                                    ? sm::kGridShared
                                                                  : sm::kGridBuffer;

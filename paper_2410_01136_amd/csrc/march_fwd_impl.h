@@ -52,8 +52,6 @@ static hipError_t fwd_s(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& e
   }
 }
 
-// The shared-read grid path is built without free-free (the host picks the
-// per-lane buffer reads then).
 template <bool FF>
 static hipError_t launch_forward_t(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                                    const FieldPack& fp, int S, float* maps, double* phi_end,
@@ -61,10 +59,8 @@ static hipError_t launch_forward_t(const GeomArgs& g, const FreqArgs& fa, const 
   switch (fp.kind) {
     case kModel16: return fwd_s<FF>(g, fa, ea, Model16{fp.m16}, S, maps, phi_end, em_end, st);
     case kGrid:
-      if constexpr (!FF) {
-        if (fp.grid_path == kGridShared)
-          return fwd_s<FF>(g, fa, ea, GridL{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
-      }
+      if (fp.grid_path == kGridShared)
+        return fwd_s<FF>(g, fa, ea, GridL{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
       if (fp.grid_path != kGridGlobal)
         return fwd_s<FF>(g, fa, ea, GridB{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
       return fwd_s<FF>(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);

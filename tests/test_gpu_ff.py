@@ -82,7 +82,7 @@ def dense_grid(orc, n=(33, 33, 9), lo=I.BOX_LO, hi=I.BOX_HI, seed0=4101):
 @pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("S", [1, 16])
 def test_grid_read_paths(sm, orc, lanes, mode, S):
-    # mode 3 (shared reads) falls back to per-lane buffer reads with free-free
+    # 64-bit addresses, per-lane buffer reads and shared reads through LDS
     import torch
     g = I.geometry("C2", nside=8, n_steps=83, freqs_hz=FREQS_FF, r_max=3.0)
     bn, c = dense_grid(orc)
