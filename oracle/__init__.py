@@ -47,7 +47,7 @@ class _Field(ctypes.Structure):
                 ("grid_n", ctypes.c_int32 * 3), ("grid_lo", ctypes.c_double * 3),
                 ("grid_hi", ctypes.c_double * 3),
                 ("grid_bn", ctypes.c_void_p), ("grid_c", ctypes.c_void_p),
-                ("te_k", ctypes.c_double)]
+                ("te_k", ctypes.c_double), ("grid_alpha", ctypes.c_void_p)]
 
 
 _lib = None
@@ -116,7 +116,7 @@ class Field:
     """Field description; keeps the grid arrays alive while in use."""
 
     def __init__(self, kind, theta, grid_bn=None, grid_c=None, grid_lo=None, grid_hi=None,
-                 te_k=0.0):
+                 te_k=0.0, grid_alpha=None):
         self.s = _Field()
         self.s.kind = int(kind)
         self.s.te_k = float(te_k)  # > 0: free-free emission and absorption at T_e [K]
@@ -139,6 +139,12 @@ class Field:
                 if self.grid_c.shape != (nz, ny, nx):
                     raise ValueError("grid_c must be [nz][ny][nx]")
                 self.s.grid_c = self.grid_c.ctypes.data
+            self.grid_alpha = None
+            if grid_alpha is not None:  # spectral index per node (theta[12] unused)
+                self.grid_alpha = np.ascontiguousarray(grid_alpha, dtype=np.float32)
+                if self.grid_alpha.shape != (nz, ny, nx):
+                    raise ValueError("grid_alpha must be [nz][ny][nx]")
+                self.s.grid_alpha = self.grid_alpha.ctypes.data
 
 
 def forward(geom: _Geom, field: Field) -> np.ndarray:

@@ -89,6 +89,7 @@ typedef struct {
   const float* grid_bn; /* [nz][ny][nx][4] = Bx, By, Bz [uG], n_e [cm^-3]   */
   const float* grid_c;  /* [nz][ny][nx] N0 [cm^-3], or NULL -> analytic N0  */
   double te_k;          /* electron temperature [K]; > 0 adds free-free      */
+  const float* grid_alpha; /* [nz][ny][nx] CR spectral index, or NULL -> theta[12] */
 } or_field;
 
 /* ========================================================================== */
@@ -445,6 +446,21 @@ void or_fields(const or_field* f, const double r[3], double B[3], double* ne, do
   }
 }
 
+/* Power-law index of the CR spectrum at r: theta[12], or for a grid field with
+   a gridded index its trilinear interpolation (Eqs. ji and jp then use the
+   local value; a spatially varying index is the first step toward the full
+   CR spectrum the paper leaves to future work, Sec. 2.1).  Outside the grid
+   box the fields vanish and the index is not used. */
+double or_alpha_at(const or_field* f, const double r[3]) {
+  if (f->kind != OR_GRID || f->grid_alpha == NULL) return f->theta[12];
+  int64_t base, s[3];
+  double w[8];
+  if (!or_grid_cell(f, r, &base, s, w)) return f->theta[12];
+  double a = 0.0;
+  for (int c = 0; c < 8; ++c) a += w[c] * (double)f->grid_alpha[or_corner(base, s, c)];
+  return a;
+}
+
 /* ========================================================================== */
 /* Emissivities (Sec. 2.1 Eq. ji, Sec. 2.2 Eq. jp)                           */
 /* ========================================================================== */
@@ -609,12 +625,13 @@ static double or_march_source(const or_geom* g, const or_source* src, double alp
     const double em_seg = te > 0.0 ? q.ne * q.ne * dpc : 0.0;
     const double EM = em_before + 0.5 * em_seg;
     em_before += em_seg;
+    const double a_n = src->f != NULL ? or_alpha_at(src->f, r) : alpha;
     for (int k = 0; k < g->n_freq; ++k) {
       const double nu = g->freq_hz[k];
       const double lam = OR_C / nu;
       const double att = te > 0.0 ? exp(-or_kff(nu, te) * EM) : 1.0;
-      const double jI = or_j_I(alpha, nu, q.Bt, q.n0);
-      const double jP = or_j_P(alpha, nu, q.Bt, q.n0);
+      const double jI = or_j_I(a_n, nu, q.Bt, q.n0);
+      const double jP = or_j_P(a_n, nu, q.Bt, q.n0);
       const double chi = RM * lam * lam + q.chi0;
       I[k] += att * jI * ray.dcm;
       Q[k] += att * jP * cos(2.0 * chi) * ray.dcm;
@@ -645,6 +662,7 @@ static int or_check(const or_geom* g, const or_field* f) {
                              f->grid_n[2] < 2))
     return -1;
   if (!(f->te_k >= 0.0) || isinf(f->te_k)) return -1;
+  if (f->grid_alpha != NULL && f->kind != OR_GRID) return -1;
   return 0;
 }
 
@@ -719,7 +737,7 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
   or_ray ray;
   or_make_ray(g, p, &ray);
   const int N = g->n_steps;
-  const double alpha = f->theta[12];
+  const int alpha_gridded = f->kind == OR_GRID && f->grid_alpha != NULL;
   const double krm = or_k_rm();
   const double te = f->te_k;
   const double dpc = ray.dkpc * 1e3;
@@ -729,12 +747,14 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
   double* EM = (double*)malloc(sizeof(double) * (size_t)N);  /* emission measure to midpoint n */
   double* emb = (double*)malloc(sizeof(double) * (size_t)N); /* dL/dEM_n */
   double* ffb = (double*)malloc(sizeof(double) * (size_t)N); /* dL/d(n_e^2 dl) of its own emission */
+  double* al = (double*)malloc(sizeof(double) * (size_t)N);  /* spectral index at midpoint n */
   /* forward sweep, keeping the per-step quantities */
   double before = 0.0, em_before = 0.0;
   for (int n = 0; n < N; ++n) {
     double r[3];
     or_midpoint(g, &ray, n, r);
     or_local_eval(f, &ray, r, &q[n]);
+    al[n] = or_alpha_at(f, r);
     const double seg = q[n].ne * q[n].blos * ray.dcm;
     RM[n] = krm * (before + 0.5 * seg);
     before += seg;
@@ -751,6 +771,7 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
     emb[n] = 0.0;
     ffb[n] = 0.0;
     const double em_seg = te > 0.0 ? q[n].ne * q[n].ne * dpc : 0.0;
+    const double alpha = al[n];
     for (int k = 0; k < g->n_freq; ++k) {
       const double nu = g->freq_hz[k];
       const double lam = OR_C / nu;
@@ -789,6 +810,7 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
     const double neb_seg = segb * q[n].blos * ray.dcm + (te > 0.0 ? em_segb * 2.0 * q[n].ne * dpc : 0.0);
     const double blosb = segb * q[n].ne * ray.dcm;
     /* j_I, j_P depend on Bt, n0 (and alpha); chi0 = atan2(num, den) */
+    const double alpha = al[n];
     double Btb = 0.0, n0b = 0.0, ab = 0.0;
     for (int k = 0; k < g->n_freq; ++k) {
       const double nu = g->freq_hz[k];
@@ -813,7 +835,7 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
       numb = Btb * q[n].num / q[n].Bt + chi0b[n] * q[n].den / bt2;
       denb = Btb * q[n].den / q[n].Bt - chi0b[n] * q[n].num / bt2;
     }
-    tb[12] += ab;
+    if (!alpha_gridded) tb[12] += ab; /* a gridded index is an input without a gradient */
     /* num = 1e-6 B.e_b, den = -1e-6 B.e_l, blos = -1e-6 B.n  (B in uG) */
     double Bb[3];
     for (int k = 0; k < 3; ++k)
@@ -856,6 +878,7 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
   free(EM);
   free(emb);
   free(ffb);
+  free(al);
   free(jIb);
   free(jPb);
   free(chi0b);
