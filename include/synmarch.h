@@ -111,7 +111,17 @@ typedef struct syn_field {
   const float* grid_c;          /* (device) or NULL                           */
   const void* mlp;              /* (device)                                   */
   double te_k;                  /* thermal electron temperature [K]; 0 = off  */
+  const float* grid_alpha;      /* (device) GRID: CR spectral index per node,
+                                   float [nz][ny][nx], or NULL for theta[12]   */
 } syn_field;
+/* Gridded spectral index (grid_alpha != NULL, GRID fields only; a first step
+   toward the full CR spectrum the paper leaves to future work, Sec. 2.1):
+   Eqs. ji and jp are evaluated at each midpoint with alpha interpolated
+   trilinearly from the nodes like the other gridded fields.  Values must
+   exceed 1/3 (the pole of Gamma(alpha/4 - 1/12)); they are not checked on the
+   host.  theta[12] then only sets the reference point of the prefactors and
+   receives no gradient (dtheta[12] = 0); the index itself gets no gradient.
+   SYN_EINVAL for a non-GRID field or a pointer not 4-byte aligned. */
 /* Free-free emission and absorption (te_k > 0; the paper names both as future
    work in Sec. 5 and gives no formulas, so this follows the textbook radio
    treatment): the thermal electrons n_e, taken as a fully ionised hydrogen

@@ -40,7 +40,7 @@ class SynField(ctypes.Structure):
                 ("grid_n", ctypes.c_int32 * 3), ("grid_lo_kpc", ctypes.c_double * 3),
                 ("grid_hi_kpc", ctypes.c_double * 3), ("grid_bn", ctypes.c_void_p),
                 ("grid_c", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
-                ("te_k", ctypes.c_double)]
+                ("te_k", ctypes.c_double), ("grid_alpha", ctypes.c_void_p)]
 
 
 class SynBatchDesc(ctypes.Structure):
@@ -146,10 +146,12 @@ class Field:
 
     def __init__(self, kind: int, theta, grid_bn: Optional[torch.Tensor] = None,
                  grid_c: Optional[torch.Tensor] = None, lo=None, hi=None,
-                 mlp: Optional[torch.Tensor] = None, te_k: float = 0.0):
+                 mlp: Optional[torch.Tensor] = None, te_k: float = 0.0,
+                 grid_alpha: Optional[torch.Tensor] = None):
         self.s = SynField()
         self.s.kind = int(kind)
         self.s.te_k = float(te_k)  # > 0: free-free emission and absorption at T_e [K]
+        self.grid_alpha = grid_alpha  # CR spectral index per node (GRID fields)
         th = np.asarray(theta, dtype=np.float64).reshape(-1)
         if th.size != NPARAM:
             raise ValueError("theta must have 16 entries")
@@ -167,6 +169,11 @@ class Field:
                 if tuple(grid_c.shape) != (nz, ny, nx):
                     raise ValueError("grid_c must be [nz][ny][nx]")
                 self.s.grid_c = grid_c.data_ptr()
+            if grid_alpha is not None:
+                _dev_f32(grid_alpha, "grid_alpha")
+                if tuple(grid_alpha.shape) != (nz, ny, nx):
+                    raise ValueError("grid_alpha must be [nz][ny][nx]")
+                self.s.grid_alpha = grid_alpha.data_ptr()
         if lo is not None:
             self.s.grid_lo_kpc[:] = [float(v) for v in lo]
             self.s.grid_hi_kpc[:] = [float(v) for v in hi]
@@ -179,20 +186,23 @@ class Field:
 
     def with_theta(self, theta) -> "Field":
         return Field(self.s.kind, theta, self.grid_bn, self.grid_c,
-                     self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, self.s.te_k)
+                     self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, self.s.te_k,
+                     self.grid_alpha)
 
     def with_te(self, te_k: float) -> "Field":
         """The same field with free-free emission and absorption at T_e = te_k [K]."""
         return Field(self.s.kind, self.theta, self.grid_bn, self.grid_c,
-                     self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, te_k)
+                     self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, te_k,
+                     self.grid_alpha)
 
 
 def model16(theta) -> Field:
     return Field(FIELD_MODEL16, theta)
 
 
-def grid(theta, grid_bn: torch.Tensor, grid_c: Optional[torch.Tensor], lo, hi) -> Field:
-    return Field(FIELD_GRID, theta, grid_bn, grid_c, lo, hi)
+def grid(theta, grid_bn: torch.Tensor, grid_c: Optional[torch.Tensor], lo, hi,
+         grid_alpha: Optional[torch.Tensor] = None) -> Field:
+    return Field(FIELD_GRID, theta, grid_bn, grid_c, lo, hi, grid_alpha=grid_alpha)
 
 
 def sphere(theta) -> Field:

@@ -172,6 +172,10 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
   fp->ff = f->te_k > 0.0;
   if (fp->ff && f->kind == SYN_FIELD_MLP)
     return fail(SYN_EUNSUPPORTED, "free-free (te_k > 0) is not available for the MLP surrogate");
+  if (f->grid_alpha != nullptr) {
+    if (f->kind != SYN_FIELD_GRID) return fail(SYN_EINVAL, "grid_alpha needs a GRID field");
+    if (((uintptr_t)f->grid_alpha & 3) != 0) return fail(SYN_EINVAL, "grid_alpha must be 4-byte aligned");
+  }
   switch (f->kind) {
     case SYN_FIELD_MODEL16: {
       syn_status s = check_m16_theta(f->theta);
@@ -201,6 +205,7 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
       sm::GridArgs& ga = fp->grid;
       ga.bn = reinterpret_cast<const float4*>(f->grid_bn);
       ga.c = f->grid_c;
+      ga.alpha = f->grid_alpha;
       for (int k = 0; k < 3; ++k) {
         ga.n[k] = f->grid_n[k];
         ga.lo[k] = f->grid_lo_kpc[k];
@@ -297,6 +302,8 @@ void freq_args(const syn_geom* g, double alpha, double te_k, sm::FreqArgs* fa) {
     fa->kappa[f] = krm * 1e-6 * kKpcCm * lam * lam / kPi;       // turns of 2 RM lambda^2
     fa->dlnsI[f] = -0.5 * log(base) + 0.5 * log(2.0) - 1.0 / (alpha + 1.0) + dig + 0.5 * log(1e-6);
     fa->dlnsP[f] = fa->dlnsI[f] + 1.0 / (alpha + 1.0) - 1.0 / (alpha + 7.0 / 3.0);
+    // the part of d ln sI / d alpha outside Gamma(..) and 1 / (alpha + 1), per log2
+    fa->va_k1l2[f] = (-0.5 * log(base) + 0.5 * log(2.0) + 0.5 * log(1e-6)) / log(2.0);
     if (te_k > 0.0) {
       const double kff_kpc = 1e3 * 0.08235 * pow(te_k, -1.35) * pow(nu / 1e9, -2.1);
       fa->kffl2[f] = kff_kpc / log(2.0);
@@ -309,6 +316,10 @@ sm::EmitArgs emit_args(double alpha) {
   sm::EmitArgs e;
   e.alpha3 = alpha == 3.0 ? 1 : 0;
   e.eI = (float)((alpha + 1.0) / 4.0);
+  // reference point of a gridded alpha: the prefactors above belong to theta[12]
+  e.va_alpha_ref = alpha;
+  e.va_gref = lgamma(alpha / 4.0 - 1.0 / 12.0) + lgamma(alpha / 4.0 + 19.0 / 12.0) - log(alpha + 1.0);
+  e.va_pref = (alpha + 1.0) / (alpha + 7.0 / 3.0);
   return e;
 }
 

@@ -19,11 +19,16 @@ hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs&
                           const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
                           const double* em_end, double* partials, double* dtheta, float* gbn,
                           float* gc, hipStream_t st) {
+  if (fp.grid.alpha != nullptr)
+    return fp.ff ? launch_adjoint_va_ff(g, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta,
+                                        gbn, gc, st)
+                 : launch_adjoint_va(g, fa, ea, fp, S, dmaps, phi_end, nullptr, partials, dtheta,
+                                     gbn, gc, st);
   if (fp.ff)
     return launch_adjoint_ff(g, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta, gbn, gc,
                              st);
-  return launch_adjoint_t<false>(g, fa, ea, fp, S, dmaps, phi_end, nullptr, partials, dtheta, gbn,
-                                 gc, st);
+  return launch_adjoint_t<false, false>(g, fa, ea, fp, S, dmaps, phi_end, nullptr, partials,
+                                        dtheta, gbn, gc, st);
 }
 
 }  // namespace sm

@@ -51,7 +51,11 @@ constexpr bool exact_freqs(int MF) { return MF == 1 || MF == 3; }
 // the observer attenuated by e^-tau_f, tau_f = kff_f dkpc EM with EM the sum of
 // n_e^2 over the earlier segments plus half of this one (a second prefix sum,
 // carried like the Faraday sum), and the segment adds T_e dtau_f to I.
-template <class F, int S, int MF, bool FF = false, class FA>
+//
+// Gridded spectral index (VA): the emission of a segment uses the local alpha,
+// its exponent in B_perp and its frequency prefactors (one ratio per
+// frequency to the prefactors of theta[12]), so the I sum is per frequency.
+template <class F, int S, int MF, bool FF = false, bool VA = false, class FA>
 __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, float* __restrict__ maps,
                                 MapAddr ma, double* __restrict__ phi_end,
@@ -59,16 +63,20 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   const Ray ray = make_ray(g, q);
   const auto rctx = fld.ray_ctx(g, ray);
   constexpr bool zero_beyond = zero_beyond_path<F>();
+  constexpr bool PF = FF || VA;  // per-frequency I sums
   constexpr int MFF = FF ? MF : 1;
+  constexpr int MPF = PF ? MF : 1;
   double carry = 0.0;  // Faraday sum (n_e B_par, uG cm^-3) of all earlier chunks
   double emc = 0.0;    // FF: sum of n_e^2 (cm^-6) of all earlier chunks
   double accI = 0.0;
   double accQ[MF], accU[MF];
-  double accIf[MFF], accF[MFF];  // FF: attenuated synchrotron I and free-free sums
+  double accIf[MPF], accF[MFF];  // per-frequency synchrotron I; FF: free-free sums
 #pragma unroll
   for (int f = 0; f < MF; ++f) accQ[f] = accU[f] = 0.0;
 #pragma unroll
-  for (int f = 0; f < MFF; ++f) accIf[f] = accF[f] = 0.0;
+  for (int f = 0; f < MPF; ++f) accIf[f] = 0.0;
+#pragma unroll
+  for (int f = 0; f < MFF; ++f) accF[f] = 0.0;
 
   for (int c0 = 0; c0 < g.n_steps; c0 += S) {
     const int n = c0 + sub;
@@ -102,9 +110,15 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       }
       emd = (float)(em * ray.dkpc);
     }
-    Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
+    double al = 0.0;
+    VaStep vs{};
+    if constexpr (VA) {
+      al = fld.alpha_at(g, ray, s, ea.va_alpha_ref);
+      vs = va_step(al, ea);
+    }
+    Emit e = VA ? emission(v.n0, bl, bb, false, vs.eI) : emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
     if (!zero_beyond && !act) e.u = e.zr = e.zi = 0.0f;
-    if constexpr (!FF) accI += (double)e.u;
+    if constexpr (!PF) accI += (double)e.u;
     const double psid = psi * ray.dkpc;
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
@@ -112,12 +126,21 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
         float sn, cs;
         sincos_turns(psid * fa.kappa[f], &sn, &cs);  // turns of 2 RM lambda^2
         float zr = e.zr, zi = e.zi;
-        if constexpr (FF) {
-          const float att = exp2f(-(float)fa.kffl2[f] * emd);
-          zr *= att;
-          zi *= att;
-          accIf[f] += (double)(att * e.u);
-          accF[f] += (double)(att * w);
+        if constexpr (PF) {
+          float mI = 1.0f, mP = 1.0f;  // per-frequency multipliers of I and of Q + iU
+          if constexpr (VA) {
+            mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
+            mP = mI * vs.prat;
+          }
+          if constexpr (FF) {
+            const float att = exp2f(-(float)fa.kffl2[f] * emd);
+            mI *= att;
+            mP *= att;
+            accF[f] += (double)(att * w);
+          }
+          zr *= mP;
+          zi *= mP;
+          accIf[f] += (double)(mI * e.u);
         }
         accQ[f] += (double)(zr * cs - zi * sn);
         accU[f] += (double)(zr * sn + zi * cs);
@@ -132,12 +155,13 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       accQ[f] = group_sum<S>(accQ[f]);
       accU[f] = group_sum<S>(accU[f]);
     }
+    if constexpr (PF) {
+#pragma unroll
+      for (int f = 0; f < MF; ++f) accIf[f] = group_sum<S>(accIf[f]);
+    }
     if constexpr (FF) {
 #pragma unroll
-      for (int f = 0; f < MF; ++f) {
-        accIf[f] = group_sum<S>(accIf[f]);
-        accF[f] = group_sum<S>(accF[f]);
-      }
+      for (int f = 0; f < MF; ++f) accF[f] = group_sum<S>(accF[f]);
     }
   }
   if (valid && sub == 0) {
@@ -145,10 +169,11 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     for (int f = 0; f < MF; ++f) {
       if (exact_freqs(MF) || f < fa.n_freq) {
         double tI;
-        if constexpr (FF)
-          tI = fa.sI[f] * ray.dkpc * accIf[f] + fa.tff[f] * ray.dkpc * accF[f];
+        if constexpr (PF)
+          tI = fa.sI[f] * ray.dkpc * accIf[f];
         else
           tI = fa.sI[f] * ray.dkpc * accI;
+        if constexpr (FF) tI += fa.tff[f] * ray.dkpc * accF[f];
         maps[ma.at(f, 0, ray.ring)] = (float)tI;
         maps[ma.at(f, 1, ray.ring)] = (float)(fa.sP[f] * ray.dkpc * accQ[f]);
         maps[ma.at(f, 2, ray.ring)] = (float)(fa.sP[f] * ray.dkpc * accU[f]);
@@ -175,7 +200,8 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 // Faraday sum of the earlier pieces, a rotation by its phase turns the latter
 // into the piece's phase-cotangent total, and a suffix scan gives each piece
 // those of the pieces after it.
-template <class F, int S, int MF, bool THETA, bool GRID, bool FF = false, class FA>
+template <class F, int S, int MF, bool THETA, bool GRID, bool FF = false, bool VA = false,
+          class FA>
 __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, const float* __restrict__ dmaps,
                                 MapAddr ma, const double* __restrict__ phi_end, double* tb,
@@ -185,6 +211,9 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   const Ray ray = make_ray(g, q);
   const double dk = ray.dkpc;
   constexpr int MFF = FF ? MF : 1;
+  constexpr bool PF = FF || VA;  // per-frequency multipliers of the emission
+  // (with a gridded alpha, theta[12] does not enter the maps: no alpha gradient)
+  constexpr bool ALPHA_GRAD = THETA && !VA;
 
   // per-sightline cotangent constants
   double GI = 0.0;
@@ -250,19 +279,35 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
         emd = (float)((Ak + 0.5 * (double)w) * dk);
         Ak += (double)w;
       }
-      const Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
+      double al = 0.0;
+      VaStep vs{};
+      if constexpr (VA) {
+        al = fld.alpha_at(g, ray, ((double)n + 0.5) * dk, ea.va_alpha_ref);
+        vs = va_step(al, ea);
+      }
+      const Emit e =
+          VA ? emission(v.n0, bl, bb, false, vs.eI) : emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
 #pragma unroll
       for (int f = 0; f < MF; ++f) {
         if (f < fa.n_freq) {
           float sn, cs;
           sincos_turns(psid * fa.kappa[f], &sn, &cs);
           float zr = e.zr, zi = e.zi;
-          if constexpr (FF) {
-            const float att = exp2f(-(float)fa.kffl2[f] * emd);
-            zr *= att;
-            zi *= att;
-            Uf[f] += (double)(att * e.u);
-            Vf[f] += (double)(att * w);
+          if constexpr (PF) {
+            float mI = 1.0f, mP = 1.0f;
+            if constexpr (VA) {
+              mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
+              mP = mI * vs.prat;
+            }
+            if constexpr (FF) {
+              const float att = exp2f(-(float)fa.kffl2[f] * emd);
+              mI *= att;
+              mP *= att;
+              Vf[f] += (double)(att * w);
+            }
+            zr *= mP;
+            zi *= mP;
+            if constexpr (FF) Uf[f] += (double)(mI * e.u);
           }
           Wr[f] += (double)(zr * cs - zi * sn);
           Wi[f] += (double)(zr * sn + zi * cs);
@@ -303,11 +348,12 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     E = phi_end[ma.off + ray.ring];
     if constexpr (FF) EM = em_end[ma.off + ray.ring];
   }
-  double accI = 0.0, accPr[MF], accPi[MF], accIf[MFF];
+  constexpr int MPF = PF ? MF : 1;
+  double accI = 0.0, accPr[MF], accPi[MF], accIf[MPF];
 #pragma unroll
   for (int f = 0; f < MF; ++f) accPr[f] = accPi[f] = 0.0;
 #pragma unroll
-  for (int f = 0; f < MFF; ++f) accIf[f] = 0.0;
+  for (int f = 0; f < MPF; ++f) accIf[f] = 0.0;
 
   // every lane of a wavefront runs the same number of iterations (the grid
   // scatter is collective); a short or empty last piece idles through the rest
@@ -346,15 +392,24 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       }
       emd = (float)(em * dk);
     }
-    Emit e = emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
+    double al = 0.0;
+    VaStep vs{};
+    if constexpr (VA) {
+      al = fld.alpha_at(g, ray, s, ea.va_alpha_ref);
+      vs = va_step(al, ea);
+    }
+    const float eI = VA ? vs.eI : ea.eI;
+    const bool a3 = VA ? false : ea.alpha3 != 0;
+    Emit e = emission(v.n0, bl, bb, a3, eI);
     if (!act) e.u = e.zr = e.zi = 0.0f;
-    // H = sum_f a_f h_f e^{2 pi i t_f};  K = sum_f a_f k_f e^{2 pi i t_f}
-    // (a_f the free-free attenuation, 1 without)
+    // H = sum_f mP_f h_f e^{2 pi i t_f};  K = sum_f mP_f k_f e^{2 pi i t_f}
+    // (mI_f, mP_f the per-frequency multipliers of I and Q + iU: the free-free
+    // attenuation and the local-alpha prefactor ratio; 1 without either)
     double Hr = 0.0, Hi = 0.0, Kr = 0.0, Ki = 0.0;
-    double GIe = GI;  // FF: sum_f a_f gi_f
+    double GIe = GI;  // sum_f mI_f gi_f
     double Cw = 0.0;  // FF: d L / d w of this segment's own free-free emission
     double X = 0.0;   // FF: d L / d EM at this midpoint
-    if constexpr (FF) GIe = 0.0;
+    if constexpr (PF) GIe = 0.0;
     const double psid = psi * dk;
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
@@ -363,34 +418,45 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
         sincos_turns(psid * fa.kappa[f], &sn, &cs);
         const double hrf = hr[f] * cs - hi[f] * sn, hif = hr[f] * sn + hi[f] * cs;
         const double krf = kr[f] * cs - ki[f] * sn, kif = kr[f] * sn + ki[f] * cs;
-        if constexpr (FF) {
-          const double att = (double)exp2f(-(float)fa.kffl2[f] * emd);
-          Hr += att * hrf;
-          Hi += att * hif;
-          Kr += att * krf;
-          Ki += att * kif;
-          GIe += att * gi_f[f];
-          Cw += att * cf[f];
-          X -= kd[f] * att * (gi_f[f] * (double)e.u + cf[f] * (double)w +
-                              hrf * (double)e.zr - hif * (double)e.zi);
-          if constexpr (THETA) {
-            accIf[f] += att * (double)e.u;
-            accPr[f] += att * (double)(e.zr * cs - e.zi * sn);
-            accPi[f] += att * (double)(e.zr * sn + e.zi * cs);
+        if constexpr (PF) {
+          double mI = 1.0, mP = 1.0, att = 1.0;
+          if constexpr (VA) {
+            mI = (double)va_ratio(vs, fa.va_k1l2[f], al, ea);
+            mP = mI * (double)vs.prat;
+          }
+          if constexpr (FF) {
+            att = (double)exp2f(-(float)fa.kffl2[f] * emd);
+            mI *= att;
+            mP *= att;
+          }
+          Hr += mP * hrf;
+          Hi += mP * hif;
+          Kr += mP * krf;
+          Ki += mP * kif;
+          GIe += mI * gi_f[f];
+          if constexpr (FF) {
+            Cw += att * cf[f];
+            X -= kd[f] * (mI * gi_f[f] * (double)e.u + att * cf[f] * (double)w +
+                          mP * (hrf * (double)e.zr - hif * (double)e.zi));
+          }
+          if constexpr (ALPHA_GRAD) {
+            accIf[f] += mI * (double)e.u;
+            accPr[f] += mP * (double)(e.zr * cs - e.zi * sn);
+            accPi[f] += mP * (double)(e.zr * sn + e.zi * cs);
           }
         } else {
           Hr += hrf;
           Hi += hif;
           Kr += krf;
           Ki += kif;
-          if constexpr (THETA) {
+          if constexpr (ALPHA_GRAD) {
             accPr[f] += (double)(e.zr * cs - e.zi * sn);
             accPi[f] += (double)(e.zr * sn + e.zi * cs);
           }
         }
       }
     }
-    if constexpr (THETA && !FF) accI += (double)e.u;
+    if constexpr (ALPHA_GRAD && !PF) accI += (double)e.u;
     // cotangent of the Faraday sum at this midpoint: Im(zc K)
     const double pb = (double)e.zr * Ki + (double)e.zi * Kr;
     double cbar;  // cotangent of this step's increment: later steps + half of its own
@@ -419,8 +485,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       wbar = Cw + ebar;
     }
     // local reverse of the emission and projections
-    const EmitBar eb = emission_vjp(v.n0, bl, bb, ea.alpha3 != 0, ea.eI, (float)GIe, (float)Hr,
-                                    (float)(-Hi));
+    const EmitBar eb = emission_vjp(v.n0, bl, bb, a3, eI, (float)GIe, (float)Hr, (float)(-Hi));
     float neb = (float)(cbar * bpar);
     if constexpr (FF) neb += (float)(2.0 * wbar) * v.ne;
     const float bparb = (float)(cbar * (double)v.ne);
@@ -433,20 +498,20 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     if constexpr (THETA) {
       if (act) {
         fld.vjp_at(g, ray, s, gv, tb);
-        tb[12] += (double)eb.alpha;
+        if constexpr (ALPHA_GRAD) tb[12] += (double)eb.alpha;
       }
     }
     if constexpr (GRID) fld.accumulate_step(g, ray, s, gv, act, acc, gbn, gc);
   }
   if constexpr (GRID) fld.flush_all(acc, gbn, gc);
 
-  if constexpr (THETA) {
+  if constexpr (ALPHA_GRAD) {
     // alpha also enters the per-frequency prefactors: d ln s / d alpha * this lane's share
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
       if (f < fa.n_freq) {
         double aI;
-        if constexpr (FF) aI = accIf[f];
+        if constexpr (PF) aI = accIf[f];
         else aI = accI;
         tb[12] += fa.dlnsI[f] * gi_f[f] * aI + fa.dlnsP[f] * (hr[f] * accPr[f] - hi[f] * accPi[f]);
       }

@@ -14,8 +14,11 @@ namespace sm {
 hipError_t launch_forward(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                           const FieldPack& fp, int S, float* maps, double* phi_end,
                           double* em_end, hipStream_t st) {
+  if (fp.grid.alpha != nullptr)
+    return fp.ff ? launch_forward_va_ff(g, fa, ea, fp, S, maps, phi_end, em_end, st)
+                 : launch_forward_va(g, fa, ea, fp, S, maps, phi_end, nullptr, st);
   if (fp.ff) return launch_forward_ff(g, fa, ea, fp, S, maps, phi_end, em_end, st);
-  return launch_forward_t<false>(g, fa, ea, fp, S, maps, phi_end, nullptr, st);
+  return launch_forward_t<false, false>(g, fa, ea, fp, S, maps, phi_end, nullptr, st);
 }
 
 }  // namespace sm

@@ -10,7 +10,7 @@
 
 namespace sm {
 
-template <class F, int S, int MF, bool FF>
+template <class F, int S, int MF, bool FF, bool VA>
 __global__ __launch_bounds__(256) void k_forward(GeomArgs g, FreqArgs fa, EmitArgs ea, F fld,
                                                  float* __restrict__ maps,
                                                  double* __restrict__ phi_end,
@@ -21,53 +21,59 @@ __global__ __launch_bounds__(256) void k_forward(GeomArgs g, FreqArgs fa, EmitAr
   int64_t q = tid / S;
   const bool valid = q < g.npix;
   if (!valid) q = g.npix - 1;  // idle lanes march a real sightline, results dropped
-  fwd_lane<F, S, MF, FF>(g, fa, ea, fld, q, sub, valid, maps, MapAddr{g.npix, 0}, phi_end, em_end);
+  fwd_lane<F, S, MF, FF, VA>(g, fa, ea, fld, q, sub, valid, maps, MapAddr{g.npix, 0}, phi_end,
+                             em_end);
 }
 
-template <bool FF, class F, int S>
+template <bool FF, bool VA, class F, int S>
 static hipError_t fwd_mf(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
                          float* maps, double* phi_end, double* em_end, hipStream_t st) {
   const int64_t nb = march_blocks(g.npix, S);
   const dim3 grid((unsigned)nb), block(256);
   if (fa.n_freq <= 1)
-    k_forward<F, S, 1, FF><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
+    k_forward<F, S, 1, FF, VA><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
   else if (std::is_same_v<F, GridL> && fa.n_freq == 3)  // the three-frequency gridded maps
-    k_forward<F, S, 3, FF><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
+    k_forward<F, S, 3, FF, VA><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
   else if (fa.n_freq <= 4)
-    k_forward<F, S, 4, FF><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
+    k_forward<F, S, 4, FF, VA><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
   else
-    k_forward<F, S, 16, FF><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
+    k_forward<F, S, 16, FF, VA><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
   return hipGetLastError();
 }
 
-template <bool FF, class F>
+template <bool FF, bool VA, class F>
 static hipError_t fwd_s(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
                         int S, float* maps, double* phi_end, double* em_end, hipStream_t st) {
   switch (S) {
-    case 1: return fwd_mf<FF, F, 1>(g, fa, ea, f, maps, phi_end, em_end, st);
-    case 4: return fwd_mf<FF, F, 4>(g, fa, ea, f, maps, phi_end, em_end, st);
-    case 16: return fwd_mf<FF, F, 16>(g, fa, ea, f, maps, phi_end, em_end, st);
-    case 64: return fwd_mf<FF, F, 64>(g, fa, ea, f, maps, phi_end, em_end, st);
+    case 1: return fwd_mf<FF, VA, F, 1>(g, fa, ea, f, maps, phi_end, em_end, st);
+    case 4: return fwd_mf<FF, VA, F, 4>(g, fa, ea, f, maps, phi_end, em_end, st);
+    case 16: return fwd_mf<FF, VA, F, 16>(g, fa, ea, f, maps, phi_end, em_end, st);
+    case 64: return fwd_mf<FF, VA, F, 64>(g, fa, ea, f, maps, phi_end, em_end, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <bool FF>
+// VA: gridded spectral index (grid fields only).
+template <bool FF, bool VA>
 static hipError_t launch_forward_t(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                                    const FieldPack& fp, int S, float* maps, double* phi_end,
                                    double* em_end, hipStream_t st) {
-  switch (fp.kind) {
-    case kModel16: return fwd_s<FF>(g, fa, ea, Model16{fp.m16}, S, maps, phi_end, em_end, st);
-    case kGrid:
-      if (fp.grid_path == kGridShared)
-        return fwd_s<FF>(g, fa, ea, GridL{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
-      if (fp.grid_path != kGridGlobal)
-        return fwd_s<FF>(g, fa, ea, GridB{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
-      return fwd_s<FF>(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
-    case kSphere: return fwd_s<FF>(g, fa, ea, Sphere{fp.sph}, S, maps, phi_end, em_end, st);
-    case kWmap: return fwd_s<FF>(g, fa, ea, Wmap{fp.wmap}, S, maps, phi_end, em_end, st);
-    default: return hipErrorInvalidValue;
+  if (fp.kind == kGrid) {
+    if (fp.grid_path == kGridShared)
+      return fwd_s<FF, VA>(g, fa, ea, GridL{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
+    if (fp.grid_path != kGridGlobal)
+      return fwd_s<FF, VA>(g, fa, ea, GridB{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
+    return fwd_s<FF, VA>(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, maps, phi_end, em_end, st);
   }
+  if constexpr (!VA) {
+    switch (fp.kind) {
+      case kModel16: return fwd_s<FF, VA>(g, fa, ea, Model16{fp.m16}, S, maps, phi_end, em_end, st);
+      case kSphere: return fwd_s<FF, VA>(g, fa, ea, Sphere{fp.sph}, S, maps, phi_end, em_end, st);
+      case kWmap: return fwd_s<FF, VA>(g, fa, ea, Wmap{fp.wmap}, S, maps, phi_end, em_end, st);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace sm

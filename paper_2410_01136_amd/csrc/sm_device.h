@@ -380,6 +380,22 @@ struct Grid {
     return eval_at(g, r, 0.0);
   }
 
+  // Gridded CR spectral index at distance s (trilinear; alpha_ref outside the
+  // grid box, where the fields vanish).
+  __device__ inline double alpha_at(const GeomArgs& g, const Ray& r, double s,
+                                    double alpha_ref) const {
+    // in FP64: the emissivity's exponent and prefactors amplify an error in
+    // alpha about tenfold
+    const Cell c = cell_at(g, r, s);
+    const int64_t sy = p.n[0], sz = (int64_t)p.n[0] * p.n[1];
+    const float* a = p.alpha;
+    const double tx = c.tx, ty = c.ty, tz = c.tz;
+    auto lx = [&](int64_t o) { return (double)a[o] + tx * ((double)a[o + 1] - (double)a[o]); };
+    const double y0 = lx(c.base) + ty * (lx(c.base + sy) - lx(c.base));
+    const double y1 = lx(c.base + sz) + ty * (lx(c.base + sy + sz) - lx(c.base + sz));
+    return c.inside ? y0 + tz * (y1 - y0) : alpha_ref;
+  }
+
   // theta-gradient of a grid field: only an analytic N0 depends on theta
   __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
                                 double* tb) const {
@@ -939,6 +955,37 @@ struct Sphere {
 // The physical prefactors (Gamma functions, nu, units, Rayleigh-Jeans) are
 // applied per frequency at the end.
 // ---------------------------------------------------------------------------
+// ln Gamma(x) for x > 0: Stirling's series with three correction terms after
+// shifting the argument by 6 (truncation error below 3e-9 for x >= 0.08).
+__device__ inline double lngamma_pos(double x) {
+  const double y = x + 6.0, iy = 1.0 / y, iy2 = iy * iy;
+  const double p = x * (x + 1.0) * (x + 2.0) * (x + 3.0) * (x + 4.0) * (x + 5.0);
+  return (y - 0.5) * log(y) - y + 0.9189385332046728 +
+         iy * (1.0 / 12.0 - iy2 * (1.0 / 360.0 - iy2 * (1.0 / 1260.0))) - log(p);
+}
+
+// Emission prefactors at a local spectral index a (gridded alpha): the
+// exponent step G(a) - G(alpha_ref) shared by all frequencies, and the
+// per-frequency ratio sI(a) / sI(alpha_ref) = 2^(k1l2 (a - alpha_ref) + dg log2 e).
+struct VaStep {
+  float eI;    // (a + 1) / 4
+  double dg;   // G(a) - G(alpha_ref)
+  float prat;  // [(a + 1) / (a + 7/3)] / [(alpha_ref + 1) / (alpha_ref + 7/3)]
+};
+__device__ inline VaStep va_step(double a, const EmitArgs& ea) {
+  VaStep v;
+  v.eI = (float)(0.25 * (a + 1.0));
+  v.dg = lngamma_pos(0.25 * a - 1.0 / 12.0) + lngamma_pos(0.25 * a + 19.0 / 12.0) -
+         log(a + 1.0) - ea.va_gref;
+  v.prat = (float)((a + 1.0) / ((a + 7.0 / 3.0) * ea.va_pref));
+  return v;
+}
+__device__ inline float va_ratio(const VaStep& v, double k1l2, double a, const EmitArgs& ea) {
+  const double x = k1l2 * (a - ea.va_alpha_ref) + v.dg * 1.4426950408889634;
+  const double n = floor(x);
+  return ldexpf(exp2f((float)(x - n)), (int)n);
+}
+
 struct Emit {
   float u, zr, zi;
 };

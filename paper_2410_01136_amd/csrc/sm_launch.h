@@ -40,6 +40,12 @@ hipError_t launch_forward(const GeomArgs& g, const FreqArgs& fa, const EmitArgs&
 hipError_t launch_forward_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                              const FieldPack& fp, int S, float* maps, double* phi_end,
                              double* em_end, hipStream_t st);
+hipError_t launch_forward_va(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                             const FieldPack& fp, int S, float* maps, double* phi_end,
+                             double* em_end, hipStream_t st);
+hipError_t launch_forward_va_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                                const FieldPack& fp, int S, float* maps, double* phi_end,
+                                double* em_end, hipStream_t st);
 
 // partials: [march_blocks(npix, S)][16] doubles; dtheta: device double[16]
 hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
@@ -50,6 +56,14 @@ hipError_t launch_adjoint_ff(const GeomArgs& g, const FreqArgs& fa, const EmitAr
                              const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
                              const double* em_end, double* partials, double* dtheta, float* gbn,
                              float* gc, hipStream_t st);
+hipError_t launch_adjoint_va(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                             const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
+                             const double* em_end, double* partials, double* dtheta, float* gbn,
+                             float* gc, hipStream_t st);
+hipError_t launch_adjoint_va_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                                const FieldPack& fp, int S, const float* dmaps,
+                                const double* phi_end, const double* em_end, double* partials,
+                                double* dtheta, float* gbn, float* gc, hipStream_t st);
 
 hipError_t launch_chi2(int64_t n_pix, int n_maps, const float* maps, const float* target,
                        const double* inv_s2, float* dmaps, double* chi2, double* partials,

@@ -38,6 +38,7 @@ struct WmapArgs {
 struct GridArgs {
   const float4* bn;  // [nz][ny][nx] x (Bx, By, Bz, n_e)
   const float* c;    // [nz][ny][nx] N0 or nullptr
+  const float* alpha;  // [nz][ny][nx] CR spectral index or nullptr (theta[12])
   int32_t n[3];
   double lo[3], inv_h[3], umax[3];  // umax = n - 1
   // 32-bit buffer addressing (grids under 4 GiB): sizes in bytes and the byte
@@ -94,11 +95,19 @@ struct FreqArgs {
   // cm^-6), and the free-free term of T_I = tff * dkpc * sum e^-tau n_e^2
   double kffl2[kMaxFreq];
   double tff[kMaxFreq];
+  // gridded alpha: log2(e) d ln sI / d alpha without the Gamma-function part
+  double va_k1l2[kMaxFreq];
 };
 
 struct EmitArgs {
   int32_t alpha3;  // alpha == 3 exactly: integer powers, no log/exp
   float eI;        // (alpha + 1) / 4
+  // gridded alpha: the prefactors above are those of alpha_ref = theta[12];
+  // at a local alpha they scale by exp(k1_f (alpha - alpha_ref) + G(alpha) -
+  // G(alpha_ref)), G = ln Gamma(alpha/4 - 1/12) + ln Gamma(alpha/4 + 19/12)
+  // - ln(alpha + 1), and j_P / j_I by (alpha + 1) / (alpha + 7/3)
+  double va_alpha_ref, va_gref;
+  double va_pref;  // (alpha_ref + 1) / (alpha_ref + 7/3)
 };
 
 }  // namespace sm

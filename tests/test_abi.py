@@ -247,3 +247,19 @@ def test_free_free_arguments_checked_on_host(sm):
     mlp = sm.Field(sm.FIELD_MLP, I.THETA0, te_k=8000.0)
     st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(mlp.s), 0x1000, None, 0, None)
     assert st == sm.SYN_EUNSUPPORTED
+
+
+def test_grid_alpha_checked_on_host(sm):
+    g = _geom(sm)
+    f = sm.model16(I.THETA0)
+    f.s.grid_alpha = 0x1000
+    st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, None)
+    assert st == sm.SYN_EINVAL and "grid_alpha" in sm.syn_last_error().decode()
+    f = sm.Field(sm.FIELD_GRID, I.THETA0)
+    f.s.grid_bn = 0x1000
+    f.s.grid_n[:] = [4, 4, 4]
+    f.s.grid_lo_kpc[:] = [-1, -1, -1]
+    f.s.grid_hi_kpc[:] = [1, 1, 1]
+    f.s.grid_alpha = 0x1002
+    st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, None)
+    assert st == sm.SYN_EINVAL and "grid_alpha" in sm.syn_last_error().decode()
