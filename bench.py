@@ -407,11 +407,12 @@ def bench_wmap(sm, I, np, torch, tune, args):
 
 
 def bench_free_free(sm, I, np, torch, args, grid_field):
-    """Free-free emission and absorption (T_e = 8000 K, the thermal electrons of
-    the fields): the headline gridded workload (N_side 256, 512 steps, 256^3
-    nodes) moved to {150, 300, 600} MHz, and the N_side 64 / 768 step analytic
-    theta-gradient workload (forward + adjoint) at the same frequencies, each
-    timed with and without free-free."""
+    """The physics variants: free-free emission and absorption (T_e = 8000 K,
+    the thermal electrons of the fields) on the headline gridded workload
+    (N_side 256, 512 steps, 256^3 nodes) moved to {150, 300, 600} MHz and on the
+    N_side 64 / 768 step analytic theta-gradient workload (forward + adjoint)
+    at the same frequencies, each timed with and without; and the headline
+    forward with a gridded spectral index, timed with and without."""
     freqs = (0.15e9, 0.3e9, 0.6e9)
     te = 8000.0
     g = I.geometry("C1", freqs_hz=freqs)
@@ -437,9 +438,26 @@ def bench_free_free(sm, I, np, torch, args, grid_field):
 
         wall, _ = time_launches(fwd_adj, args.steps, args.warmup)
         theta_ms["free_free" if t else "plain"] = round(wall, 4)
+    # a gridded spectral index on the same 256^3 nodes (2.4 in the plane,
+    # steepening by 0.225 per kpc of |z|), at the headline frequencies
+    nz, ny, nx = grid_field.grid_c.shape
+    z = torch.linspace(I.BOX_LO[2], I.BOX_HI[2], nz, device="cuda").view(nz, 1, 1)
+    alpha = (2.4 + 0.225 * z.abs()).expand(nz, ny, nx).contiguous()
+    g1 = I.geometry("C1")
+    geom1 = sm.geom_from(g1)
+    maps1 = torch.empty((len(g1.freqs_hz), 3, g1.npix), dtype=torch.float32, device="cuda")
+    va = sm.grid(grid_field.theta, grid_field.grid_bn, grid_field.grid_c, I.BOX_LO, I.BOX_HI,
+                 grid_alpha=alpha)
+    alpha_ms = {}
+    for name, f in (("plain", grid_field), ("alpha_grid", va)):
+        _, ev = time_launches(lambda: sm.forward(geom1, f, maps=maps1), args.steps, args.warmup)
+        alpha_ms[name] = round(ev, 4)
     res = {
         "workload": "T_e 8000 K; 256^3 grid at N_side 256 x 512 steps and analytic model at "
-                    "N_side 64 x 768 steps (forward + theta-adjoint), both at {150, 300, 600} MHz",
+                    "N_side 64 x 768 steps (forward + theta-adjoint), both at {150, 300, 600} MHz; "
+                    "gridded spectral index on the 256^3 headline forward at {1, 2.3, 5} GHz",
+        "alpha_grid_forward_ms": alpha_ms,
+        "alpha_grid_over_plain": round(alpha_ms["alpha_grid"] / alpha_ms["plain"], 3),
         "grid_forward_ms": grid_ms,
         "grid_forward_ff_sightline_steps_per_s": float(f"{g.units / (grid_ms['free_free'] * 1e-3):.4e}"),
         "grid_read_path": grid_read_path(sm, g.npix),

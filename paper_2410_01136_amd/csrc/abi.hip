@@ -318,8 +318,17 @@ sm::EmitArgs emit_args(double alpha) {
   e.eI = (float)((alpha + 1.0) / 4.0);
   // reference point of a gridded alpha: the prefactors above belong to theta[12]
   e.va_alpha_ref = alpha;
-  e.va_gref = lgamma(alpha / 4.0 - 1.0 / 12.0) + lgamma(alpha / 4.0 + 19.0 / 12.0) - log(alpha + 1.0);
   e.va_pref = (alpha + 1.0) / (alpha + 7.0 / 3.0);
+  const double x[2] = {alpha / 4.0 - 1.0 / 12.0, alpha / 4.0 + 19.0 / 12.0};
+  e.va_q = alpha + 1.0;
+  for (int k = 0; k < 2; ++k) {
+    const double y = x[k] + 6.0, iy = 1.0 / y, iy2 = iy * iy;
+    e.va_y[k] = y;
+    e.va_iy[k] = iy;
+    e.va_ly[k] = log(y);
+    e.va_ser[k] = iy * (1.0 / 12.0 - iy2 * (1.0 / 360.0 - iy2 * (1.0 / 1260.0)));
+    e.va_q *= x[k] * (x[k] + 1.0) * (x[k] + 2.0) * (x[k] + 3.0) * (x[k] + 4.0) * (x[k] + 5.0);
+  }
   return e;
 }
 

@@ -955,28 +955,41 @@ struct Sphere {
 // The physical prefactors (Gamma functions, nu, units, Rayleigh-Jeans) are
 // applied per frequency at the end.
 // ---------------------------------------------------------------------------
-// ln Gamma(x) for x > 0: Stirling's series with three correction terms after
-// shifting the argument by 6 (truncation error below 3e-9 for x >= 0.08).
-__device__ inline double lngamma_pos(double x) {
-  const double y = x + 6.0, iy = 1.0 / y, iy2 = iy * iy;
-  const double p = x * (x + 1.0) * (x + 2.0) * (x + 3.0) * (x + 4.0) * (x + 5.0);
-  return (y - 0.5) * log(y) - y + 0.9189385332046728 +
-         iy * (1.0 / 12.0 - iy2 * (1.0 / 360.0 - iy2 * (1.0 / 1260.0))) - log(p);
-}
-
 // Emission prefactors at a local spectral index a (gridded alpha): the
-// exponent step G(a) - G(alpha_ref) shared by all frequencies, and the
+// exponent step dg = G(a) - G(alpha_ref) shared by all frequencies, with
+// G(a) = ln Gamma(a/4 - 1/12) + ln Gamma(a/4 + 19/12) - ln(a + 1), and the
 // per-frequency ratio sI(a) / sI(alpha_ref) = 2^(k1l2 (a - alpha_ref) + dg log2 e).
+//
+// Each ln Gamma(x) is Stirling's series with three correction terms at
+// y = x + 6 (truncation error below 3e-9 for x >= 0.08) less ln of the shift
+// product.  The difference to alpha_ref is taken term by term in FP64 with the
+// reference values from the host, so that the only logarithms left are those
+// of ratios near 1 (ln y = ln y_ref + log1p((y - y_ref) / y_ref) and
+// ln(Q / Q_ref)), which FP32 evaluates to a few 1e-8 absolute.
 struct VaStep {
   float eI;    // (a + 1) / 4
   double dg;   // G(a) - G(alpha_ref)
   float prat;  // [(a + 1) / (a + 7/3)] / [(alpha_ref + 1) / (alpha_ref + 7/3)]
 };
+__device__ inline double stirling_tail(double iy) {
+  const double iy2 = iy * iy;
+  return iy * (1.0 / 12.0 - iy2 * (1.0 / 360.0 - iy2 * (1.0 / 1260.0)));
+}
 __device__ inline VaStep va_step(double a, const EmitArgs& ea) {
   VaStep v;
   v.eI = (float)(0.25 * (a + 1.0));
-  v.dg = lngamma_pos(0.25 * a - 1.0 / 12.0) + lngamma_pos(0.25 * a + 19.0 / 12.0) -
-         log(a + 1.0) - ea.va_gref;
+  const double x[2] = {0.25 * a - 1.0 / 12.0, 0.25 * a + 19.0 / 12.0};
+  double dg = 0.0, q = a + 1.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double y = x[k] + 6.0;
+    const double dy = y - ea.va_y[k];
+    const double l1 = (double)log1pf((float)(dy * ea.va_iy[k]));  // ln(y / y_ref)
+    // S(y) - S(y_ref), S(y) = (y - 1/2) ln y - y + ln(2 pi) / 2 + tail(1/y)
+    dg += (y - 0.5) * l1 + dy * (ea.va_ly[k] - 1.0) + stirling_tail(1.0 / y) - ea.va_ser[k];
+    q *= x[k] * (x[k] + 1.0) * (x[k] + 2.0) * (x[k] + 3.0) * (x[k] + 4.0) * (x[k] + 5.0);
+  }
+  v.dg = dg - (double)logf((float)(q / ea.va_q));
   v.prat = (float)((a + 1.0) / ((a + 7.0 / 3.0) * ea.va_pref));
   return v;
 }

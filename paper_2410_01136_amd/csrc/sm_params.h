@@ -106,8 +106,13 @@ struct EmitArgs {
   // at a local alpha they scale by exp(k1_f (alpha - alpha_ref) + G(alpha) -
   // G(alpha_ref)), G = ln Gamma(alpha/4 - 1/12) + ln Gamma(alpha/4 + 19/12)
   // - ln(alpha + 1), and j_P / j_I by (alpha + 1) / (alpha + 7/3)
-  double va_alpha_ref, va_gref;
+  double va_alpha_ref;
   double va_pref;  // (alpha_ref + 1) / (alpha_ref + 7/3)
+  // G at alpha_ref in the form the device differences against: the shifted
+  // Gamma arguments y = x + 6 (x = alpha/4 - 1/12 and alpha/4 + 19/12), 1/y,
+  // ln y and the Stirling correction terms at them, and the product
+  // Q = x1 (x1 + 1) .. (x1 + 5) x2 (x2 + 1) .. (x2 + 5) (alpha + 1)
+  double va_y[2], va_iy[2], va_ly[2], va_ser[2], va_q;
 };
 
 }  // namespace sm
