@@ -174,3 +174,27 @@ def test_theta_gradient_with_analytic_cr(sm, orc):
     print("alpha grid theta 9-11: max scaled err / scale", err.max() / scale, flush=True)
     assert np.all(err <= 1e-3 * scale)
     assert dth[12] == 0.0
+
+
+@pytest.mark.parametrize("n_steps,S", [(1, 16), (3, 64), (29, 4)])
+def test_tiny_and_ragged_schedules(sm, orc, lanes, n_steps, S):
+    import torch
+    g = I.geometry("C2", nside=2, n_steps=n_steps, freqs_hz=(1.0e9, 1.4e9))
+    bn, c, alpha = fields(orc, n=(17, 17, 9))
+    lanes(sm.FIELD_GRID, S)
+    lanes(sm.FIELD_GRID, S, kernel=1)
+    field = gpu_field(sm, bn, c, alpha)
+    geom = sm.geom_from(g)
+    ws = sm.alloc_workspace(geom, field)
+    maps = sm.forward(geom, field, ws=ws)
+    dm = I.cotangents((2, 3, g.npix), seed=53)
+    dbn = torch.zeros_like(field.grid_bn)
+    sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws, want_theta=False, dgrid_bn=dbn)
+    torch.cuda.synchronize()
+    of = ofield(orc, bn, c, alpha)
+    check(maps.cpu().numpy(), orc.forward(oracle_geom(orc, g), of), f"alpha n={n_steps} S={S}")
+    _, rbn, _ = orc.adjoint(oracle_geom(orc, g), of, dm.astype(np.float64), want_grid=True)
+    a = dbn.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(a - rbn) / np.linalg.norm(rbn)
+    print(f"alpha grid n={n_steps} S={S}: rel L2 {rel:.2e}", flush=True)
+    assert rel <= 1e-3

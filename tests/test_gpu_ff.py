@@ -190,3 +190,45 @@ def test_grid_gradient(sm, orc, lanes, S):
         cos = (a * b).sum() / (np.linalg.norm(a) * np.linalg.norm(b))
         print(f"grid ff S={S} {lab}: rel L2 {rel:.2e}, 1-cos {1 - cos:.2e}", flush=True)
         assert rel <= 1e-3 and cos >= 1 - 1e-6
+
+
+@pytest.mark.parametrize("n_steps,S", [(1, 16), (1, 1), (3, 64), (17, 4)])
+def test_tiny_and_ragged_schedules(sm, orc, lanes, n_steps, S):
+    # one step (the attenuation of a lone midpoint is e^{-tau/2}), fewer steps
+    # than lanes, a ragged last chunk; forward and theta-gradient
+    g = I.geometry("C0", nside=1, n_steps=n_steps, freqs_hz=FREQS_FF, r_max=2.0)
+    lanes(sm.FIELD_MODEL16, S)
+    lanes(sm.FIELD_MODEL16, S, kernel=1)
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.MODEL16, THETA_FF, te_k=TE))
+    check(gpu_maps(sm, g, sm.model16(THETA_FF).with_te(TE)), ref, f"ff n={n_steps} S={S}")
+    dm = I.cotangents((2, 3, g.npix), seed=44)
+    got = _theta_grad(sm, g, sm.model16(THETA_FF).with_te(TE), dm)
+    rth, _, _ = orc.adjoint(oracle_geom(orc, g), orc.Field(orc.MODEL16, THETA_FF, te_k=TE),
+                            dm.astype(np.float64))
+    assert_theta_close(got, rth, THETA_FF, f"ff grad n={n_steps} S={S}")
+
+
+@pytest.mark.parametrize("S", [1, 64])
+def test_grid_gradient_few_steps(sm, orc, lanes, S):
+    # 5 steps over 64 pieces: most pieces empty, the rest one step long
+    import torch
+    g = I.geometry("C2", nside=2, n_steps=5, freqs_hz=FREQS_FF, r_max=3.0)
+    bn, c = dense_grid(orc, n=(9, 9, 5))
+    dm = I.cotangents((2, 3, g.npix), seed=45)
+    lanes(sm.FIELD_GRID, S, kernel=1)
+    bn_t, c_t = torch.from_numpy(bn).cuda(), torch.from_numpy(c).cuda()
+    field = sm.grid(THETA_FF, bn_t, c_t, I.BOX_LO, I.BOX_HI).with_te(TE)
+    geom = sm.geom_from(g)
+    ws = sm.alloc_workspace(geom, field)
+    sm.forward(geom, field, ws=ws)
+    dbn, dc = torch.zeros_like(bn_t), torch.zeros_like(c_t)
+    sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws, want_theta=False, dgrid_bn=dbn,
+               dgrid_c=dc)
+    torch.cuda.synchronize()
+    of = orc.Field(orc.GRID, THETA_FF, grid_bn=bn, grid_c=c, grid_lo=I.BOX_LO, grid_hi=I.BOX_HI,
+                   te_k=TE)
+    _, rbn, rc = orc.adjoint(oracle_geom(orc, g), of, dm.astype(np.float64), want_grid=True)
+    for a, b in ((dbn.cpu().numpy().astype(np.float64), rbn), (dc.cpu().numpy().astype(np.float64), rc)):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print(f"few-step grid ff S={S}: rel L2 {rel:.2e}", flush=True)
+        assert rel <= 1e-3
