@@ -320,15 +320,16 @@ sm::EmitArgs emit_args(double alpha) {
   e.va_alpha_ref = alpha;
   e.va_pref = (alpha + 1.0) / (alpha + 7.0 / 3.0);
   const double x[2] = {alpha / 4.0 - 1.0 / 12.0, alpha / 4.0 + 19.0 / 12.0};
-  e.va_q = alpha + 1.0;
+  double q = alpha + 1.0;
   for (int k = 0; k < 2; ++k) {
     const double y = x[k] + 6.0, iy = 1.0 / y, iy2 = iy * iy;
     e.va_y[k] = y;
     e.va_iy[k] = iy;
     e.va_ly[k] = log(y);
     e.va_ser[k] = iy * (1.0 / 12.0 - iy2 * (1.0 / 360.0 - iy2 * (1.0 / 1260.0)));
-    e.va_q *= x[k] * (x[k] + 1.0) * (x[k] + 2.0) * (x[k] + 3.0) * (x[k] + 4.0) * (x[k] + 5.0);
+    q *= x[k] * (x[k] + 1.0) * (x[k] + 2.0) * (x[k] + 3.0) * (x[k] + 4.0) * (x[k] + 5.0);
   }
+  e.va_iq = 1.0 / q;
   return e;
 }
 

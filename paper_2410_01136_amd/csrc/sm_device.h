@@ -962,41 +962,41 @@ struct Sphere {
 //
 // Each ln Gamma(x) is Stirling's series with three correction terms at
 // y = x + 6 (truncation error below 3e-9 for x >= 0.08) less ln of the shift
-// product.  The difference to alpha_ref is taken term by term in FP64 with the
-// reference values from the host, so that the only logarithms left are those
-// of ratios near 1 (ln y = ln y_ref + log1p((y - y_ref) / y_ref) and
-// ln(Q / Q_ref)), which FP32 evaluates to a few 1e-8 absolute.
+// product.  The difference to alpha_ref is taken term by term against
+// reference values from the host: ln y = ln y_ref + log1p((y - y_ref) / y_ref)
+// and ln(Q / Q_ref) with Q formed in FP64, so every term left is of size <~ 1
+// and FP32 gives it to a few 1e-8 absolute.
 struct VaStep {
   float eI;    // (a + 1) / 4
   double dg;   // G(a) - G(alpha_ref)
   float prat;  // [(a + 1) / (a + 7/3)] / [(alpha_ref + 1) / (alpha_ref + 7/3)]
 };
-__device__ inline double stirling_tail(double iy) {
-  const double iy2 = iy * iy;
-  return iy * (1.0 / 12.0 - iy2 * (1.0 / 360.0 - iy2 * (1.0 / 1260.0)));
-}
 __device__ inline VaStep va_step(double a, const EmitArgs& ea) {
   VaStep v;
   v.eI = (float)(0.25 * (a + 1.0));
-  const double x[2] = {0.25 * a - 1.0 / 12.0, 0.25 * a + 19.0 / 12.0};
-  double dg = 0.0, q = a + 1.0;
+  const double da = a - ea.va_alpha_ref;
+  const float dy = (float)(0.25 * da);  // y - y_ref, the same for both arguments
+  double q = a + 1.0;
+  float dgf = 0.0f;  // the parts of dg of size <~ 1, each to a few 1e-8 in FP32
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const double y = x[k] + 6.0;
-    const double dy = y - ea.va_y[k];
-    const double l1 = (double)log1pf((float)(dy * ea.va_iy[k]));  // ln(y / y_ref)
+    const double x = k == 0 ? 0.25 * a - 1.0 / 12.0 : 0.25 * a + 19.0 / 12.0;
+    const float y = (float)(x + 6.0);
+    const float l1 = log1pf(dy * (float)ea.va_iy[k]);  // ln(y / y_ref)
+    const float iy = frcp(y), iy2 = iy * iy;
+    const float tail = iy * (1.0f / 12.0f - iy2 * (1.0f / 360.0f - iy2 * (1.0f / 1260.0f)));
     // S(y) - S(y_ref), S(y) = (y - 1/2) ln y - y + ln(2 pi) / 2 + tail(1/y)
-    dg += (y - 0.5) * l1 + dy * (ea.va_ly[k] - 1.0) + stirling_tail(1.0 / y) - ea.va_ser[k];
-    q *= x[k] * (x[k] + 1.0) * (x[k] + 2.0) * (x[k] + 3.0) * (x[k] + 4.0) * (x[k] + 5.0);
+    dgf += (y - 0.5f) * l1 + dy * (float)(ea.va_ly[k] - 1.0) + (tail - (float)ea.va_ser[k]);
+    q *= x * (x + 1.0) * (x + 2.0) * (x + 3.0) * (x + 4.0) * (x + 5.0);
   }
-  v.dg = dg - (double)logf((float)(q / ea.va_q));
-  v.prat = (float)((a + 1.0) / ((a + 7.0 / 3.0) * ea.va_pref));
+  v.dg = (double)dgf - (double)logf((float)(q * ea.va_iq));
+  v.prat = (float)(a + 1.0) * frcp((float)((a + 7.0 / 3.0) * ea.va_pref));
   return v;
 }
 __device__ inline float va_ratio(const VaStep& v, double k1l2, double a, const EmitArgs& ea) {
   const double x = k1l2 * (a - ea.va_alpha_ref) + v.dg * 1.4426950408889634;
   const double n = floor(x);
-  return ldexpf(exp2f((float)(x - n)), (int)n);
+  return ldexpf(fexp2((float)(x - n)), (int)n);
 }
 
 struct Emit {

@@ -112,7 +112,7 @@ struct EmitArgs {
   // Gamma arguments y = x + 6 (x = alpha/4 - 1/12 and alpha/4 + 19/12), 1/y,
   // ln y and the Stirling correction terms at them, and the product
   // Q = x1 (x1 + 1) .. (x1 + 5) x2 (x2 + 1) .. (x2 + 5) (alpha + 1)
-  double va_y[2], va_iy[2], va_ly[2], va_ser[2], va_q;
+  double va_y[2], va_iy[2], va_ly[2], va_ser[2], va_iq;  // va_iq = 1 / Q(alpha_ref)
 };
 
 }  // namespace sm
