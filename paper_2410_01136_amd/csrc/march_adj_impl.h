@@ -144,29 +144,27 @@ static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
   if (GR) {
     // the LDS of a CU is shared by the workgroups it runs at once (at most four
     // here, fewer when registers or the grid size allow no more)
-    static int n_cu = 0;
-    if (n_cu == 0) {
-      int dev = 0, v = 0;
-      if (hipGetDevice(&dev) == hipSuccess &&
-          hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-        n_cu = v;
-      else
-        n_cu = 256;
-    }
-    // workgroups one CU can hold with the smallest box (registers permitting)
-    static int by_regs = 0;
-    if (by_regs == 0) {
+    int n_cu = 0;
+    hipError_t e0 = device_cus(&n_cu);
+    if (e0 != hipSuccess) return e0;
+    // workgroups one CU can hold with the smallest box (registers permitting);
+    // the first call on a device also lifts the kernel's dynamic LDS limit there
+    static PerDevice regs_cache;
+    int by_regs = 0;
+    e0 = regs_cache.get(&by_regs, [](int* out) {
       const void* fn = reinterpret_cast<const void*>(&k_adjoint<F, S, MF, TH, GR, FF, VA>);
-      hipError_t ea2 = hipFuncSetAttribute(
+      hipError_t e = hipFuncSetAttribute(
           fn, hipFuncAttributeMaxDynamicSharedMemorySize,
           (int)((size_t)kAdjBoxNodesMax * 5 * sizeof(float) + kStageBytesPerBlock));
-      if (ea2 != hipSuccess) return ea2;
+      if (e != hipSuccess) return e;
       int nblk = 0;
-      ea2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &nblk, fn, 256, (size_t)adj_box_cap(4) * 5 * sizeof(float) + kStageBytesPerBlock);
-      if (ea2 != hipSuccess) return ea2;
-      by_regs = std::min(std::max(nblk, 1), 4);
-    }
+      if (e != hipSuccess) return e;
+      *out = std::min(std::max(nblk, 1), 4);
+      return hipSuccess;
+    });
+    if (e0 != hipSuccess) return e0;
     // the box takes the LDS share of one of the workgroups that run on a CU at once
     const int per_cu = (int)std::min<int64_t>(by_regs, (nb + n_cu - 1) / n_cu);
     cap = adj_box_cap(per_cu);

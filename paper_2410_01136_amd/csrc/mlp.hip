@@ -263,25 +263,27 @@ __global__ __launch_bounds__(512) void k_eval_mlp(MlpArgs m, int64_t n, const fl
 }
 
 static int mlp_grid_blocks() {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
-  }
+  int cus = 256;
+  if (device_cus(&cus) != hipSuccess) cus = 256;
   return cus;
+}
+
+// Lifts a kernel's dynamic LDS limit to the packed weights, once per device.
+static hipError_t mlp_lds_attr(const void* fn, PerDevice& done) {
+  int one = 0;
+  return done.get(&one, [fn](int* out) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMlpBytes);
+    *out = 1;
+    return e;
+  });
 }
 
 template <int MF>
 static hipError_t fwd_mlp_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                              const MlpArgs& m, float* maps, double* phi_end, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_forward_mlp<MF>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMlpBytes);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static PerDevice attr_done;
+  hipError_t e = mlp_lds_attr(reinterpret_cast<const void*>(k_forward_mlp<MF>), attr_done);
+  if (e != hipSuccess) return e;
   int64_t blocks = mlp_grid_blocks();
   const int64_t need = (g.npix + 7) / 8;
   if (blocks > need) blocks = need;
@@ -298,13 +300,9 @@ hipError_t launch_forward_mlp(const GeomArgs& g, const FreqArgs& fa, const EmitA
 
 hipError_t launch_eval_mlp(const MlpArgs& m, int64_t n, const float* xyz, float* out,
                            hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eval_mlp),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMlpBytes);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static PerDevice attr_done;
+  hipError_t e = mlp_lds_attr(reinterpret_cast<const void*>(k_eval_mlp), attr_done);
+  if (e != hipSuccess) return e;
   int64_t blocks = mlp_grid_blocks();
   const int64_t need = ((n + 63) / 64 + 7) / 8;
   if (blocks > need) blocks = need;

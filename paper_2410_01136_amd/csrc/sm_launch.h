@@ -3,9 +3,46 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "sm_params.h"
 
 namespace sm {
+
+// A value computed once per device on first use (a kernel attribute set, an
+// occupancy or CU count), safe to read from several host threads; 0 means not
+// yet computed.  The calling thread's current device is the one meant.
+struct PerDevice {
+  static constexpr int kMaxDevices = 64;
+  std::atomic<int> v[kMaxDevices] = {};
+  template <class Fn>  // Fn: hipError_t(int* out)
+  hipError_t get(int* out, Fn&& compute) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return compute(out);
+    const int have = v[dev].load(std::memory_order_acquire);
+    if (have != 0) {
+      *out = have;
+      return hipSuccess;
+    }
+    e = compute(out);
+    if (e == hipSuccess) v[dev].store(*out, std::memory_order_release);
+    return e;
+  }
+};
+
+// Multiprocessor (CU) count of the current device.
+inline hipError_t device_cus(int* out) {
+  static PerDevice cache;
+  return cache.get(out, [](int* o) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(o, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && *o < 1) *o = 1;
+    return e;
+  });
+}
 
 enum FieldKind { kModel16 = 0, kGrid = 1, kSphere = 2, kMlp = 3, kWmap = 4 };
 
