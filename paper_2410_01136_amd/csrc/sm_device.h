@@ -725,8 +725,10 @@ struct GridB : Grid {
 // one sightline mostly lie in the same cell, yet each lane's own corner loads
 // cost the texture-address unit one access per group of four lanes and per
 // cache line touched, which bounds the direct form.  Here the wavefront finds
-// its distinct cells (runs of equal cells along each sightline), loads every
-// distinct cell once -- eight lanes per cell for the (B, n_e) corners, four for
+// its distinct cells (runs of equal cells along each sightline; with 16 lanes
+// per sightline, a run in the cell the previous sightline holds at the same
+// step shares that sightline's slot -- the four sightlines of a wavefront are
+// neighbours on the sky), loads every distinct cell once -- eight lanes per cell for the (B, n_e) corners, four for
 // the N0 rows, so each group of four lanes reads one cell -- into LDS, and each
 // lane then reads its cell's corners from LDS.  Wavefronts with more distinct
 // cells than the LDS slots fall back to the direct reads.  Every lane of the
@@ -751,17 +753,43 @@ struct GridL : GridB {
     else
       prev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)node, 0x111 /* row_shr:1 */, 0xf, 0xf,
                                                    true);
-    const bool start = ((lane & (S - 1)) == 0) || (prev != node);
-    const uint64_t m = __builtin_amdgcn_ballot_w64(start);
+    const uint64_t mrun = __builtin_amdgcn_ballot_w64(((lane & (S - 1)) == 0) || (prev != node));
+    // the lanes that open a slot: every run start, except (16 lanes per
+    // sightline) a run that starts in the cell the previous sightline of the
+    // wavefront occupies at the same step -- neighbouring sightlines cross the
+    // same cells for most of their length, so that run reuses the slot
+    uint64_t m = mrun, mrg = 0;
+    if constexpr (S == 16) {
+      const uint32_t up = (uint32_t)__shfl_up((int)node, 16, 64);
+      mrg = mrun & __builtin_amdgcn_ballot_w64(lane >= 16 && up == node);
+      m = mrun & ~mrg;
+    }
     const int nsl = __builtin_popcountll(m);
     if (nsl > kSlots) return false;
-    // slot = runs starting at or below this lane, minus one; lane 0 always
-    // starts a run, so that is the count of starts among lanes 1..lane, i.e.
-    // the set bits of m >> 1 below this lane
+    // the slot opened at or before this lane: slots opened at or below it,
+    // minus one; lane 0 always opens one, so that is the count among lanes
+    // 1..lane, i.e. the set bits of m >> 1 below this lane.  It is the lane's
+    // slot when its run opened a slot.
     const uint64_t m1 = m >> 1;
-    const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
-    if (start) s_node[w][slot] = node;
+    int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
+    if (__builtin_amdgcn_inverse_ballot_w64(m)) s_node[w][slot] = node;
+    if constexpr (S == 16) {
+      // run start of each lane: the highest run start at or below it in its
+      // sightline's row (lane 16 k always starts one)
+      int rs = __builtin_amdgcn_inverse_ballot_w64(mrun) ? lane : 0;
+      rs = max(rs, __builtin_amdgcn_update_dpp(0, rs, 0x111 /* row_shr:1 */, 0xf, 0xf, true));
+      rs = max(rs, __builtin_amdgcn_update_dpp(0, rs, 0x112 /* row_shr:2 */, 0xf, 0xf, true));
+      rs = max(rs, __builtin_amdgcn_update_dpp(0, rs, 0x114 /* row_shr:4 */, 0xf, 0xf, true));
+      rs = max(rs, __builtin_amdgcn_update_dpp(0, rs, 0x118 /* row_shr:8 */, 0xf, 0xf, true));
+      // a merged run takes the slot of the lane 16 below its start (same cell);
+      // that lane's slot is final one pass after its own row's, so three
+      // passes settle the four sightlines
+      const bool from_up = (mrg >> rs) & 1ull;
+      const int src = from_up ? rs - 16 : lane;
+#pragma unroll
+      for (int it = 0; it < 3; ++it) slot = __shfl(slot, src, 64);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
