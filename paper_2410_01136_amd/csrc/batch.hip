@@ -76,12 +76,13 @@ __global__ __launch_bounds__(256) void k_batch_fwd(const BatchSet* __restrict__ 
   }
 }
 
+// (one lane per sightline, the plans' shape: held to 128 VGPRs, 4 wavefronts
+// per SIMD, which it fits without spilling)
 template <int S, bool WM>
-__global__ __launch_bounds__(256) void k_batch_adj(const BatchSet* __restrict__ sets, int n_sets,
-                                                   int n_items, unsigned int* counter,
-                                                   int64_t total, const float* __restrict__ dmaps,
-                                                   const double* __restrict__ phi_end,
-                                                   double* __restrict__ partials) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 4 : 1))) void
+k_batch_adj(const BatchSet* __restrict__ sets, int n_sets, int n_items, unsigned int* counter,
+            int64_t total, const float* __restrict__ dmaps, const double* __restrict__ phi_end,
+            double* __restrict__ partials) {
   using F = decltype(set_field<WM>(sets[0]));
   for (;;) {
     const int item = next_item(counter);

@@ -348,6 +348,11 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     E = phi_end[ma.off + ray.ring];
     if constexpr (FF) EM = em_end[ma.off + ray.ring];
   }
+  // this lane's theta cotangents, summed in FP32 over its steps (a few hundred
+  // terms at most) and added to the FP64 tb at the end
+  float tbf[THETA ? kNParam : 1];
+#pragma unroll
+  for (int k = 0; k < (THETA ? kNParam : 1); ++k) tbf[k] = 0.0f;
   constexpr int MPF = PF ? MF : 1;
   double accI = 0.0, accPr[MF], accPi[MF], accIf[MPF];
 #pragma unroll
@@ -497,13 +502,17 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     gv.n0 = eb.n0;
     if constexpr (THETA) {
       if (act) {
-        fld.vjp_at(g, ray, s, gv, tb);
-        if constexpr (ALPHA_GRAD) tb[12] += (double)eb.alpha;
+        fld.vjp_at(g, ray, s, gv, tbf);
+        if constexpr (ALPHA_GRAD) tbf[12] += eb.alpha;
       }
     }
     if constexpr (GRID) fld.accumulate_step(g, ray, s, gv, act, acc, gbn, gc);
   }
   if constexpr (GRID) fld.flush_all(acc, gbn, gc);
+  if constexpr (THETA) {
+#pragma unroll
+    for (int k = 0; k < kNParam; ++k) tb[k] += (double)tbf[k];
+  }
 
   if constexpr (ALPHA_GRAD) {
     // alpha also enters the per-frequency prefactors: d ln s / d alpha * this lane's share

@@ -151,6 +151,9 @@ constexpr float kRhoMin = 1e-3f;
 __device__ inline float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline float flog2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// the hardware square root (about 1 ulp) without the correctly rounded
+// expansion, which costs some fifteen more instructions
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // 16-parameter analytic model, evaluated in FP32 with host-prepared constants
 // (reciprocal scale lengths pre-multiplied by log2(e)).
@@ -158,7 +161,7 @@ struct Model16 {
   M16Args p;
 
   __device__ inline FV eval(float x, float y, float z) const {
-    const float rho = __builtin_sqrtf(x * x + y * y);
+    const float rho = fsqrt(x * x + y * y);
     const float rg = fmaxf(rho, kRhoMin);
     const float ir = frcp(rg);
     const float rhx = x * ir, rhy = y * ir;  // rho^
@@ -202,8 +205,9 @@ struct Model16 {
     return eval((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
                 (float)(g.r_obs[2] + s * r.nz));
   }
+  template <class T>
   __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
-                                double* tb) const {
+                                T* tb) const {
     vjp((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
         (float)(g.r_obs[2] + s * r.nz), gv, tb);
   }
@@ -212,13 +216,14 @@ struct Model16 {
 
   // cosmic-ray normalisation alone (grids with an analytic N0)
   __device__ inline float n0_at(float x, float y, float z) const {
-    const float rho = __builtin_sqrtf(x * x + y * y);
+    const float rho = fsqrt(x * x + y * y);
     return p.C0 * fexp2(-((rho - kRsun) * p.l2_invhr + fabsf(z) * p.l2_invhz));
   }
 
-  // Adds dL/dtheta given dL/d(B, n_e, N0) at (x, y, z).  tb[16] in FP64.
-  __device__ inline void vjp(float x, float y, float z, const FV& g, double* tb) const {
-    const float rho = __builtin_sqrtf(x * x + y * y);
+  // Adds dL/dtheta given dL/d(B, n_e, N0) at (x, y, z) to tb[16] (FP32 or FP64).
+  template <class T>
+  __device__ inline void vjp(float x, float y, float z, const FV& g, T* tb) const {
+    const float rho = fsqrt(x * x + y * y);
     const float rg = fmaxf(rho, kRhoMin);
     const float ir = frcp(rg);
     const float rhx = x * ir, rhy = y * ir;
@@ -240,40 +245,41 @@ struct Model16 {
     const float bp = cp * cc * gr - sp * cc * gf;               // . d dir / d psi
     const float bc = -sp * sc * gr - cp * sc * gf + cc * gz;    // . d dir / d chi
     const float disk = p.B0 * Ed * bd;
-    tb[0] += (double)(Ed * bd);
-    tb[1] += (double)(p.B0 * Ed * bp);
-    tb[2] += (double)(p.B0 * Ed * bp * lnr);
-    tb[3] += (double)(p.B0 * Ed * bc * tz);
-    tb[4] += (double)(disk * dR * p.invRB * p.invRB);
-    tb[5] += (double)(disk * az * p.invzB * p.invzB);
+    tb[0] += (T)(Ed * bd);
+    tb[1] += (T)(p.B0 * Ed * bp);
+    tb[2] += (T)(p.B0 * Ed * bp * lnr);
+    tb[3] += (T)(p.B0 * Ed * bc * tz);
+    tb[4] += (T)(disk * dR * p.invRB * p.invRB);
+    tb[5] += (T)(disk * az * p.invzB * p.invzB);
     const float Eh = fexp2(-(az * p.l2_invzH + dR * p.l2_invRH));
     const float zq = z * p.invzH;
-    tb[6] += (double)(zq * Eh * gf);
+    tb[6] += (T)(zq * Eh * gf);
     const float hal = p.BH0 * zq * Eh * gf;
-    tb[7] += (double)(p.BH0 * Eh * gf * (-z * p.invzH * p.invzH + zq * az * p.invzH * p.invzH));
-    tb[8] += (double)(hal * dR * p.invRH * p.invRH);
+    tb[7] += (T)(p.BH0 * Eh * gf * (-z * p.invzH * p.invzH + zq * az * p.invzH * p.invzH));
+    tb[8] += (T)(hal * dR * p.invRH * p.invRH);
     const float Ec = fexp2(-(dR * p.l2_invhr + az * p.l2_invhz));
     const float n0 = p.C0 * Ec;
-    tb[9] += (double)(g.n0 * Ec);
-    tb[10] += (double)(g.n0 * n0 * dR * p.invhr * p.invhr);
-    tb[11] += (double)(g.n0 * n0 * az * p.invhz * p.invhz);
+    tb[9] += (T)(g.n0 * Ec);
+    tb[10] += (T)(g.n0 * n0 * dR * p.invhr * p.invhr);
+    tb[11] += (T)(g.n0 * n0 * az * p.invhz * p.invhz);
     const float En = fexp2(-(az * p.l2_invhne + dR * p.l2_kappa));
     const float ne = p.n0 * En;
-    tb[13] += (double)(g.ne * En);
-    tb[14] += (double)(g.ne * ne * az * p.invhne * p.invhne);
-    tb[15] += (double)(-g.ne * ne * dR);
+    tb[13] += (T)(g.ne * En);
+    tb[14] += (T)(g.ne * ne * az * p.invhne * p.invhne);
+    tb[15] += (T)(-g.ne * ne * dR);
   }
 
   // dL/dtheta of the cosmic-ray normalisation alone (theta 9..11)
-  __device__ inline void vjp_n0(float x, float y, float z, float gn0, double* tb) const {
-    const float rho = __builtin_sqrtf(x * x + y * y);
+  template <class T>
+  __device__ inline void vjp_n0(float x, float y, float z, float gn0, T* tb) const {
+    const float rho = fsqrt(x * x + y * y);
     const float az = fabsf(z);
     const float dR = rho - kRsun;
     const float Ec = fexp2(-(dR * p.l2_invhr + az * p.l2_invhz));
     const float n0 = p.C0 * Ec;
-    tb[9] += (double)(gn0 * Ec);
-    tb[10] += (double)(gn0 * n0 * dR * p.invhr * p.invhr);
-    tb[11] += (double)(gn0 * n0 * az * p.invhz * p.invhz);
+    tb[9] += (T)(gn0 * Ec);
+    tb[10] += (T)(gn0 * n0 * dR * p.invhr * p.invhr);
+    tb[11] += (T)(gn0 * n0 * az * p.invhz * p.invhz);
   }
 };
 
@@ -397,8 +403,9 @@ struct Grid {
   }
 
   // theta-gradient of a grid field: only an analytic N0 depends on theta
+  template <class T>
   __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
-                                double* tb) const {
+                                T* tb) const {
     if (p.c == nullptr)
       cr.vjp_n0((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
                 (float)(g.r_obs[2] + s * r.nz), gv.n0, tb);
@@ -864,7 +871,7 @@ struct Wmap {
   WmapArgs p;
 
   __device__ inline FV eval(float x, float y, float z) const {
-    const float rho = __builtin_sqrtf(x * x + y * y);
+    const float rho = fsqrt(x * x + y * y);
     const bool ring = rho >= p.rin && rho <= p.rout && rho > 0.0f;
     const float ir = frcp(fmaxf(rho, 1e-30f));
     const float rhx = x * ir, rhy = y * ir;
@@ -899,9 +906,10 @@ struct Wmap {
     return eval_at(g, r, s);
   }
 
-  // Adds dL/dtheta given dL/d(B, n_e, N0) at (x, y, z); tb[16] in FP64.
-  __device__ inline void vjp(float x, float y, float z, const FV& g, double* tb) const {
-    const float rho = __builtin_sqrtf(x * x + y * y);
+  // Adds dL/dtheta given dL/d(B, n_e, N0) at (x, y, z) to tb[16] (FP32 or FP64).
+  template <class T>
+  __device__ inline void vjp(float x, float y, float z, const FV& g, T* tb) const {
+    const float rho = fsqrt(x * x + y * y);
     if (rho >= p.rin && rho <= p.rout && rho > 0.0f) {
       const float ir = frcp(rho);
       const float rhx = x * ir, rhy = y * ir;
@@ -917,10 +925,10 @@ struct Wmap {
       const float bd = cp * cc * gr + sp * cc * gf + sc * gz;
       const float bp = -sp * cc * gr + cp * cc * gf;
       const float bc = -cp * sc * gr - sp * sc * gf + cc * gz;
-      tb[0] += (double)bd;
-      tb[1] += (double)(p.b0 * bp);
-      tb[2] += (double)(p.b0 * bp * lnr);
-      tb[3] += (double)(p.b0 * bc * tz);
+      tb[0] += (T)bd;
+      tb[1] += (T)(p.b0 * bp);
+      tb[2] += (T)(p.b0 * bp * lnr);
+      tb[3] += (T)(p.b0 * bc * tz);
     }
     const float az = fabsf(z);
     const float ez = fexp2(-2.0f * kLog2e * az * p.invhz);
@@ -928,18 +936,19 @@ struct Wmap {
     const float E = fexp2(-rho * p.invhr * kLog2e) * 4.0f * ez * frcp(opz * opz);
     const float n0 = p.C0 * E;
     const float th = copysignf((1.0f - ez) * frcp(opz), z);  // tanh(z / h_z)
-    tb[9] += (double)(g.n0 * E);
-    tb[10] += (double)(g.n0 * n0 * rho * p.invhr * p.invhr);
-    tb[11] += (double)(g.n0 * n0 * 2.0f * th * z * p.invhz * p.invhz);
+    tb[9] += (T)(g.n0 * E);
+    tb[10] += (T)(g.n0 * n0 * rho * p.invhr * p.invhr);
+    tb[11] += (T)(g.n0 * n0 * 2.0f * th * z * p.invhz * p.invhz);
     const float dR = rho - kRsun;
     const float En = fexp2(-(az * p.l2_invhne + dR * p.l2_kappa));
     const float ne = p.n0 * En;
-    tb[13] += (double)(g.ne * En);
-    tb[14] += (double)(g.ne * ne * az * p.invhne * p.invhne);
-    tb[15] += (double)(-g.ne * ne * dR);
+    tb[13] += (T)(g.ne * En);
+    tb[14] += (T)(g.ne * ne * az * p.invhne * p.invhne);
+    tb[15] += (T)(-g.ne * ne * dR);
   }
+  template <class T>
   __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
-                                double* tb) const {
+                                T* tb) const {
     vjp((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
         (float)(g.r_obs[2] + s * r.nz), gv, tb);
   }
