@@ -354,9 +354,22 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 #pragma unroll
   for (int k = 0; k < (THETA ? kNParam : 1); ++k) tbf[k] = 0.0f;
   constexpr int MPF = PF ? MF : 1;
-  double accI = 0.0, accPr[MF], accPi[MF], accIf[MPF];
+  // Without per-frequency multipliers (the plain march) a step's cotangent
+  // rotations and this lane's alpha sums are FP32: each step's terms are FP32
+  // products, the sums over steps that need it (the Faraday cotangents) stay
+  // FP64.
+  using CT = std::conditional_t<PF, double, float>;
+  CT accI = 0, accPr[MF], accPi[MF];
+  double accIf[MPF];
+  float hrs[MF], his[MF], krs[MF], kis[MF];
 #pragma unroll
-  for (int f = 0; f < MF; ++f) accPr[f] = accPi[f] = 0.0;
+  for (int f = 0; f < MF; ++f) {
+    accPr[f] = accPi[f] = 0;
+    hrs[f] = (float)hr[f];
+    his[f] = (float)hi[f];
+    krs[f] = (float)kr[f];
+    kis[f] = (float)ki[f];
+  }
 #pragma unroll
   for (int f = 0; f < MPF; ++f) accIf[f] = 0.0;
 
@@ -410,7 +423,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     // H = sum_f mP_f h_f e^{2 pi i t_f};  K = sum_f mP_f k_f e^{2 pi i t_f}
     // (mI_f, mP_f the per-frequency multipliers of I and Q + iU: the free-free
     // attenuation and the local-alpha prefactor ratio; 1 without either)
-    double Hr = 0.0, Hi = 0.0, Kr = 0.0, Ki = 0.0;
+    CT Hr = 0, Hi = 0, Kr = 0, Ki = 0;
     double GIe = GI;  // sum_f mI_f gi_f
     double Cw = 0.0;  // FF: d L / d w of this segment's own free-free emission
     double X = 0.0;   // FF: d L / d EM at this midpoint
@@ -421,9 +434,9 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       if (f < fa.n_freq) {
         float sn, cs;
         sincos_turns(psid * fa.kappa[f], &sn, &cs);
-        const double hrf = hr[f] * cs - hi[f] * sn, hif = hr[f] * sn + hi[f] * cs;
-        const double krf = kr[f] * cs - ki[f] * sn, kif = kr[f] * sn + ki[f] * cs;
         if constexpr (PF) {
+          const double hrf = hr[f] * cs - hi[f] * sn, hif = hr[f] * sn + hi[f] * cs;
+          const double krf = kr[f] * cs - ki[f] * sn, kif = kr[f] * sn + ki[f] * cs;
           double mI = 1.0, mP = 1.0, att = 1.0;
           if constexpr (VA) {
             mI = (double)va_ratio(vs, fa.va_k1l2[f], al, ea);
@@ -450,20 +463,20 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
             accPi[f] += mP * (double)(e.zr * sn + e.zi * cs);
           }
         } else {
-          Hr += hrf;
-          Hi += hif;
-          Kr += krf;
-          Ki += kif;
+          Hr += hrs[f] * cs - his[f] * sn;
+          Hi += hrs[f] * sn + his[f] * cs;
+          Kr += krs[f] * cs - kis[f] * sn;
+          Ki += krs[f] * sn + kis[f] * cs;
           if constexpr (ALPHA_GRAD) {
-            accPr[f] += (double)(e.zr * cs - e.zi * sn);
-            accPi[f] += (double)(e.zr * sn + e.zi * cs);
+            accPr[f] += e.zr * cs - e.zi * sn;
+            accPi[f] += e.zr * sn + e.zi * cs;
           }
         }
       }
     }
-    if constexpr (ALPHA_GRAD && !PF) accI += (double)e.u;
+    if constexpr (ALPHA_GRAD && !PF) accI += e.u;
     // cotangent of the Faraday sum at this midpoint: Im(zc K)
-    const double pb = (double)e.zr * Ki + (double)e.zi * Kr;
+    const double pb = (double)((CT)e.zr * Ki + (CT)e.zi * Kr);
     double cbar;  // cotangent of this step's increment: later steps + half of its own
     if constexpr (SERIAL) {
       cbar = suf + 0.5 * pb;
@@ -521,8 +534,9 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       if (f < fa.n_freq) {
         double aI;
         if constexpr (PF) aI = accIf[f];
-        else aI = accI;
-        tb[12] += fa.dlnsI[f] * gi_f[f] * aI + fa.dlnsP[f] * (hr[f] * accPr[f] - hi[f] * accPi[f]);
+        else aI = (double)accI;
+        tb[12] += fa.dlnsI[f] * gi_f[f] * aI +
+                  fa.dlnsP[f] * (hr[f] * (double)accPr[f] - hi[f] * (double)accPi[f]);
       }
     }
   }
