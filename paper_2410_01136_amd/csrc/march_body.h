@@ -82,7 +82,14 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     const int n = c0 + sub;
     const bool act = n < g.n_steps;
     const double s = ((double)n + 0.5) * ray.dkpc;  // midpoint of segment n
-    const FV v = fld.template eval_step<S>(g, ray, rctx, s, n);
+    // (the shared-read grid brings a gridded alpha with its cell records)
+    constexpr bool VA_SHARED = VA && std::is_same_v<F, GridL>;
+    double al = 0.0;
+    FV v;
+    if constexpr (VA_SHARED)
+      v = fld.template eval_step_va<S>(g, ray, rctx, s, n, ea.va_alpha_ref, al);
+    else
+      v = fld.template eval_step<S>(g, ray, rctx, s, n);
     const float bl = v.bx * ray.elx + v.by * ray.ely;
     const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
     const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);
@@ -110,10 +117,9 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       }
       emd = (float)(em * ray.dkpc);
     }
-    double al = 0.0;
     VaStep vs{};
     if constexpr (VA) {
-      al = fld.alpha_at(g, ray, s, ea.va_alpha_ref);
+      if constexpr (!VA_SHARED) al = fld.alpha_at(g, ray, s, ea.va_alpha_ref);
       vs = va_step(al, ea);
     }
     Emit e = VA ? emission(v.n0, bl, bb, false, vs.eI) : emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);

@@ -742,14 +742,44 @@ struct GridB : Grid {
 // wavefront must call eval_step together.
 struct GridL : GridB {
   static constexpr int kSlots = 32;      // distinct cells per wavefront and step chunk
-  static constexpr int kRecFloats = 44;  // 8 x 4 corners + 4 x 2 N0 + 4 padding (bank spread)
+  // record of a cell: 8 x 4 corners + 4 x 2 N0 (+ 4 x 2 alpha with a gridded
+  // index) + 4 padding (bank spread)
+  static constexpr int kRecFloats = 44;
   static constexpr int kRoundsB = kSlots / 8, kRoundsC = kSlots / 16;
   static_assert(kSlots % 16 == 0, "whole load rounds of both kinds");
 
-  template <int S>
-  __device__ inline bool load_shared(uint32_t node, Corners& k) const {
+  __device__ inline __amdgpu_buffer_rsrc_t rsrc_a() const {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p.alpha, (short)0, (int)p.c_bytes, 0x00020000);
+  }
+  __device__ inline f2v lda(uint32_t off, uint32_t so) const {
+    return __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(rsrc_a(), off, so, 0));
+  }
+  // the 4 alpha rows (x0, x1) of a cell, row y + 2z
+  __device__ inline void load_alpha_direct(uint32_t node, f2v* ka) const {
+    const uint32_t oc = node * 4u;
+    ka[0] = lda(oc, 0);
+    ka[1] = lda(oc, p.sy4);
+    ka[2] = lda(oc, p.sz4);
+    ka[3] = lda(oc, p.sy4 + p.sz4);
+  }
+  // alpha at the cell's interpolation point, interpolated in FP64 like
+  // Grid::alpha_at (an error in alpha is amplified by the emissivity)
+  __device__ inline double interp_alpha(const CellB& c, const f2v* ka, double alpha_ref) const {
+    const double tx = c.tx, ty = c.ty, tz = c.tz;
+    auto lx = [&](int row) {
+      return (double)ka[row].x + tx * ((double)ka[row].y - (double)ka[row].x);
+    };
+    const double y0 = lx(0) + ty * (lx(1) - lx(0));
+    const double y1 = lx(2) + ty * (lx(3) - lx(2));
+    return c.in ? y0 + tz * (y1 - y0) : alpha_ref;
+  }
+
+  // WA: the alpha rows travel with the records (gridded spectral index)
+  template <int S, bool WA = false>
+  __device__ inline bool load_shared(uint32_t node, Corners& k, f2v* ka = nullptr) const {
+    constexpr int kRec = WA ? kRecFloats + 8 : kRecFloats;
     __shared__ uint32_t s_node[4][kSlots];
-    __shared__ float s_rec[4][kSlots][kRecFloats];
+    __shared__ float s_rec[4][kSlots][kRec];
     const int lane = (int)__lane_id();
     const int w = (int)(threadIdx.x >> 6);
     // a run starts where the cell differs from the previous lane's, or at the
@@ -815,7 +845,7 @@ struct GridL : GridB {
 #pragma unroll
     for (int r = 0; r < kRoundsC; ++r) nc[r] = s_node[w][(lane >> 2) + 16 * r];
     f4v vb[kRoundsB];
-    f2v vc[kRoundsC];
+    f2v vc[kRoundsC], va[kRoundsC];
 #pragma unroll
     for (int r = 0; r < kRoundsB; ++r)
       if ((lane >> 3) + 8 * r < nsl) vb[r] = ld4(nb[r] * 16u + offb, 0);
@@ -823,6 +853,11 @@ struct GridL : GridB {
 #pragma unroll
       for (int r = 0; r < kRoundsC; ++r)
         if ((lane >> 2) + 16 * r < nsl) vc[r] = ld2(nc[r] * 4u + offc, 0);
+    }
+    if constexpr (WA) {
+#pragma unroll
+      for (int r = 0; r < kRoundsC; ++r)
+        if ((lane >> 2) + 16 * r < nsl) va[r] = lda(nc[r] * 4u + offc, 0);
     }
 #pragma unroll
     for (int r = 0; r < kRoundsB; ++r) {
@@ -836,6 +871,13 @@ struct GridL : GridB {
         if (sl < nsl) *reinterpret_cast<f2v*>(&s_rec[w][sl][32 + 2 * row]) = vc[r];
       }
     }
+    if constexpr (WA) {
+#pragma unroll
+      for (int r = 0; r < kRoundsC; ++r) {
+        const int sl = (lane >> 2) + 16 * r;
+        if (sl < nsl) *reinterpret_cast<f2v*>(&s_rec[w][sl][40 + 2 * row]) = va[r];
+      }
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -844,6 +886,10 @@ struct GridL : GridB {
     if (with_c) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) k.c[j] = *reinterpret_cast<const f2v*>(&s_rec[w][slot][32 + 2 * j]);
+    }
+    if constexpr (WA) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ka[j] = *reinterpret_cast<const f2v*>(&s_rec[w][slot][40 + 2 * j]);
     }
     return true;
   }
@@ -858,6 +904,22 @@ struct GridL : GridB {
     } else {
       if (!load_shared<S>(c.node, k)) load_direct(c.node, k);
     }
+    return interp(g, r, s, c, k);
+  }
+
+  // The fields and the gridded spectral index at step n (alpha_ref outside the
+  // grid box).
+  template <int S>
+  __device__ inline FV eval_step_va(const GeomArgs& g, const Ray& r, const RayCtx& x, double s,
+                                    int n, double alpha_ref, double& al) const {
+    const CellB c = cell_b(g, r, x, s, n);
+    Corners k;
+    f2v ka[4];
+    if (S == 1 || !load_shared<S, true>(c.node, k, ka)) {
+      load_direct(c.node, k);
+      load_alpha_direct(c.node, ka);
+    }
+    al = interp_alpha(c, ka, alpha_ref);
     return interp(g, r, s, c, k);
   }
 };
