@@ -155,6 +155,16 @@ __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // expansion, which costs some fifteen more instructions
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Coordinate k of the point at distance s along the ray, in FP32, for fields
+// that vary smoothly over kiloparsecs (the analytic model and the cosmic-ray
+// density): an FP32 FMA's error there, ~1e-6 kpc, moves them by ~1e-7.  Fields
+// with sharp edges (the sphere, the WMAP ring) and grid coordinates take the
+// FP64 position.
+__device__ inline float smooth_x(const GeomArgs& g, const Ray& r, double s, int k) {
+  const double n3[3] = {r.nx, r.ny, r.nz};
+  return fmaf((float)s, (float)n3[k], (float)g.r_obs[k]);
+}
+
 // 16-parameter analytic model, evaluated in FP32 with host-prepared constants
 // (reciprocal scale lengths pre-multiplied by log2(e)).
 struct Model16 {
@@ -202,14 +212,14 @@ struct Model16 {
     return eval_at(g, r, s);
   }
   __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
-    return eval((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
-                (float)(g.r_obs[2] + s * r.nz));
+    return eval(smooth_x(g, r, s, 0), smooth_x(g, r, s, 1),
+                smooth_x(g, r, s, 2));
   }
   template <class T>
   __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
                                 T* tb) const {
-    vjp((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
-        (float)(g.r_obs[2] + s * r.nz), gv, tb);
+    vjp(smooth_x(g, r, s, 0), smooth_x(g, r, s, 1),
+        smooth_x(g, r, s, 2), gv, tb);
   }
 
   __device__ inline FV eval_point(float x, float y, float z) const { return eval(x, y, z); }
@@ -370,8 +380,8 @@ struct Grid {
                             gc[c.base + sy + sz + 1])
                       : 0.0f;
     } else {
-      v.n0 = cr.n0_at((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
-                      (float)(g.r_obs[2] + s * r.nz));
+      v.n0 = cr.n0_at(smooth_x(g, r, s, 0), smooth_x(g, r, s, 1),
+                      smooth_x(g, r, s, 2));
     }
     return v;
   }
@@ -407,8 +417,8 @@ struct Grid {
   __device__ inline void vjp_at(const GeomArgs& g, const Ray& r, double s, const FV& gv,
                                 T* tb) const {
     if (p.c == nullptr)
-      cr.vjp_n0((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
-                (float)(g.r_obs[2] + s * r.nz), gv.n0, tb);
+      cr.vjp_n0(smooth_x(g, r, s, 0), smooth_x(g, r, s, 1),
+                smooth_x(g, r, s, 2), gv.n0, tb);
   }
 
   // Gradient accumulator of one lane: the 8 corners x 5 channels of the cell the
@@ -712,8 +722,8 @@ struct GridB : Grid {
                 w[4] * k.c[2].x + w[5] * k.c[2].y + w[6] * k.c[3].x + w[7] * k.c[3].y;
       v.n0 = c.in ? a : 0.0f;
     } else {
-      v.n0 = cr.n0_at((float)(g.r_obs[0] + s * r.nx), (float)(g.r_obs[1] + s * r.ny),
-                      (float)(g.r_obs[2] + s * r.nz));
+      v.n0 = cr.n0_at(smooth_x(g, r, s, 0), smooth_x(g, r, s, 1),
+                      smooth_x(g, r, s, 2));
     }
     return v;
   }
