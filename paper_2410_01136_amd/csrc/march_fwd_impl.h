@@ -10,13 +10,8 @@
 
 namespace sm {
 
-// (the free-free shared-read forward for up to 3 frequencies is held to 128
-// VGPRs, 4 wavefronts per SIMD instead of 3, at the cost of a few spilled
-// registers: 3.35 ms against 3.48 ms on the 256^3 grid at 3 frequencies)
 template <class F, int S, int MF, bool FF, bool VA>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu((FF && !VA && MF <= 3 && std::is_same_v<F, GridL>) ? 4 : 1)))
-void k_forward(GeomArgs g, FreqArgs fa, EmitArgs ea, F fld,
+__global__ __launch_bounds__(256) void k_forward(GeomArgs g, FreqArgs fa, EmitArgs ea, F fld,
                                                  float* __restrict__ maps,
                                                  double* __restrict__ phi_end,
                                                  double* __restrict__ em_end) {
