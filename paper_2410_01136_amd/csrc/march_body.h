@@ -360,14 +360,12 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 #pragma unroll
   for (int k = 0; k < (THETA ? kNParam : 1); ++k) tbf[k] = 0.0f;
   constexpr int MPF = PF ? MF : 1;
-  // Without per-frequency multipliers (the plain march) a step's cotangent
-  // rotations and this lane's alpha sums are FP32: each step's terms are FP32
-  // products, the sums over steps that need it (the Faraday cotangents) stay
-  // FP64.
-  using CT = std::conditional_t<PF, double, float>;
-  CT accI = 0, accPr[MF], accPi[MF];
-  double accIf[MPF];
-  float hrs[MF], his[MF], krs[MF], kis[MF];
+  // A step's cotangent rotations and multipliers, and this lane's alpha sums,
+  // are FP32: each step's terms are FP32 products; the sums over steps that
+  // need it (the Faraday and emission-measure cotangents) stay FP64.
+  using CT = float;
+  CT accI = 0, accPr[MF], accPi[MF], accIf[MPF];
+  float hrs[MF], his[MF], krs[MF], kis[MF], gis[MF], cfs[MFF], kds[MFF];
 #pragma unroll
   for (int f = 0; f < MF; ++f) {
     accPr[f] = accPi[f] = 0;
@@ -375,9 +373,15 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     his[f] = (float)hi[f];
     krs[f] = (float)kr[f];
     kis[f] = (float)ki[f];
+    gis[f] = (float)gi_f[f];
   }
 #pragma unroll
-  for (int f = 0; f < MPF; ++f) accIf[f] = 0.0;
+  for (int f = 0; f < MFF; ++f) {
+    cfs[f] = (float)cf[f];
+    kds[f] = (float)kd[f];
+  }
+#pragma unroll
+  for (int f = 0; f < MPF; ++f) accIf[f] = 0;
 
   // every lane of a wavefront runs the same number of iterations (the grid
   // scatter is collective); a short or empty last piece idles through the rest
@@ -430,10 +434,10 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     // (mI_f, mP_f the per-frequency multipliers of I and Q + iU: the free-free
     // attenuation and the local-alpha prefactor ratio; 1 without either)
     CT Hr = 0, Hi = 0, Kr = 0, Ki = 0;
-    double GIe = GI;  // sum_f mI_f gi_f
-    double Cw = 0.0;  // FF: d L / d w of this segment's own free-free emission
-    double X = 0.0;   // FF: d L / d EM at this midpoint
-    if constexpr (PF) GIe = 0.0;
+    float GIe = (float)GI;  // sum_f mI_f gi_f
+    float Cw = 0.0f;  // FF: d L / d w of this segment's own free-free emission
+    float X = 0.0f;   // FF: d L / d EM at this midpoint
+    if constexpr (PF) GIe = 0.0f;
     const double psid = psi * dk;
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
@@ -441,15 +445,15 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
         float sn, cs;
         sincos_turns(psid * fa.kappa[f], &sn, &cs);
         if constexpr (PF) {
-          const double hrf = hr[f] * cs - hi[f] * sn, hif = hr[f] * sn + hi[f] * cs;
-          const double krf = kr[f] * cs - ki[f] * sn, kif = kr[f] * sn + ki[f] * cs;
-          double mI = 1.0, mP = 1.0, att = 1.0;
+          const float hrf = hrs[f] * cs - his[f] * sn, hif = hrs[f] * sn + his[f] * cs;
+          const float krf = krs[f] * cs - kis[f] * sn, kif = krs[f] * sn + kis[f] * cs;
+          float mI = 1.0f, mP = 1.0f, att = 1.0f;
           if constexpr (VA) {
-            mI = (double)va_ratio(vs, fa.va_k1l2[f], al, ea);
-            mP = mI * (double)vs.prat;
+            mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
+            mP = mI * vs.prat;
           }
           if constexpr (FF) {
-            att = (double)exp2f(-(float)fa.kffl2[f] * emd);
+            att = exp2f(-(float)fa.kffl2[f] * emd);
             mI *= att;
             mP *= att;
           }
@@ -457,16 +461,15 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
           Hi += mP * hif;
           Kr += mP * krf;
           Ki += mP * kif;
-          GIe += mI * gi_f[f];
+          GIe += mI * gis[f];
           if constexpr (FF) {
-            Cw += att * cf[f];
-            X -= kd[f] * (mI * gi_f[f] * (double)e.u + att * cf[f] * (double)w +
-                          mP * (hrf * (double)e.zr - hif * (double)e.zi));
+            Cw += att * cfs[f];
+            X -= kds[f] * (mI * gis[f] * e.u + att * cfs[f] * w + mP * (hrf * e.zr - hif * e.zi));
           }
           if constexpr (ALPHA_GRAD) {
-            accIf[f] += mI * (double)e.u;
-            accPr[f] += mP * (double)(e.zr * cs - e.zi * sn);
-            accPi[f] += mP * (double)(e.zr * sn + e.zi * cs);
+            accIf[f] += mI * e.u;
+            accPr[f] += mP * (e.zr * cs - e.zi * sn);
+            accPi[f] += mP * (e.zr * sn + e.zi * cs);
           }
         } else {
           Hr += hrs[f] * cs - his[f] * sn;
@@ -495,21 +498,22 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     }
     double wbar = 0.0;  // FF: cotangent of this segment's n_e^2
     if constexpr (FF) {
-      if (!act) X = Cw = 0.0;
+      if (!act) X = Cw = 0.0f;
+      const double Xd = (double)X;
       double ebar;  // through the emission measure: later midpoints + half of its own
       if constexpr (SERIAL) {
-        ebar = sufE + 0.5 * X;
-        sufE += X;
+        ebar = sufE + 0.5 * Xd;
+        sufE += Xd;
       } else {
-        const double sincl = group_suffix_scan<S>(X, sub);
+        const double sincl = group_suffix_scan<S>(Xd, sub);
         const double stot = group_first<S>(sincl);
-        ebar = sufE + sincl - 0.5 * X;
+        ebar = sufE + sincl - 0.5 * Xd;
         sufE += stot;
       }
-      wbar = Cw + ebar;
+      wbar = (double)Cw + ebar;
     }
     // local reverse of the emission and projections
-    const EmitBar eb = emission_vjp(v.n0, bl, bb, a3, eI, (float)GIe, (float)Hr, (float)(-Hi));
+    const EmitBar eb = emission_vjp(v.n0, bl, bb, a3, eI, GIe, Hr, -Hi);
     float neb = (float)(cbar * bpar);
     if constexpr (FF) neb += (float)(2.0 * wbar) * v.ne;
     const float bparb = (float)(cbar * (double)v.ne);
@@ -538,9 +542,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
       if (f < fa.n_freq) {
-        double aI;
-        if constexpr (PF) aI = accIf[f];
-        else aI = (double)accI;
+        const double aI = (double)(PF ? accIf[f] : accI);
         tb[12] += fa.dlnsI[f] * gi_f[f] * aI +
                   fa.dlnsP[f] * (hr[f] * (double)accPr[f] - hi[f] * (double)accPi[f]);
       }
