@@ -192,11 +192,13 @@ def test_grid_read_paths_agree(sm, orc, lanes, S, with_c):
     # LDS-shared cells, per-lane buffer reads and 64-bit addresses read the same
     # nodes; 197 steps leave a ragged last chunk, the coarse z axis makes many
     # cells per chunk and the fine one few; on the 4 x 3 x 2 grid neighbouring
-    # sightlines share nearly every cell (shared slots across sightlines)
+    # sightlines share nearly every cell (shared slots across sightlines); on
+    # the 31 pc z-cells of the last grid long steps cross a cell each, so most
+    # chunks hold more distinct cells than the LDS slots (per-lane fallback)
     import torch
     g = I.geometry("C1", nside=16, n_steps=197)
     lanes(sm.FIELD_GRID, S)
-    for n in ((37, 29, 13), (9, 7, 65), (4, 3, 2)):
+    for n in ((37, 29, 13), (9, 7, 65), (4, 3, 2), (6, 5, 257)):
         bn, c = small_turbulent_grid(orc, n=n, seed0=1301, with_c=with_c)
         f = sm.grid(I.THETA0, torch.from_numpy(bn).cuda(),
                     torch.from_numpy(c).cuda() if with_c else None, I.BOX_LO, I.BOX_HI)
