@@ -363,8 +363,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   // A step's cotangent rotations and multipliers, and this lane's alpha sums,
   // are FP32: each step's terms are FP32 products; the sums over steps that
   // need it (the Faraday and emission-measure cotangents) stay FP64.
-  using CT = float;
-  CT accI = 0, accPr[MF], accPi[MF], accIf[MPF];
+  float accI = 0, accPr[MF], accPi[MF], accIf[MPF];
   float hrs[MF], his[MF], krs[MF], kis[MF], gis[MF], cfs[MFF], kds[MFF];
 #pragma unroll
   for (int f = 0; f < MF; ++f) {
@@ -433,7 +432,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     // H = sum_f mP_f h_f e^{2 pi i t_f};  K = sum_f mP_f k_f e^{2 pi i t_f}
     // (mI_f, mP_f the per-frequency multipliers of I and Q + iU: the free-free
     // attenuation and the local-alpha prefactor ratio; 1 without either)
-    CT Hr = 0, Hi = 0, Kr = 0, Ki = 0;
+    float Hr = 0, Hi = 0, Kr = 0, Ki = 0;
     float GIe = (float)GI;  // sum_f mI_f gi_f
     float Cw = 0.0f;  // FF: d L / d w of this segment's own free-free emission
     float X = 0.0f;   // FF: d L / d EM at this midpoint
@@ -485,7 +484,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     }
     if constexpr (ALPHA_GRAD && !PF) accI += e.u;
     // cotangent of the Faraday sum at this midpoint: Im(zc K)
-    const double pb = (double)((CT)e.zr * Ki + (CT)e.zi * Kr);
+    const double pb = (double)(e.zr * Ki + e.zi * Kr);
     double cbar;  // cotangent of this step's increment: later steps + half of its own
     if constexpr (SERIAL) {
       cbar = suf + 0.5 * pb;
