@@ -155,10 +155,14 @@ def test_chi2_kernel(sm):
 
 
 @pytest.mark.slow
-def test_c2_full_size_theta_gradient(sm, orc):
+@pytest.mark.parametrize("S", [0, 1])
+def test_c2_full_size_theta_gradient(sm, orc, lanes, S):
     """C2 at full size: chi^2 of I/Q/U against a target from perturbed parameters
-    plus 1% noise, gradient at theta0 vs the oracle."""
+    plus 1% noise, gradient at theta0 vs the oracle; with the built-in lane
+    count and with one lane per sightline, whose FP32 theta sums run over all
+    768 steps."""
     import torch
+    lanes(sm.FIELD_MODEL16, S)
     g = I.geometry("C2")
     og = oracle_geom(orc, g)
     th_star = I.perturbed_thetas(1, 2001)[0]
