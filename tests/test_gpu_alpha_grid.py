@@ -85,6 +85,31 @@ def test_forward(sm, orc, lanes, mode, freqs, S):
     check(gpu, ref, f"alpha grid mode={mode} nf={len(freqs)} S={S}")
 
 
+@pytest.mark.parametrize("n", [(33, 33, 9), (9, 9, 129)])
+def test_shared_reads_carry_alpha(sm, orc, lanes, n):
+    # the shared-read path brings alpha in the cells' LDS records; on the fine
+    # z grid most chunks hold more distinct cells than the LDS slots and read
+    # their cells per lane: both meet the oracle, and agree with the per-lane
+    # path to FP32 rounding (which the general-alpha emission and depolarised
+    # Q/U amplify a little more than the alpha = 3 march does)
+    import torch
+    g = I.geometry("C1", nside=16, n_steps=117, freqs_hz=(1.0e9, 2.3e9, 5.0e9))
+    bn, c, alpha = fields(orc, n=n)
+    lanes(sm.FIELD_GRID, 16)
+    out = []
+    try:
+        for mode in (3, 2):
+            sm.set_grid_addressing(mode)
+            out.append(sm.forward(sm.geom_from(g), gpu_field(sm, bn, c, alpha)).cpu().numpy())
+    finally:
+        sm.set_grid_addressing(0)
+    ref = orc.forward(oracle_geom(orc, g), ofield(orc, bn, c, alpha))
+    check(out[0], ref, f"alpha grid shared n={n}")
+    err = np.abs(out[0] - out[1]).max(axis=-1) / np.abs(out[1]).max(axis=-1)
+    print(f"alpha shared vs per-lane n={n}: max rel diff {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-5, (n, err)
+
+
 # dense thermal plasma, weak field, strong CR density (as in test_gpu_ff.py)
 THETA_FF = np.array([0.005, -0.25, 0.15, 0.35, 7.0, 1.2, 0.002, 1.4, 9.0,
                      42.0, 7.5, 1.1, 2.85, 3.0, 0.9, 0.02])
