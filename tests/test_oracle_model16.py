@@ -1,0 +1,146 @@
+"""Point-value pins of the oracle's 16-parameter spiral-disk model.
+
+The model is the reading of the spiral-disk test configuration (an
+exponential disk field with a logarithmic-spiral pitch, the paper's WMAP
+forms for the pitch gradient psi_1 ln(R / R_sun) and the out-of-plane tilt
+chi_B0 tanh(z / 1 kpc) of Sec. 3.1, an odd halo, exponential cosmic-ray and
+thermal-electron disks):
+
+  B  = B0 e^{-(R - R_sun)/R_B - |z|/z_B} [sin psi cos chi rho^ + cos psi cos chi phi^ + sin chi z^]
+     + B_H0 (z / z_H) e^{-|z|/z_H - (R - R_sun)/R_H} phi^,
+  N0 = C0 e^{-(R - R_sun)/h_r - |z|/h_z},   n_e = n0 e^{-|z|/h_ne - kappa (R - R_sun)},
+
+R_sun = 8.5 kpc, rho^ = (x, y, 0)/R, phi^ = (-y, x, 0)/R, psi measured from
+phi^ (B_rho / B_phi = tan psi).  Each expected value below is worked out by
+hand from these formulas at a chosen point, with the unit vectors written out
+for that point, so that a slip in the oracle -- rho^ and phi^ exchanged, a
+sign of psi, a scale length applied to the wrong coordinate, a halo that is
+not odd, a tilt with the wrong argument -- fails one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2410_01136_amd import inputs as I
+
+
+def model(orc, th, r):
+    return orc.fields_at(orc.Field(orc.MODEL16, np.asarray(th, dtype=np.float64)),
+                         np.asarray(r, dtype=np.float64))
+
+
+def base_theta(**kw):
+    """theta0 with the named entries replaced."""
+    names = ["B0", "psi0", "psi1", "chiB0", "RB", "zB", "BH0", "zH", "RH", "C0", "hr", "hz",
+             "alpha", "n0", "hne", "kappa"]
+    th = I.THETA0.copy()
+    for k, v in kw.items():
+        th[names.index(k)] = v
+    return th
+
+
+def test_field_at_the_sun_has_the_stated_pitch(orc):
+    # at the Sun (-8.5, 0, 0): rho^ = (-1, 0, 0), phi^ = (0, -1, 0); with psi0 = -12 deg
+    # B = 6 [sin(-12 deg) rho^ + cos(-12 deg) phi^] = (6 sin 12 deg, -6 cos 12 deg, 0)
+    B, ne, n0 = model(orc, I.THETA0, (-8.5, 0.0, 0.0))
+    s12, c12 = math.sin(math.radians(12.0)), math.cos(math.radians(12.0))
+    np.testing.assert_allclose(B, [6.0 * s12, -6.0 * c12, 0.0], rtol=1e-14, atol=1e-15)
+    assert np.linalg.norm(B) == pytest.approx(6.0, rel=1e-14)
+    b_rho = B @ np.array([-1.0, 0.0, 0.0])
+    b_phi = B @ np.array([0.0, -1.0, 0.0])
+    assert b_rho / b_phi == pytest.approx(math.tan(math.radians(-12.0)), rel=1e-13)
+    # the cosmic-ray and thermal-electron normalisations are their values at the Sun
+    assert n0 == pytest.approx(4.0e-5, rel=1e-14)
+    assert ne == pytest.approx(0.03, rel=1e-14)
+
+
+def test_pitch_at_another_azimuth(orc):
+    # at (0, 8.5, 0) (R = R_sun, l of the GC frame 90 deg): rho^ = (0, 1, 0), phi^ = (-1, 0, 0);
+    # pitch +20 deg: B = 6 (sin 20 deg rho^ + cos 20 deg phi^) = (-6 cos 20, 6 sin 20, 0)
+    th = base_theta(psi0=math.radians(20.0))
+    B, _, _ = model(orc, th, (0.0, 8.5, 0.0))
+    np.testing.assert_allclose(B, [-6.0 * math.cos(math.radians(20.0)),
+                                   6.0 * math.sin(math.radians(20.0)), 0.0],
+                               rtol=1e-14, atol=1e-14)
+
+
+def test_disk_scale_lengths(orc):
+    th = base_theta(RB=5.0, zB=0.7)
+    # radial e-fold: R = R_sun + R_B on the x axis beyond the Sun
+    B1, _, _ = model(orc, th, (-(8.5 + 5.0), 0.0, 0.0))
+    assert np.linalg.norm(B1) == pytest.approx(6.0 * math.exp(-1.0), rel=1e-13)
+    # vertical e-fold above the Sun, and the same below (|z|)
+    for z in (0.7, -0.7):
+        B2, _, _ = model(orc, th, (-8.5, 0.0, z))
+        assert np.linalg.norm(B2) == pytest.approx(6.0 * math.exp(-1.0), rel=1e-13)
+    # the two lengths act on their own coordinates: one R_B inward, z_B / 2 up
+    B3, _, _ = model(orc, th, (8.5 - 5.0, 0.0, 0.35))
+    assert np.linalg.norm(B3) == pytest.approx(6.0 * math.exp(1.0 - 0.5), rel=1e-13)
+
+
+def test_pitch_gradient_uses_the_log_radius(orc):
+    # psi = psi0 + psi1 ln(R / R_sun): at R = R_sun e, psi = psi0 + psi1
+    th = base_theta(psi0=math.radians(-12.0), psi1=0.4, RB=1e30)
+    R = 8.5 * math.e
+    B, _, _ = model(orc, th, (0.0, -R, 0.0))  # rho^ = (0, -1, 0), phi^ = (1, 0, 0)
+    psi = math.radians(-12.0) + 0.4
+    np.testing.assert_allclose(B, [6.0 * math.cos(psi), -6.0 * math.sin(psi), 0.0],
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_out_of_plane_tilt(orc):
+    # chi = chiB0 tanh(z / 1 kpc); at z = 1 kpc above the Sun: B_z = |B_disk| sin chi and the
+    # in-plane part shrinks by cos chi; the disk e-fold e^{-1/z_B} = e^{-1} at z_B = 1
+    th = base_theta(chiB0=0.3)
+    B, _, _ = model(orc, th, (-8.5, 0.0, 1.0))
+    chi = 0.3 * math.tanh(1.0)
+    amp = 6.0 * math.exp(-1.0)
+    s12, c12 = math.sin(math.radians(12.0)), math.cos(math.radians(12.0))
+    np.testing.assert_allclose(B, [amp * s12 * math.cos(chi), -amp * c12 * math.cos(chi),
+                                   amp * math.sin(chi)], rtol=1e-13, atol=1e-15)
+    # below the plane the tilt is reversed (tanh is odd)
+    Bm, _, _ = model(orc, th, (-8.5, 0.0, -1.0))
+    assert Bm[2] == pytest.approx(-B[2], rel=1e-14)
+    assert Bm[0] == pytest.approx(B[0], rel=1e-14)
+
+
+def test_halo_value_and_oddness(orc):
+    # disk off: B = B_H0 (z / z_H) e^{-|z|/z_H - (R - R_sun)/R_H} phi^, phi^ = (0, -1, 0) at the Sun
+    th = base_theta(B0=0.0, BH0=2.0, zH=1.5, RH=6.0)
+    z = 0.75
+    B, _, _ = model(orc, th, (-8.5, 0.0, z))
+    val = 2.0 * (z / 1.5) * math.exp(-z / 1.5)
+    np.testing.assert_allclose(B, [0.0, -val, 0.0], rtol=1e-14, atol=1e-16)
+    Bm, _, _ = model(orc, th, (-8.5, 0.0, -z))
+    np.testing.assert_allclose(Bm, -B, rtol=1e-14, atol=1e-16)
+    # radial fall-off of the halo with R_H, not with R_B
+    B2, _, _ = model(orc, th, (-(8.5 + 6.0), 0.0, z))
+    assert np.linalg.norm(B2) == pytest.approx(val * math.exp(-1.0), rel=1e-13)
+
+
+def test_cosmic_ray_and_electron_scale_lengths(orc):
+    th = base_theta(hr=4.0, hz=0.5, hne=0.8, kappa=0.125)
+    _, ne, n0 = model(orc, th, (-(8.5 + 4.0), 0.0, 0.0))
+    assert n0 == pytest.approx(4.0e-5 * math.exp(-1.0), rel=1e-13)
+    assert ne == pytest.approx(0.03 * math.exp(-0.125 * 4.0), rel=1e-13)
+    _, ne, n0 = model(orc, th, (-8.5, 0.0, -0.5))
+    assert n0 == pytest.approx(4.0e-5 * math.exp(-1.0), rel=1e-13)
+    assert ne == pytest.approx(0.03 * math.exp(-0.5 / 0.8), rel=1e-13)
+    # the thermal disk at theta0 has no radial decline (kappa = 0)
+    _, ne, _ = model(orc, I.THETA0, (3.0, 4.0, 0.0))
+    assert ne == pytest.approx(0.03, rel=1e-14)
+
+
+def test_field_near_the_axis_uses_the_floor_radius(orc):
+    # on the z axis R = 0: rho^ and phi^ use max(R, 1e-3 kpc), so the field is finite
+    B, ne, n0 = model(orc, I.THETA0, (0.0, 0.0, 0.2))
+    assert np.all(np.isfinite(B)) and np.isfinite(ne) and np.isfinite(n0)
+    # just off the axis on +x: rho^ = (1, 0, 0), phi^ = (0, 1, 0) exactly
+    x = 5e-4
+    B, _, _ = model(orc, I.THETA0, (x, 0.0, 0.0))
+    amp = 6.0 * math.exp(8.5 / 8.0 - 0.0) * math.exp(-x / 8.0)
+    s12, c12 = math.sin(math.radians(12.0)), math.cos(math.radians(12.0))
+    # |rho^| = x / 1e-3 below the floor radius
+    np.testing.assert_allclose(B, [amp * -s12 * (x / 1e-3), amp * c12 * (x / 1e-3), 0.0],
+                               rtol=1e-12)
