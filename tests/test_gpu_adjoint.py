@@ -3,13 +3,14 @@
 Tolerances (the maps agree to ~1e-6 relative; a gradient is a weighted sum over
 residual-sized cotangents, so it amplifies map errors):
   * theta: per component |theta_k (g_gpu - g_ref)_k| <= 1e-3 max_k |theta_k g_ref_k|,
-  * grid: relative L2 error <= 1e-3 and cosine similarity >= 1 - 1e-6.
+  * grid: relative L2 error <= 1e-3, cosine similarity >= 1 - 1e-6 and every
+    voxel within 1e-3 of the largest gradient entry (parity.check_grid_gradient).
 """
 import numpy as np
 import pytest
 
 from paper_2410_01136_amd import inputs as I
-from parity import oracle_geom
+from parity import check_grid_gradient, oracle_geom
 
 pytestmark = pytest.mark.gpu
 
@@ -109,10 +110,7 @@ def test_grid_gradient(sm, orc, lanes, S, with_c):
     if with_c:
         pairs.append((dc.cpu().numpy().astype(np.float64), rc))
     for a, b in pairs:
-        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        cos = (a * b).sum() / (np.linalg.norm(a) * np.linalg.norm(b))
-        print(f"grid S={S} with_c={with_c}: rel L2 {rel:.2e}, 1-cos {1 - cos:.2e}", flush=True)
-        assert rel <= 1e-3 and cos >= 1 - 1e-6
+        check_grid_gradient(a, b, f"grid S={S} with_c={with_c}")
     # alpha (and, with analytic N0, the CR parameters) get theta gradients too
     idx = [12] if with_c else [9, 10, 11, 12]
     th_got = dth.cpu().numpy()
@@ -202,9 +200,7 @@ def test_grid_gradient_sub_box(sm, orc, lanes, S):
     ofield = orc.Field(orc.GRID, THETA_T, grid_bn=bn, grid_c=reg_c, grid_lo=lo, grid_hi=hi)
     _, rbn, rc = orc.adjoint(oracle_geom(orc, g), ofield, dm.astype(np.float64), want_grid=True)
     for a, b in ((dbn.cpu().numpy().astype(np.float64), rbn), (dc.cpu().numpy().astype(np.float64), rc)):
-        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        print(f"sub-box grid S={S}: rel L2 {rel:.2e}", flush=True)
-        assert rel <= 1e-3
+        check_grid_gradient(a, b, f"sub-box grid S={S}")
 
 
 @pytest.mark.slow
@@ -230,9 +226,5 @@ def test_c2_full_size_grid_gradient(sm, orc, lanes, S):
     ofield = orc.Field(orc.GRID, I.THETA0, grid_bn=reg_bn, grid_c=None, grid_lo=I.BOX_LO,
                        grid_hi=I.BOX_HI)
     _, rbn, _ = orc.adjoint(oracle_geom(orc, g), ofield, dm.astype(np.float64), want_grid=True)
-    a = dbn.cpu().numpy().astype(np.float64)
-    rel = np.linalg.norm(a - rbn) / np.linalg.norm(rbn)
-    cos = (a * rbn).sum() / (np.linalg.norm(a) * np.linalg.norm(rbn))
-    print(f"C2 full grid S={sm.get_lanes_per_ray(1, sm.FIELD_GRID, g.npix)}: rel L2 {rel:.2e}, "
-          f"1-cos {1 - cos:.2e}", flush=True)
-    assert rel <= 1e-3 and cos >= 1 - 1e-6
+    check_grid_gradient(dbn.cpu().numpy(), rbn,
+                        f"C2 full grid S={sm.get_lanes_per_ray(1, sm.FIELD_GRID, g.npix)}")

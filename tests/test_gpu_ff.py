@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2410_01136_amd import inputs as I
-from parity import compare_maps, oracle_geom
+from parity import FP32_TERMS, check_grid_gradient, compare_maps, oracle_geom
 
 pytestmark = pytest.mark.gpu
 
@@ -43,8 +43,8 @@ def gpu_maps(sm, g, field):
     return maps.cpu().numpy()
 
 
-def check(gpu, ref, label):
-    ok, rep = compare_maps(gpu, ref)
+def check(gpu, ref, label, floor=0.0, max_floor=0):
+    ok, rep = compare_maps(gpu, ref, floor=floor, max_floor=max_floor)
     print(label, rep, flush=True)
     assert ok, (label, rep)
 
@@ -69,7 +69,10 @@ def test_model16_theta0_low_frequencies(sm, orc, freqs):
     # two and three (four-slot) and six (sixteen-slot) frequencies
     g = I.geometry("C0", freqs_hz=freqs)
     ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.MODEL16, I.THETA0, te_k=TE))
-    check(gpu_maps(sm, g, sm.model16(I.THETA0).with_te(TE)), ref, f"theta0 ff {len(freqs)} freqs")
+    # (the disk model's most depolarised pixels: the declared FP32 term floor,
+    # at most 0.1% of the pixels of each frequency)
+    check(gpu_maps(sm, g, sm.model16(I.THETA0).with_te(TE)), ref, f"theta0 ff {len(freqs)} freqs",
+          FP32_TERMS, 3 * len(freqs))
 
 
 def dense_grid(orc, n=(33, 33, 9), lo=I.BOX_LO, hi=I.BOX_HI, seed0=4101):
@@ -186,10 +189,7 @@ def test_grid_gradient(sm, orc, lanes, S):
     got = dbn.cpu().numpy().astype(np.float64)
     for a, b, lab in ((got, rbn, "bn"), (got[..., 3], rbn[..., 3], "n_e"),
                       (dc.cpu().numpy().astype(np.float64), rc, "N0")):
-        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        cos = (a * b).sum() / (np.linalg.norm(a) * np.linalg.norm(b))
-        print(f"grid ff S={S} {lab}: rel L2 {rel:.2e}, 1-cos {1 - cos:.2e}", flush=True)
-        assert rel <= 1e-3 and cos >= 1 - 1e-6
+        check_grid_gradient(a, b, f"grid ff S={S} {lab}")
 
 
 @pytest.mark.parametrize("n_steps,S", [(1, 16), (1, 1), (3, 64), (17, 4)])
@@ -229,6 +229,4 @@ def test_grid_gradient_few_steps(sm, orc, lanes, S):
                    te_k=TE)
     _, rbn, rc = orc.adjoint(oracle_geom(orc, g), of, dm.astype(np.float64), want_grid=True)
     for a, b in ((dbn.cpu().numpy().astype(np.float64), rbn), (dc.cpu().numpy().astype(np.float64), rc)):
-        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        print(f"few-step grid ff S={S}: rel L2 {rel:.2e}", flush=True)
-        assert rel <= 1e-3
+        check_grid_gradient(a, b, f"few-step grid ff S={S}")
