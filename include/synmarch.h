@@ -169,6 +169,20 @@ syn_status syn_chi2(int64_t n_pix, int32_t n_maps, const float* maps, const floa
                     const double* inv_sigma2, float* dmaps, double* chi2, void* ws,
                     size_t ws_bytes, hipStream_t stream);
 
+/* syn_chi2 for callers that cannot allocate device memory (code under HIP
+   graph capture, serving loops, harnesses that forbid hipMalloc): the same
+   arguments, kernels and results (bit for bit), without the workspace; the
+   FP64 partial sums live in a static 32 KiB device array of the library, one
+   per GPU, kept until the process ends.  The call allocates nothing.  Calls
+   that overlap on one GPU (on different streams, or from several threads)
+   share that array and race: order them.  n_pix * n_maps may be at most
+   SYN_CHI2_MAX_VALUES; beyond it, and for the arguments syn_chi2 rejects,
+   SYN_EINVAL; a failing HIP call, SYN_EHIP. */
+#define SYN_CHI2_MAX_VALUES ((int64_t)1 << 36)
+syn_status syn_chi2_cotangent(int64_t n_pix, int32_t n_maps, const float* maps,
+                              const float* target, const double* inv_sigma2, float* dmaps,
+                              double* chi2, hipStream_t stream);
+
 /* One step of the Adam optimiser (Kingma & Ba 2015, arXiv:1412.6980,
    Algorithm 1) in place on n FP32 parameters, as used to fit a gridded field
    to observed maps in Sec. 3.3 (the gradient comes from syn_adjoint):

@@ -68,6 +68,7 @@ syn_forward = _sig("syn_forward", _i32, [_G, _F, _vp, _vp, _sz, _vp])
 syn_adjoint = _sig("syn_adjoint", _i32, [_G, _F, _vp, _vp, _sz, _vp, _vp, _vp, _vp])
 syn_chi2_workspace_bytes = _sig("syn_chi2_workspace_bytes", _sz, [_i64, _i32])
 syn_chi2 = _sig("syn_chi2", _i32, [_i64, _i32, _vp, _vp, _dp, _vp, _vp, _vp, _sz, _vp])
+syn_chi2_cotangent = _sig("syn_chi2_cotangent", _i32, [_i64, _i32, _vp, _vp, _dp, _vp, _vp, _vp])
 syn_sample_model16 = _sig("syn_sample_model16", _i32,
                           [_dp, ctypes.POINTER(_i32), _dp, _dp, _vp, _vp, _vp])
 syn_eval_fields = _sig("syn_eval_fields", _i32, [_F, _i64, _vp, _vp, _vp])
@@ -277,6 +278,29 @@ def chi2(maps: torch.Tensor, target: torch.Tensor, inv_sigma2, want_grad: bool =
                    inv.ctypes.data_as(_dp), _ptr(dm), out.data_ptr(), ws.data_ptr(), nws,
                    _stream(stream)), "syn_chi2")
     return out, dm
+
+
+def chi2_cotangent(maps: torch.Tensor, target: torch.Tensor, inv_sigma2, chi2_out: torch.Tensor,
+                   dmaps_out: Optional[torch.Tensor] = None, stream=None) -> None:
+    """chi2 into chi2_out (device float64 [1]) and dchi2/dmaps into dmaps_out,
+    through the entry point that allocates nothing (static device scratch)."""
+    _dev_f32(maps, "maps")
+    _dev_f32(target, "target")
+    if maps.shape != target.shape:
+        raise ValueError("maps and target differ in shape")
+    if dmaps_out is not None:
+        _dev_f32(dmaps_out, "dmaps_out")
+        if dmaps_out.shape != maps.shape:
+            raise ValueError("dmaps_out differs from maps in shape")
+    if chi2_out.dtype != torch.float64 or not chi2_out.is_cuda or chi2_out.numel() < 1:
+        raise ValueError("chi2_out must be a device float64 tensor")
+    n_maps = int(np.prod(maps.shape[:-1]))
+    n_pix = int(maps.shape[-1])
+    inv = np.ascontiguousarray(np.broadcast_to(np.asarray(inv_sigma2, dtype=np.float64).reshape(-1),
+                                               (n_maps,)))
+    check(syn_chi2_cotangent(n_pix, n_maps, maps.data_ptr(), target.data_ptr(),
+                             inv.ctypes.data_as(_dp), _ptr(dmaps_out), chi2_out.data_ptr(),
+                             _stream(stream)), "syn_chi2_cotangent")
 
 
 def sample_model16(theta, n_xyz, lo, hi, device="cuda", stream=None):

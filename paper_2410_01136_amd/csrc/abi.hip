@@ -479,6 +479,27 @@ syn_status syn_chi2(int64_t n_pix, int32_t n_maps, const float* maps, const floa
   return SYN_OK;
 }
 
+syn_status syn_chi2_cotangent(int64_t n_pix, int32_t n_maps, const float* maps,
+                              const float* target, const double* inv_sigma2, float* dmaps,
+                              double* chi2, hipStream_t stream) {
+  if (n_pix < 1 || n_maps < 1 || n_maps > 3 * SYN_MAX_FREQ) return fail(SYN_EINVAL, "need n_pix >= 1 and 1 <= n_maps <= 48");
+  if (n_pix > SYN_CHI2_MAX_VALUES / n_maps)
+    return fail(SYN_EINVAL, "n_pix * n_maps exceeds SYN_CHI2_MAX_VALUES (2^36)");
+  if (maps == nullptr || target == nullptr || inv_sigma2 == nullptr || chi2 == nullptr)
+    return fail(SYN_EINVAL, "maps, target, inv_sigma2 and chi2 are required");
+  if (((uintptr_t)chi2 & 7) != 0) return fail(SYN_EINVAL, "chi2 misaligned");
+  for (int i = 0; i < n_maps; ++i)
+    if (!(isfinite(inv_sigma2[i]) && inv_sigma2[i] >= 0.0)) return fail(SYN_EINVAL, "inv_sigma2 must be finite and >= 0");
+  const int64_t np = sm::chi2_partials(n_pix, n_maps);
+  if (np > sm::kChi2MaxPartials) return fail(SYN_EINVAL, "more chi2 partial sums than the static scratch holds");
+  double* scratch = nullptr;
+  hipError_t e = sm::chi2_scratch(&scratch);
+  if (e != hipSuccess) return hip_fail(e, "chi2 scratch address");
+  e = sm::launch_chi2(n_pix, n_maps, maps, target, inv_sigma2, dmaps, chi2, scratch, np, stream);
+  if (e != hipSuccess) return hip_fail(e, "chi2 launch");
+  return SYN_OK;
+}
+
 syn_status syn_sample_model16(const double* theta, const int32_t n[3], const double lo[3],
                               const double hi[3], float* out_bn, float* out_c,
                               hipStream_t stream) {

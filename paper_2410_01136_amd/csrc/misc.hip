@@ -1,5 +1,8 @@
 // Small kernels around the march: the chi^2 cotangent, sampling the analytic
 // model onto grid nodes, and point evaluation of any field kind.
+#include <atomic>
+#include <mutex>
+
 #include "sm_device.h"
 #include "sm_launch.h"
 
@@ -52,8 +55,44 @@ int64_t chi2_partials(int64_t n_pix, int n_maps) {
   const int64_t total = n_pix * n_maps;
   int64_t nb = (total + 256 * 8 - 1) / (256 * 8);
   if (nb < 1) nb = 1;
-  if (nb > 4096) nb = 4096;
+  if (nb > kChi2MaxPartials) nb = kChi2MaxPartials;
   return nb;
+}
+
+// Scratch of the chi^2 entry point that allocates nothing: its per-block FP64
+// partial sums live in this file-scope device array (32 KiB; every GPU the
+// library runs on holds its own copy until the process ends).  k_chi2 writes
+// every partial that k_sum_fixed then reads, so nothing needs clearing between
+// calls; calls that overlap on one GPU share the array and race.
+static __device__ __align__(256) double scratch[kChi2MaxPartials];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::atomic<double*> g_scratch_ptr[kMaxScratchDevices];
+std::mutex g_scratch_mu;
+}  // namespace
+
+// Device address of the current GPU's copy of the chi^2 scratch array, looked up
+// once per device (with that device current) and kept.
+hipError_t chi2_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  double* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (p == nullptr) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (p == nullptr) {
+      void* a = nullptr;
+      e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      p = static_cast<double*>(a);
+      g_scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return hipSuccess;
 }
 
 hipError_t launch_chi2(int64_t n_pix, int n_maps, const float* maps, const float* target,

@@ -106,6 +106,11 @@ hipError_t launch_chi2(int64_t n_pix, int n_maps, const float* maps, const float
                        const double* inv_s2, float* dmaps, double* chi2, double* partials,
                        int64_t n_partials, hipStream_t st);
 int64_t chi2_partials(int64_t n_pix, int n_maps);
+// Largest number of chi^2 partial sums (the block count is capped here), and
+// the device address of the current GPU's static scratch array that holds
+// that many for the entry point that allocates nothing.
+constexpr int64_t kChi2MaxPartials = 4096;
+hipError_t chi2_scratch(double** out);
 
 hipError_t launch_adam(int64_t n, int period, uint32_t mask, float* p, const float* g, float* m,
                        float* v, int t, double lr, double b1, double b2, double eps,
