@@ -20,19 +20,32 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sync_oracle.c")
 _LIB = os.path.join(_HERE, "libsync_oracle.so")
+_LIB_SAN = os.path.join(_HERE, "libsync_oracle_san.so")
+# SYNC_ORACLE_LIB names another build of the same source to load instead (the
+# sanitized one: its process must preload the clang ASan runtime)
+_LIB_OVERRIDE = os.environ.get("SYNC_ORACLE_LIB")
 
 MODEL16, GRID, SPHERE, WMAP = 0, 1, 2, 4
 NPARAM = 16
 MAX_FREQ = 16
 
 
-def build(quiet: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
-           "-o", _LIB + ".tmp", _SRC, "-lm"]
+def build(quiet: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math); with sanitize,
+    a second copy with clang under AddressSanitizer and UndefinedBehaviorSanitizer."""
+    if sanitize:
+        clang = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "clang")
+        out = _LIB_SAN
+        cmd = [clang, "-O1", "-g", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+               "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+               "-fno-omit-frame-pointer", "-shared-libsan", "-o", out + ".tmp", _SRC, "-lm"]
+    else:
+        out = _LIB
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+               "-o", out + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True, capture_output=quiet)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 class _Geom(ctypes.Structure):
@@ -57,9 +70,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    if _LIB_OVERRIDE:
+        lib = ctypes.CDLL(_LIB_OVERRIDE)
+    else:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
     dp = ctypes.POINTER(ctypes.c_double)
     gp, fp = ctypes.POINTER(_Geom), ctypes.POINTER(_Field)
     lib.or_forward.argtypes = [gp, fp, dp]

@@ -15,7 +15,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsynmarch.so")
+# SYNMARCH_LIB names another build of the same sources to load instead (the
+# host-sanitized one: its process must preload the clang ASan runtime)
+LIB_PATH = os.environ.get("SYNMARCH_LIB") or os.path.join(_HERE, "libsynmarch.so")
 
 SYN_OK, SYN_EINVAL, SYN_EUNSUPPORTED, SYN_ENOMEM, SYN_EHIP, SYN_EWORKSPACE = 0, -1, -2, -3, -4, -5
 FIELD_MODEL16, FIELD_GRID, FIELD_SPHERE, FIELD_MLP, FIELD_WMAP = 0, 1, 2, 3, 4
