@@ -152,8 +152,12 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
    dgrid_bn (device, float [nz][ny][nx][4]) and dgrid_c (device, float
    [nz][ny][nx]) when non-NULL (atomic float adds: bitwise order may vary).
    ws must be the workspace of the syn_forward call with the same geom and
-   field.  Sightlines are recomputed in reverse step order; the Faraday sum is
-   rebuilt from its stored total, so no per-step state is stored. */
+   field: the library records, per workspace address, a hash of the geometry
+   and field (parameters and grid pointers included) of the last syn_forward
+   that wrote it, and returns SYN_EWORKSPACE for a workspace no forward wrote
+   or one written under another geometry or field.  Sightlines are
+   recomputed in reverse step order; the Faraday sum is rebuilt from its
+   stored total, so no per-step state is stored. */
 syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float* dmaps,
                        void* ws, size_t ws_bytes, double* dtheta, float* dgrid_bn,
                        float* dgrid_c, hipStream_t stream);
@@ -301,6 +305,33 @@ int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix);
    SYN_EINVAL for any other mode. */
 syn_status syn_set_grid_addressing(int32_t mode);
 int32_t syn_get_grid_addressing(void);
+
+/* Autotuned launch shapes (the project's tuner, which times every lane count
+   and grid read mode on the workload at hand and caches the fastest).
+   syn_autotune_load reads the tuner's cache file (path: host string): a JSON
+   object whose keys are
+     "<device name>|<build id>|k<kernel>|f<field kind>|p<npix>|n<n_steps>|q<n_freq>"
+   (with a trailing "|g" when the value carries a grid read mode) and whose
+   values are a lane count (1, 4, 16, 64) or [lane count, grid read mode 2|3].
+   Entries whose build id is not this library's (syn_build_id: a hash of the
+   sources it was built from) are stale and skipped; the rest replace the
+   table.  From then on a syn_forward, syn_adjoint or syn_batch_create whose
+   kernel family, field kind, N_side, step count and frequency count (1 for
+   batch plans, whose npix is the plan's total) match an entry for the current
+   device (name "*": any device) uses its lane count -- unless one was set
+   with syn_set_lanes_per_ray -- and, for gridded forwards under automatic
+   grid addressing, its read mode.  A missing or unreadable file, malformed
+   JSON, a malformed key or a value out of range returns SYN_EINVAL and leaves
+   the table as it was (calls then keep their previous or built-in shapes).
+   Process-wide. */
+syn_status syn_autotune_load(const char* path);
+void syn_autotune_clear(void);
+int32_t syn_autotune_entries(void);
+/* 1 and the table's lane count and grid read mode (0: none) if an entry
+   applies to this shape on the current device, else 0. */
+int32_t syn_autotune_lookup(int32_t kernel, int32_t field_kind, int64_t npix, int32_t n_steps,
+                            int32_t n_freq, int32_t* lanes, int32_t* grid_mode);
+const char* syn_build_id(void);
 
 const char* syn_last_error(void);
 int32_t syn_version(void);

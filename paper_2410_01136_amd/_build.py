@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import hashlib
 import os
 import subprocess
 
@@ -47,10 +48,21 @@ def asan_runtime() -> str:
     return r.stdout.strip()
 
 
-def _compile(src: str, sanitize: bool) -> str:
+def build_id() -> str:
+    """Hash of the library's sources (csrc/ and the public header); compiled in as
+    the build id that keys the autotuner's cache."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(CSRC, "*"))) + [os.path.join(HERE, "..", "include", "synmarch.h")]:
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, sanitize: bool, bid: str) -> str:
     sub = "san" if sanitize else ""
     obj = os.path.join(BUILD_DIR, sub, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, *(SAN_FLAGS if sanitize else []), "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *(SAN_FLAGS if sanitize else []), f'-DSYN_BUILD_ID="{bid}"', "-c", src,
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -60,8 +72,9 @@ def _compile(src: str, sanitize: bool) -> str:
 def build(verbose: bool = False, sanitize: bool = False) -> str:
     os.makedirs(os.path.join(BUILD_DIR, "san" if sanitize else ""), exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    bid = build_id()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, sanitize), srcs))
+        objs = list(ex.map(lambda s: _compile(s, sanitize, bid), srcs))
     lib = LIB_SAN if sanitize else LIB
     tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *(SAN_LINK if sanitize else []),

@@ -90,6 +90,12 @@ syn_adam_step = _sig("syn_adam_step", _i32, [_i64, _i32, ctypes.c_uint32, _vp, _
                                              _i32, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, _vp])
 syn_get_grid_addressing = _sig("syn_get_grid_addressing", _i32, [])
+syn_autotune_load = _sig("syn_autotune_load", _i32, [ctypes.c_char_p])
+syn_autotune_clear = _sig("syn_autotune_clear", None, [])
+syn_autotune_entries = _sig("syn_autotune_entries", _i32, [])
+syn_autotune_lookup = _sig("syn_autotune_lookup", _i32, [_i32, _i32, _i64, _i32, _i32,
+                                                         ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+syn_build_id = _sig("syn_build_id", ctypes.c_char_p, [])
 syn_host_nest_pixel = _sig("syn_host_nest_pixel", _i32,
                            [_i32, _i64, ctypes.POINTER(_i64), _dp, _dp])
 

@@ -7,13 +7,16 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/synmarch.h"
 #include "batch.h"
 #include "sm_device.h"
 #include "sm_launch.h"
+#include "tune_table.h"
 
 namespace {
 
@@ -84,6 +87,20 @@ int lanes_for(int kernel, int kind, int64_t npix) {
   const int s = (kernel >= 0 && kernel < 3 && kind >= 0 && kind < 5) ? g_lanes[kernel][kind].load()
                                                                       : 0;
   return s > 0 ? s : default_lanes(kernel, kind, npix);
+}
+
+// Launch shape of a call: a lane count set with syn_set_lanes_per_ray wins,
+// then the autotuned table for this exact shape (syn_autotune_load), then the
+// built-in choice.  *grid_mode receives the table's grid read mode (0: none).
+int lanes_for_shape(int kernel, int kind, int64_t npix, int steps, int freqs, int* grid_mode) {
+  *grid_mode = 0;
+  const int s = (kernel >= 0 && kernel < 3 && kind >= 0 && kind < 5) ? g_lanes[kernel][kind].load()
+                                                                      : 0;
+  int tl = 0, tm = 0;
+  const bool tuned = sm::tune_lookup(kernel, kind, npix, steps, freqs, &tl, &tm);
+  if (tuned) *grid_mode = tm;
+  if (s > 0) return s;
+  return tuned ? tl : default_lanes(kernel, kind, npix);
 }
 
 // ---- argument checks --------------------------------------------------------
@@ -343,6 +360,66 @@ size_t ws_bytes_for(int64_t npix, bool adjoint, bool ff) {
          (size_t)sm::march_blocks(npix, 64) * sm::kNParam * sizeof(double);
 }
 
+// ---- workspace tags --------------------------------------------------------
+// syn_forward records, per workspace address, a hash of the geometry and field
+// it ran with; syn_adjoint accepts a workspace only under the same hash, so a
+// workspace from another geometry, field or parameter vector (whose stored
+// Faraday totals would give a silently wrong gradient), or one no forward has
+// written, is refused.  Host-side only: nothing is read back from the device.
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+  template <class T>
+  void add(const T& v) { bytes(&v, sizeof(v)); }
+};
+
+uint64_t ws_tag(const syn_geom* g, const syn_field* f) {
+  Fnv x;
+  x.add(g->nside);
+  x.add(g->n_steps);
+  x.bytes(g->r_obs_kpc, sizeof(g->r_obs_kpc));
+  x.add(g->r_max_kpc);
+  x.bytes(g->box_lo_kpc, sizeof(g->box_lo_kpc));
+  x.bytes(g->box_hi_kpc, sizeof(g->box_hi_kpc));
+  x.add(g->n_freq);
+  x.bytes(g->freq_hz, sizeof(double) * (size_t)g->n_freq);
+  x.add(f->kind);
+  x.bytes(f->theta, sizeof(f->theta));
+  x.bytes(f->grid_n, sizeof(f->grid_n));
+  x.bytes(f->grid_lo_kpc, sizeof(f->grid_lo_kpc));
+  x.bytes(f->grid_hi_kpc, sizeof(f->grid_hi_kpc));
+  x.add(f->grid_bn);
+  x.add(f->grid_c);
+  x.add(f->mlp);
+  x.add(f->te_k);
+  x.add(f->grid_alpha);
+  return x.h;
+}
+
+std::mutex g_ws_mu;
+std::unordered_map<uintptr_t, uint64_t> g_ws_tags;
+constexpr size_t kMaxWsTags = 1u << 20;  // the table is cleared when it grows past this
+
+void ws_record(const void* ws, uint64_t tag) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (g_ws_tags.size() >= kMaxWsTags) g_ws_tags.clear();
+  g_ws_tags[(uintptr_t)ws] = tag;
+}
+
+void ws_forget(const void* ws) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  g_ws_tags.erase((uintptr_t)ws);
+}
+
+bool ws_matches(const void* ws, uint64_t tag) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto it = g_ws_tags.find((uintptr_t)ws);
+  return it != g_ws_tags.end() && it->second == tag;
+}
+
 }  // namespace
 
 extern "C" {
@@ -405,9 +482,12 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
   if (field->kind == SYN_FIELD_MLP) {
     e = sm::launch_forward_mlp(ga, fa, emit_args(field->theta[12]), fp.mlp, maps, phi_end, stream);
   } else {
-    const int S = lanes_for(SYN_KERNEL_FORWARD, field->kind, ga.npix);
+    int tuned_mode = 0;
+    const int S = lanes_for_shape(SYN_KERNEL_FORWARD, field->kind, ga.npix, ga.n_steps,
+                                  geom->n_freq, &tuned_mode);
     if (field->kind == SYN_FIELD_GRID) {
-      const int mode = g_grid_addressing.load();
+      int mode = g_grid_addressing.load();
+      if (mode == 0 && tuned_mode != 0) mode = tuned_mode;
       // automatic: shared cell reads pay off once there are enough wavefronts
       // to hide their longer dependency chain (measured: N_side 256 gains 1.3x,
       // N_side 64 loses 10%)
@@ -419,7 +499,11 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
     e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, em_end,
                            stream);
   }
-  if (e != hipSuccess) return hip_fail(e, "forward launch");
+  if (e != hipSuccess) {
+    if (ws != nullptr) ws_forget(ws);
+    return hip_fail(e, "forward launch");
+  }
+  if (ws != nullptr) ws_record(ws, ws_tag(geom, field));
   return SYN_OK;
 }
 
@@ -441,11 +525,15 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   if (dgrid_c != nullptr && ((uintptr_t)dgrid_c & 3) != 0) return fail(SYN_EINVAL, "dgrid_c misaligned");
   if (dgrid_c != nullptr && field->kind == SYN_FIELD_GRID && field->grid_c == nullptr)
     return fail(SYN_EINVAL, "dgrid_c needs a gridded N0 (grid_c)");
-  if (dtheta == nullptr && dgrid_bn == nullptr && dgrid_c == nullptr) return SYN_OK;
   if (dtheta != nullptr && ((uintptr_t)dtheta & 7) != 0) return fail(SYN_EINVAL, "dtheta misaligned");
+  if (!ws_matches(ws, ws_tag(geom, field)))
+    return fail(SYN_EWORKSPACE, "workspace was not written by a syn_forward with this geometry and field");
+  if (dtheta == nullptr && dgrid_bn == nullptr && dgrid_c == nullptr) return SYN_OK;
   sm::FreqArgs fa;
   freq_args(geom, field->theta[12], field->te_k, &fa);
-  const int S = lanes_for(SYN_KERNEL_ADJOINT, field->kind, ga.npix);
+  int tuned_mode = 0;
+  const int S = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps, geom->n_freq,
+                                &tuned_mode);
   char* w = static_cast<char*>(ws);
   double* phi_end = reinterpret_cast<double*>(w);
   double* em_end = fp.ff ? reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix)) : nullptr;
@@ -568,6 +656,29 @@ syn_status syn_set_grid_addressing(int32_t mode) {
 
 int32_t syn_get_grid_addressing(void) { return g_grid_addressing.load(); }
 
+syn_status syn_autotune_load(const char* path) {
+  if (path == nullptr) return fail(SYN_EINVAL, "path is NULL");
+  int kept = 0;
+  std::string err;
+  if (!sm::tune_load(path, &kept, &err)) return fail(SYN_EINVAL, err);
+  return SYN_OK;
+}
+
+void syn_autotune_clear(void) { sm::tune_clear(); }
+
+int32_t syn_autotune_entries(void) { return sm::tune_entries(); }
+
+int32_t syn_autotune_lookup(int32_t kernel, int32_t field_kind, int64_t npix, int32_t n_steps,
+                            int32_t n_freq, int32_t* lanes, int32_t* grid_mode) {
+  int l = 0, m = 0;
+  if (!sm::tune_lookup(kernel, field_kind, npix, n_steps, n_freq, &l, &m)) return 0;
+  if (lanes != nullptr) *lanes = l;
+  if (grid_mode != nullptr) *grid_mode = m;
+  return 1;
+}
+
+const char* syn_build_id(void) { return sm::build_id(); }
+
 int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix) {
   return lanes_for(kernel, field_kind, npix);
 }
@@ -664,7 +775,9 @@ syn_status syn_batch_create(const syn_batch_desc* desc, syn_batch** plan) {
     if (st != SYN_OK) return st;
     all_pix += ga.npix;
   }
-  const int S = lanes_for(SYN_KERNEL_BATCH, desc->kind, all_pix);
+  int tuned_mode = 0;
+  const int S = lanes_for_shape(SYN_KERNEL_BATCH, desc->kind, all_pix, desc->geom.n_steps, 1,
+                                &tuned_mode);
   std::vector<sm::BatchSet> sets(desc->n_sets);
   std::vector<int64_t> offsets(desc->n_sets);
   int64_t total = 0, items = 0;

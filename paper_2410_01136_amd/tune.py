@@ -1,19 +1,20 @@
 """Launch-shape autotuner for the march kernels.
 
-The one tunable of every kernel family is S, the number of lanes that share a
-sightline (1, 4, 16 or 64): larger S gives more parallelism for small maps
-(few sightlines), smaller S fewer scan instructions and more register reuse
-for large maps.  The tuner times each candidate with HIP events on the
-workload at hand and applies the fastest through syn_set_lanes_per_ray.
-Results are cached in a JSON file keyed by device, kernel-source hash and
-workload shape (environment variable SYNMARCH_TUNE_CACHE, default
-~/.cache/synmarch/tune.json); a missing or unreadable cache falls back to the
-built-in choice.
+The tunables are S, the number of lanes that share a sightline (1, 4, 16 or
+64): larger S gives more parallelism for small maps (few sightlines), smaller
+S fewer scan instructions and more register reuse for large maps; and, for
+gridded forwards, the grid read path (per-lane buffer reads or cells shared
+through LDS).  The tuner times each candidate with HIP events on the workload
+at hand and applies the fastest through syn_set_lanes_per_ray.  Results are
+cached in a JSON file keyed by device, the library's build id (a hash of its
+sources) and workload shape (environment variable SYNMARCH_TUNE_CACHE,
+default ~/.cache/synmarch/tune.json); a missing or unreadable cache falls back
+to the built-in choice.  load() hands the cache to the library
+(syn_autotune_load), which then applies the tuned shapes by itself to every
+call of a matching shape, with no Python in the loop.
 """
 from __future__ import annotations
 
-import glob
-import hashlib
 import json
 import os
 from typing import Callable, Dict, Iterable, Optional
@@ -26,7 +27,6 @@ CANDIDATES = (1, 4, 16, 64)
 # grid read modes tried for gridded forwards (syn_set_grid_addressing):
 # 2 = per-lane buffer reads, 3 = cell reads shared through LDS
 GRID_MODES = (2, 3)
-_HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def cache_path() -> str:
@@ -35,11 +35,17 @@ def cache_path() -> str:
 
 
 def source_hash() -> str:
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(_HERE, "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    """The loaded library's build id (hash of the sources it was built from)."""
+    return sm.syn_build_id().decode()
+
+
+def load(path: Optional[str] = None) -> int:
+    """Hands the cache to the library (syn_autotune_load); returns the number of
+    entries it kept (those tuned on this build).  Raises SynError when the file
+    is missing or malformed; the library's table is then unchanged."""
+    p = path or cache_path()
+    sm.check(sm.syn_autotune_load(p.encode()), "syn_autotune_load")
+    return int(sm.syn_autotune_entries())
 
 
 def _key(kernel: int, kind: int, npix: int, n_steps: int, n_freq: int) -> str:
@@ -47,22 +53,30 @@ def _key(kernel: int, kind: int, npix: int, n_steps: int, n_freq: int) -> str:
     return f"{dev}|{source_hash()}|k{kernel}|f{kind}|p{npix}|n{n_steps}|q{n_freq}"
 
 
+def _lane_count(v) -> bool:
+    return isinstance(v, int) and not isinstance(v, bool) and v in CANDIDATES
+
+
 def _valid(v) -> bool:
     # a lane count, or [lane count, grid read mode]
-    if isinstance(v, int):
-        return v in CANDIDATES
-    return (isinstance(v, list) and len(v) == 2 and v[0] in CANDIDATES
-            and v[1] in GRID_MODES)
+    if _lane_count(v):
+        return True
+    return (isinstance(v, list) and len(v) == 2 and _lane_count(v[0])
+            and isinstance(v[1], int) and not isinstance(v[1], bool) and v[1] in GRID_MODES)
 
 
 def load_cache(path: Optional[str] = None) -> Dict[str, object]:
+    """The cache as a dict of valid entries; {} (the built-in shapes) when the
+    file is missing, unreadable or not a JSON object."""
     path = path or cache_path()
     try:
         with open(path) as f:
             d = json.load(f)
-        return {k: v for k, v in d.items() if _valid(v)}
     except (OSError, ValueError, TypeError):
         return {}
+    if not isinstance(d, dict):
+        return {}
+    return {k: v for k, v in d.items() if isinstance(k, str) and _valid(v)}
 
 
 def save_cache(d: Dict[str, int], path: Optional[str] = None) -> None:

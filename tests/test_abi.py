@@ -120,6 +120,15 @@ def test_workspace_checks_on_host(sm):
     assert st == sm.SYN_EINVAL
 
 
+def test_adjoint_refuses_a_workspace_no_forward_wrote(sm):
+    g = _geom(sm)
+    f = sm.model16(I.THETA0)
+    need = sm.workspace_bytes(g, f, True)
+    st = sm.syn_adjoint(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, 0x7000, need, 0x3000,
+                        None, None, None)
+    assert st == sm.SYN_EWORKSPACE and "not written by a syn_forward" in sm.syn_last_error().decode()
+
+
 def test_sphere_has_no_adjoint(sm):
     g = _geom(sm)
     f = sm.sphere(I.sphere_theta())

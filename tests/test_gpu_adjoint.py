@@ -228,3 +228,33 @@ def test_c2_full_size_grid_gradient(sm, orc, lanes, S):
     _, rbn, _ = orc.adjoint(oracle_geom(orc, g), ofield, dm.astype(np.float64), want_grid=True)
     check_grid_gradient(dbn.cpu().numpy(), rbn,
                         f"C2 full grid S={sm.get_lanes_per_ray(1, sm.FIELD_GRID, g.npix)}")
+
+
+def test_adjoint_refuses_a_mismatched_workspace(sm):
+    """A workspace carries the tag of the forward that wrote it: an adjoint at
+    other parameters or another geometry is refused, the matching one runs."""
+    import torch
+    g = I.geometry("C0", nside=4, n_steps=32)
+    geom = sm.geom_from(g)
+    f = sm.model16(THETA_T)
+    ws = sm.alloc_workspace(geom, f)
+    sm.forward(geom, f, ws=ws)
+    dm = torch.from_numpy(I.cotangents((1, 3, g.npix), seed=28)).cuda()
+    th2 = THETA_T.copy()
+    th2[0] *= 1.01
+    with pytest.raises(sm.SynError) as e:
+        sm.adjoint(geom, sm.model16(th2), dm, ws)
+    assert e.value.status == sm.SYN_EWORKSPACE
+    geom2 = sm.geom_from(I.geometry("C0", nside=4, n_steps=33))
+    with pytest.raises(sm.SynError) as e:
+        sm.adjoint(geom2, f, dm, ws)
+    assert e.value.status == sm.SYN_EWORKSPACE
+    d = sm.adjoint(geom, f, dm, ws)
+    torch.cuda.synchronize()
+    assert torch.isfinite(d).all()
+    # a forward under other parameters re-tags the workspace
+    sm.forward(geom, sm.model16(th2), ws=ws)
+    with pytest.raises(sm.SynError):
+        sm.adjoint(geom, f, dm, ws)
+    sm.adjoint(geom, sm.model16(th2), dm, ws)
+    torch.cuda.synchronize()
