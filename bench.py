@@ -34,13 +34,23 @@ METRIC = "sightline-steps/s (pix×steps×freqs) fwd & adjoint vs plain, at state
 # v_fma_f64 (whose peak is 78.6 TFLOP/s) and reach 124 TFLOP/s at 8 wavefronts
 # per SIMD, so the kernels, built without packed FP32, are priced against it.
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense
 PEAK_HBM_GBS = 8000.0
-# Algorithmic work of one (sightline, step) of the gridded forward at 3 frequencies,
-# counted from the method (FMA = 2, other arithmetic or transcendental = 1):
-#   midpoint 8, trilinear of 5 channels 117, projections 13, Faraday increment and
-#   midpoint prefix 4, emission at alpha = 3 9, I sum 1, and per frequency: phase 1,
-#   reduction 2, sin+cos 2, rotation 6, Q/U sums 2 (= 13) -> 152 + 3 * 13 = 191.
-FLOP_PER_PIX_STEP_C1 = 191.0
+# Algorithmic work per (sightline, step), counted from the method as the survey
+# of the path prices it (arithmetic operations and transcendentals, 1 each):
+#   gridded forward: trilinear interpolation of 5 channels 92, projections and
+#     emission 40, 3 transcendentals, and per frequency 12 + 2 transcendentals
+#     -> 135 + 14 per frequency (177 at the headline's 3 frequencies);
+#   analytic forward (16-parameter model): 110 + 18 transcendentals + 2 FP64
+#     adds at one frequency (130), + 14 per extra frequency;
+#   reverse pass: 3.5 x its forward (the paper's gradient costs 2-4 forwards;
+#     the recompute is one of them);
+#   MLP surrogate: 2 (32*128 + 3*128^2 + 128*5) = 107,776 matrix-core flops.
+FLOP_PER_PIX_STEP_C1 = 135.0 + 3 * 14.0
+FLOP_GRID_FWD_1F = 135.0 + 14.0
+FLOP_M16_FWD_1F = 130.0
+ADJ_OVER_FWD_FLOPS = 3.5
+FLOP_MLP_PER_STEP = 2.0 * (32 * 128 + 3 * 128 * 128 + 128 * 5)
 # Compulsory HBM bytes of one launch: the grids are read once, maps written once.
 GATHER_BYTES_PER_PIX_STEP = 160.0  # 8 corners x 5 channels x 4 B from cache
 
@@ -88,6 +98,16 @@ def grid_read_path(sm, npix: int) -> str:
     if mode == 3 or (mode == 0 and npix >= (1 << 18)):
         return "buffer reads of each distinct cell shared through LDS"
     return "buffer reads, per lane"
+
+
+def alu_roofline(flop_per_unit, units, launch_ms, kernel):
+    """Roofline entry of an FP32-bound kernel: algorithmic flops per launch over
+    the launch's mean time from HIP events, against the FP32 vector peak."""
+    achieved = flop_per_unit * units / (launch_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": kernel, "flop_per_unit": flop_per_unit, "units_per_launch": units,
+            "launch_ms": round(launch_ms, 4)}
 
 
 def time_launches(fn, steps, warmup):
@@ -313,6 +333,8 @@ def bench_adjoint(sm, I, np, torch, tune, args):
         "fwd_chi2_adj_ms": round(t_wall, 4),
         "lanes_per_ray": {"forward": sm.get_lanes_per_ray(0, 0, g.npix),
                           "adjoint": sm.get_lanes_per_ray(1, 0, g.npix)},
+        "roofline": alu_roofline(ADJ_OVER_FWD_FLOPS * FLOP_M16_FWD_1F, units, a_ev,
+                                 "sm::k_adjoint<Model16NoGrid, ...> + sm::k_reduce_partials"),
     }
     log("C2 theta:", res["theta"])
     # grid gradient: B and n_e on 128^3 nodes sampled from theta0, analytic N0
@@ -344,6 +366,8 @@ def bench_adjoint(sm, I, np, torch, tune, args):
         "forward_sightline_steps_per_s": float(f"{units / (gf_ev * 1e-3):.4e}"),
         "adjoint_sightline_steps_per_s": float(f"{units / (ga_ev * 1e-3):.4e}"),
         "adjoint_over_forward_time": round(ga_ev / gf_ev, 3),
+        "roofline": alu_roofline(ADJ_OVER_FWD_FLOPS * FLOP_GRID_FWD_1F, units, ga_ev,
+                                 "sm::k_adjoint<Grid, ..., grid gradient> (reverse march with the grid scatter)"),
     }
     log("C2 grid:", res["grid"])
     res["grid"]["lanes_per_ray"] = {"forward": sm.get_lanes_per_ray(0, 1, g.npix),
@@ -408,10 +432,10 @@ def bench_free_free(sm, I, np, torch, args, grid_field):
     the thermal electrons of the fields) on the headline gridded workload
     (N_side 256, 512 steps, 256^3 nodes) moved to {150, 300, 600} MHz and on the
     N_side 64 / 768 step analytic theta-gradient workload (forward + adjoint)
-    at the same frequencies, each timed with and without; and the headline
+    at {0.6, 0.8, 1.0} GHz, each timed with and without; and the headline
     forward with a gridded spectral index, timed with and without."""
-    freqs = (0.15e9, 0.3e9, 0.6e9)
-    te = 8000.0
+    freqs = I.FF_GRID_FREQS
+    te = I.TE_FF
     g = I.geometry("C1", freqs_hz=freqs)
     geom = sm.geom_from(g)
     maps = torch.empty((len(freqs), 3, g.npix), dtype=torch.float32, device="cuda")
@@ -420,10 +444,11 @@ def bench_free_free(sm, I, np, torch, args, grid_field):
         f = grid_field.with_te(t)
         _, ev = time_launches(lambda: sm.forward(geom, f, maps=maps), args.steps, args.warmup)
         grid_ms["free_free" if t else "plain"] = round(ev, 4)
-    g2 = I.geometry("C2", freqs_hz=freqs)
+    freqs2 = I.FF_THETA_FREQS
+    g2 = I.geometry("C2", freqs_hz=freqs2)
     geom2 = sm.geom_from(g2)
-    dm = torch.from_numpy(I.cotangents((len(freqs), 3, g2.npix), seed=7001)).cuda()
-    maps2 = torch.empty((len(freqs), 3, g2.npix), dtype=torch.float32, device="cuda")
+    dm = torch.from_numpy(I.cotangents((len(freqs2), 3, g2.npix), seed=7001)).cuda()
+    maps2 = torch.empty((len(freqs2), 3, g2.npix), dtype=torch.float32, device="cuda")
     theta_ms = {}
     for t in (0.0, te):
         f = sm.model16(I.THETA0).with_te(t)
@@ -450,8 +475,9 @@ def bench_free_free(sm, I, np, torch, args, grid_field):
         _, ev = time_launches(lambda: sm.forward(geom1, f, maps=maps1), args.steps, args.warmup)
         alpha_ms[name] = round(ev, 4)
     res = {
-        "workload": "T_e 8000 K; 256^3 grid at N_side 256 x 512 steps and analytic model at "
-                    "N_side 64 x 768 steps (forward + theta-adjoint), both at {150, 300, 600} MHz; "
+        "workload": "T_e 8000 K; 256^3 grid at N_side 256 x 512 steps at {150, 300, 600} MHz and "
+                    "analytic model at N_side 64 x 768 steps (forward + theta-adjoint) at "
+                    "{0.6, 0.8, 1.0} GHz; "
                     "gridded spectral index on the 256^3 headline forward at {1, 2.3, 5} GHz",
         "alpha_grid_forward_ms": alpha_ms,
         "alpha_grid_over_plain": round(alpha_ms["alpha_grid"] / alpha_ms["plain"], 3),
@@ -651,7 +677,8 @@ def bench_surrogate(sm, I, np, torch, args, grid_field):
     pa = torch.hypot(a[1], a[2])
     pb = torch.hypot(b[1], b[2])
     units = g.npix * g.n_steps
-    flops = 2.0 * (32 * 128 + 3 * 128 * 128 + 128 * 5) * units
+    flops = FLOP_MLP_PER_STEP * units
+    achieved = flops / (s_ev * 1e-3) / 1e12
     res = {
         "workload": "N_side 512 (3,145,728 sightlines), 1024 steps, 1 GHz, 40x40x8 kpc box; MLP 3 -> "
                     "16 Fourier -> 4 x 128 GELU -> 5, BF16 weights, FP32 accumulation",
@@ -659,8 +686,11 @@ def bench_surrogate(sm, I, np, torch, args, grid_field):
         "train_loss_standardised": tr.final_loss,
         "surrogate_ms": round(s_ev, 2),
         "surrogate_sightline_steps_per_s": float(f"{units / (s_ev * 1e-3):.4e}"),
-        "mfma_tflops": round(flops / (s_ev * 1e-3) / 1e12, 2),
-        "mfma_frac_of_bf16_peak": round(flops / (s_ev * 1e-3) / 2.5e15, 4),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4),
+                     "traffic": None, "kernel": "sm::k_forward_mlp (v_mfma_f32_32x32x16_bf16)",
+                     "flop_per_unit": FLOP_MLP_PER_STEP, "units_per_launch": units,
+                     "launch_ms": round(s_ev, 3)},
         "plain_trilinear_ms": round(p_ev, 3),
         "plain_sightline_steps_per_s": float(f"{units / (p_ev * 1e-3):.4e}"),
         "surrogate_over_plain_time": round(s_ev / p_ev, 2),
@@ -705,6 +735,21 @@ def cpu_baseline_leg(sm, I, np, torch, g, noise, geom, seconds):
         "kind": "oracle",
         "sample": f"{pix.size} seeded random pixels of the headline workload (all 512 steps, "
                   f"3 frequencies), {dt:.1f} s",
+    }
+    # the same oracle on one host core, on a sample of a quarter of the time
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        n1 = int(max(16, min(pix.size, pix.size / max(threads, 1) / 4)))
+        t0 = time.perf_counter()
+        oracle.forward_pixels(og, ofield, pix[:n1])
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    cpu["one_core"] = {
+        "value": float(f"{n1 * g.n_steps * len(g.freqs_hz) / dt1:.4e}"),
+        "cores": 1,
+        "sample": f"the first {n1} pixels of the sample above, {dt1:.1f} s",
     }
     log("cpu baseline:", cpu)
     # GPU on the same (oracle-built) grids, compared on the sampled pixels

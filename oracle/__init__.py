@@ -101,6 +101,7 @@ def _load():
     lib.or_sample_model16.argtypes = [dp, ctypes.POINTER(ctypes.c_int32), dp, dp,
                                       ctypes.c_void_p, ctypes.c_void_p]
     lib.or_num_threads.restype = ctypes.c_int
+    lib.or_set_num_threads.argtypes = [ctypes.c_int]
     lib.or_midpoints.argtypes = [gp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
     lib.or_forward_tabulated.argtypes = [gp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int64, dp, dp]
@@ -279,6 +280,11 @@ def kff(nu, te_k):
 
 def num_threads():
     return _load().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (n >= 1)."""
+    _load().or_set_num_threads(int(n))
 
 
 def midpoints(geom: _Geom, pix) -> np.ndarray:

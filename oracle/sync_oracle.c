@@ -947,6 +947,16 @@ int or_sample_model16(const double* theta, const int32_t n[3], const double lo[3
   return 0;
 }
 
+/* Thread count of the OpenMP loops over pixels (for timing on a given number
+   of host cores). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -85,6 +85,16 @@ FIT_BOX_HI = (20.0, 20.0, 5.0)
 FIT_GRID = (128, 128, 32)  # nodes (x, y, z) of the fitted B grid
 
 
+# Free-free workloads (T_e = 8000 K): the 256^3 gridded headline forward at low
+# radio frequencies, and the N_side 64 / 768-step analytic forward + adjoint at
+# frequencies where the disk model at theta0 is not yet so Faraday-thick that
+# FP32 field values limit its depolarised Q/U (below ~0.5 GHz over the
+# 40 x 40 x 8 kpc box).
+TE_FF = 8000.0
+FF_GRID_FREQS = (0.15e9, 0.3e9, 0.6e9)
+FF_THETA_FREQS = (0.6e9, 0.8e9, 1.0e9)
+
+
 def geometry(name: str, **over) -> Geometry:
     """The geometry of a named configuration (keyword overrides allowed)."""
     base = {

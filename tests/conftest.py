@@ -18,3 +18,16 @@ def orc():
     import oracle
     oracle._load()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def c1_grids(orc):
+    """The headline's 256^3 node grids over the 40 x 40 x 8 kpc box: the
+    spiral-disk model sampled by the oracle plus the seeded k^-11/3 turbulence
+    (B: 50% of the local regular field; n_e: lognormal), and the model's N0."""
+    from paper_2410_01136_amd import inputs as I
+    print("building 256^3 grids", flush=True)
+    reg_bn, reg_c = orc.sample_model16(I.THETA0, (256, 256, 256), I.BOX_LO, I.BOX_HI)
+    bn = I.turbulent_grids(reg_bn)
+    del reg_bn
+    return bn, reg_c

@@ -230,3 +230,47 @@ def test_grid_gradient_few_steps(sm, orc, lanes, S):
     _, rbn, rc = orc.adjoint(oracle_geom(orc, g), of, dm.astype(np.float64), want_grid=True)
     for a, b in ((dbn.cpu().numpy().astype(np.float64), rbn), (dc.cpu().numpy().astype(np.float64), rc)):
         check_grid_gradient(a, b, f"few-step grid ff S={S}")
+
+
+@pytest.mark.slow
+def test_bench_theta_workload(sm, orc):
+    """The benchmark's analytic free-free leg as it runs: N_side 64, 768 steps,
+    40 x 40 x 8 kpc box, theta0, T_e 8000 K at {0.6, 0.8, 1.0} GHz, forward and
+    theta-adjoint of the benchmark's cotangents; maps strict except the disk
+    model's most depolarised pixels (declared FP32 term floor, at most 0.1% of
+    each frequency's pixels)."""
+    import torch
+    g = I.geometry("C2", freqs_hz=I.FF_THETA_FREQS)
+    nf = len(g.freqs_hz)
+    field = sm.model16(I.THETA0).with_te(I.TE_FF)
+    geom = sm.geom_from(g)
+    ws = sm.alloc_workspace(geom, field)
+    maps = sm.forward(geom, field, ws=ws)
+    dm = I.cotangents((nf, 3, g.npix), seed=7001)
+    dth = sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws)
+    torch.cuda.synchronize()
+    og = oracle_geom(orc, g)
+    of = orc.Field(orc.MODEL16, I.THETA0, te_k=I.TE_FF)
+    check(maps.cpu().numpy(), orc.forward(og, of), "bench theta ff", FP32_TERMS, nf * g.npix // 1000)
+    ref, _, _ = orc.adjoint(og, of, dm.astype(np.float64))
+    assert_theta_close(dth.cpu().numpy(), ref, I.THETA0, "bench theta ff gradient")
+
+
+@pytest.mark.slow
+def test_bench_grid_workload(sm, orc, c1_grids):
+    """The benchmark's gridded free-free leg as it runs: the 256^3 headline
+    grids at N_side 256, 512 steps, {150, 300, 600} MHz, T_e 8000 K, in the
+    built-in launch shape; 1500 sampled pixels against the oracle (declared FP32
+    term floor for at most 1% of them per frequency)."""
+    import torch
+    g = I.geometry("C1", freqs_hz=I.FF_GRID_FREQS)
+    bn, c = c1_grids
+    f = sm.grid(I.THETA0, torch.from_numpy(bn).cuda(), torch.from_numpy(c).cuda(), I.BOX_LO,
+                I.BOX_HI).with_te(I.TE_FF)
+    gpu = gpu_maps(sm, g, f)
+    pix = I.sample_pixels(g.npix, 1500, seed=79)
+    ref = orc.forward_pixels(oracle_geom(orc, g), orc.Field(orc.GRID, I.THETA0, grid_bn=bn, grid_c=c,
+                                                            grid_lo=I.BOX_LO, grid_hi=I.BOX_HI,
+                                                            te_k=I.TE_FF), pix)
+    check(gpu[:, :, pix], np.transpose(ref, (1, 2, 0)), "bench grid ff", FP32_TERMS,
+          len(g.freqs_hz) * pix.size // 100)

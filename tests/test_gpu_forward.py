@@ -161,15 +161,12 @@ def test_lanes_agree_closely(sm, lanes):
 
 
 @pytest.mark.slow
-def test_c1_full_size_sampled(sm, orc):
+def test_c1_full_size_sampled(sm, orc, c1_grids):
     """Full C1 shape (N_side 256, 512 steps, 3 freqs, 256^3 grids) in the launch
     configuration the benchmark times; the oracle checks 1500 sampled pixels."""
     import torch
     g = I.geometry("C1")
-    print("building 256^3 grids", flush=True)
-    reg_bn, reg_c = orc.sample_model16(I.THETA0, (256, 256, 256), I.BOX_LO, I.BOX_HI)
-    bn = I.turbulent_grids(reg_bn)
-    del reg_bn
+    bn, reg_c = c1_grids
     f_gpu = sm.grid(I.THETA0, torch.from_numpy(bn).cuda(), torch.from_numpy(reg_c).cuda(),
                     I.BOX_LO, I.BOX_HI)
     gpu = run_gpu(sm, g, f_gpu)
