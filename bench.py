@@ -143,11 +143,12 @@ def main() -> int:
     ap.add_argument("--fit-lr", type=float, default=0.05, help="Adam step size of the grid fit [uG]")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample")
-    ap.add_argument("--only", choices=("c1", "c2", "fit", "wmap", "hmc", "ff", "copy"), default=None,
+    ap.add_argument("--only", choices=("c1", "c2", "c4", "fit", "wmap", "hmc", "ff", "copy"), default=None,
                     help="profiling aids: 'c1' runs only the timed headline forward launches; "
                          "'c2' only the N_side 64 adjoint workloads (analytic and 128^3 grid); "
                          "'fit' only the grid fit; 'wmap' only the Sec. 3.1 replay; "
                          "'hmc' only the Sec. 3.2 sampler; 'ff' only the free-free workloads; "
+                         "'c4' only the surrogate (training, then its timed launches); "
                          "'copy' runs one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -211,6 +212,9 @@ def main() -> int:
 
     if args.only == "ff":
         bench_free_free(sm, I, np, torch, args, field)
+        return 0
+    if args.only == "c4":
+        bench_surrogate(sm, I, np, torch, args, field)
         return 0
     if not args.no_tune and args.only is None:
         t = tune.tune_forward(geom, field, maps=maps, use_cache=False, write_cache=False)
@@ -358,6 +362,10 @@ def bench_adjoint(sm, I, np, torch, tune, args):
         log("tuned C2 grid adjoint:", tune.tune_adjoint(geom, gfield, state["dm"], gws,
                                                        want_theta=False, dgrid_bn=dbn,
                                                        use_cache=False, write_cache=False))
+        # the forward stores the sums at the piece ends of the tuned reverse pass:
+        # size the workspace for them
+        gws = sm.alloc_workspace(geom, gfield)
+        gfwd()
 
     gf_wall, gf_ev = time_launches(gfwd, args.steps, args.warmup)
     ga_wall, ga_ev = time_launches(gadj, args.steps, args.warmup)
@@ -667,6 +675,13 @@ def bench_surrogate(sm, I, np, torch, args, grid_field):
     mf = S.mlp_field(tr.model, packed, alpha=3.0)
     g = I.geometry("C4")
     geom = sm.geom_from(g)
+    # the plain evaluator judges the surrogate on the same sky at N_side 64 and
+    # replaces it beyond 5% rms on I or 10% rms on PI
+    probe = sm.geom_from(I.geometry("C4", nside=64))
+    t0 = time.perf_counter()
+    judged = S.judge(mf, grid_field, probe)
+    torch.cuda.synchronize()
+    judge_ms = (time.perf_counter() - t0) * 1e3
     m_mlp = torch.empty((1, 3, g.npix), dtype=torch.float32, device="cuda")
     m_grid = torch.empty_like(m_mlp)
     s_wall, s_ev = time_launches(lambda: sm.forward(geom, mf, maps=m_mlp), 3, 1)
@@ -694,6 +709,9 @@ def bench_surrogate(sm, I, np, torch, args, grid_field):
         "plain_trilinear_ms": round(p_ev, 3),
         "plain_sightline_steps_per_s": float(f"{units / (p_ev * 1e-3):.4e}"),
         "surrogate_over_plain_time": round(s_ev / p_ev, 2),
+        "fallback": {"judge": "plain trilinear march of the same fields, N_side 64 x 1024 steps",
+                     "used": "surrogate" if judged.used_surrogate else "plain",
+                     "probe_error": judged.error, "judge_ms": round(judge_ms, 2)},
         "map_error_vs_plain": {
             "I_rel_rms": rms(a[0] - b[0]) / rms(b[0]),
             "Q_rel_rms": rms(a[1] - b[1]) / rms(b[1]),

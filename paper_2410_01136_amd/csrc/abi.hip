@@ -360,6 +360,19 @@ size_t ws_bytes_for(int64_t npix, bool adjoint, bool ff) {
          (size_t)sm::march_blocks(npix, 64) * sm::kNParam * sizeof(double);
 }
 
+// Piece snapshots for a grid-gradient reverse pass of `pieces` pieces (see
+// GridArgs): quantities per piece end, and their bytes (0 when there are no
+// pieces or they would take more than kMaxSnapBytes; the reverse pass then
+// recomputes its pieces' sums itself).
+constexpr size_t kMaxSnapBytes = (size_t)1 << 31;
+int snap_quantities(int n_freq, bool ff) { return 1 + 2 * n_freq + (ff ? 1 + 2 * n_freq : 0); }
+
+size_t snap_bytes(int64_t npix, int pieces, int n_freq, bool ff) {
+  if (pieces < 2) return 0;
+  const size_t b = (size_t)pieces * (size_t)snap_quantities(n_freq, ff) * (size_t)npix * sizeof(double);
+  return b > kMaxSnapBytes ? 0 : (b + 255) / 256 * 256;
+}
+
 // ---- workspace tags --------------------------------------------------------
 // syn_forward records, per workspace address, a hash of the geometry and field
 // it ran with; syn_adjoint accepts a workspace only under the same hash, so a
@@ -399,14 +412,20 @@ uint64_t ws_tag(const syn_geom* g, const syn_field* f) {
   return x.h;
 }
 
+// With the tag goes the piece count of the snapshots the forward stored (0:
+// none).
+struct WsRecord {
+  uint64_t tag;
+  int pieces;
+};
 std::mutex g_ws_mu;
-std::unordered_map<uintptr_t, uint64_t> g_ws_tags;
+std::unordered_map<uintptr_t, WsRecord> g_ws_tags;
 constexpr size_t kMaxWsTags = 1u << 20;  // the table is cleared when it grows past this
 
-void ws_record(const void* ws, uint64_t tag) {
+void ws_record(const void* ws, uint64_t tag, int pieces) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   if (g_ws_tags.size() >= kMaxWsTags) g_ws_tags.clear();
-  g_ws_tags[(uintptr_t)ws] = tag;
+  g_ws_tags[(uintptr_t)ws] = WsRecord{tag, pieces};
 }
 
 void ws_forget(const void* ws) {
@@ -414,10 +433,12 @@ void ws_forget(const void* ws) {
   g_ws_tags.erase((uintptr_t)ws);
 }
 
-bool ws_matches(const void* ws, uint64_t tag) {
+// The piece count recorded with a matching tag (>= 0), or -1 for no match.
+int ws_matches(const void* ws, uint64_t tag) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   auto it = g_ws_tags.find((uintptr_t)ws);
-  return it != g_ws_tags.end() && it->second == tag;
+  if (it == g_ws_tags.end() || it->second.tag != tag) return -1;
+  return it->second.pieces;
 }
 
 }  // namespace
@@ -433,7 +454,15 @@ size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t
   sm::FieldPack fp;
   if (check_geom(geom, &ga) != SYN_OK) return 0;
   if (check_field(field, &fp, false) != SYN_OK) return 0;
-  return ws_bytes_for(ga.npix, with_adjoint != 0, fp.ff);
+  if (with_adjoint == 0) return 0;
+  size_t b = ws_bytes_for(ga.npix, true, fp.ff);
+  if (field->kind == SYN_FIELD_GRID) {
+    int tm = 0;
+    const int pieces = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps,
+                                       geom->n_freq, &tm);
+    b += snap_bytes(ga.npix, pieces, geom->n_freq, fp.ff);
+  }
+  return b;
 }
 
 // Whether the forward may read this grid with 32-bit buffer offsets: the float4
@@ -470,11 +499,26 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
   if (maps == nullptr || ((uintptr_t)maps & 3) != 0) return fail(SYN_EINVAL, "maps must be a 4-byte aligned device pointer");
   double* phi_end = nullptr;
   double* em_end = nullptr;
+  int pieces = 0;  // snapshots stored for a grid-gradient reverse pass of this many pieces
   if (ws != nullptr) {
-    if (ws_bytes < ws_bytes_for(ga.npix, true, fp.ff) || ((uintptr_t)ws & 7) != 0)
+    const size_t base = ws_bytes_for(ga.npix, true, fp.ff);
+    if (ws_bytes < base || ((uintptr_t)ws & 7) != 0)
       return fail(SYN_EWORKSPACE, "workspace smaller than syn_workspace_bytes(...,1) or misaligned");
     phi_end = static_cast<double*>(ws);
     if (fp.ff) em_end = reinterpret_cast<double*>(static_cast<char*>(ws) + ws_phi_bytes(ga.npix));
+    if (field->kind == SYN_FIELD_GRID) {
+      int tm = 0;
+      const int p = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps,
+                                    geom->n_freq, &tm);
+      const size_t sb = snap_bytes(ga.npix, p, geom->n_freq, fp.ff);
+      if (sb > 0 && ws_bytes >= base + sb) {
+        pieces = p;
+        fp.grid.snap = reinterpret_cast<double*>(static_cast<char*>(ws) + base);
+        fp.grid.pieces = p;
+        fp.grid.piece_len = (ga.n_steps + p - 1) / p;
+        fp.grid.snap_nq = snap_quantities(geom->n_freq, fp.ff);
+      }
+    }
   }
   sm::FreqArgs fa;
   freq_args(geom, field->theta[12], field->te_k, &fa);
@@ -503,7 +547,7 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
     if (ws != nullptr) ws_forget(ws);
     return hip_fail(e, "forward launch");
   }
-  if (ws != nullptr) ws_record(ws, ws_tag(geom, field));
+  if (ws != nullptr) ws_record(ws, ws_tag(geom, field), pieces);
   return SYN_OK;
 }
 
@@ -526,18 +570,28 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   if (dgrid_c != nullptr && field->kind == SYN_FIELD_GRID && field->grid_c == nullptr)
     return fail(SYN_EINVAL, "dgrid_c needs a gridded N0 (grid_c)");
   if (dtheta != nullptr && ((uintptr_t)dtheta & 7) != 0) return fail(SYN_EINVAL, "dtheta misaligned");
-  if (!ws_matches(ws, ws_tag(geom, field)))
+  const int pieces = ws_matches(ws, ws_tag(geom, field));
+  if (pieces < 0)
     return fail(SYN_EWORKSPACE, "workspace was not written by a syn_forward with this geometry and field");
   if (dtheta == nullptr && dgrid_bn == nullptr && dgrid_c == nullptr) return SYN_OK;
   sm::FreqArgs fa;
   freq_args(geom, field->theta[12], field->te_k, &fa);
   int tuned_mode = 0;
-  const int S = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps, geom->n_freq,
-                                &tuned_mode);
+  int S = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps, geom->n_freq,
+                          &tuned_mode);
   char* w = static_cast<char*>(ws);
   double* phi_end = reinterpret_cast<double*>(w);
   double* em_end = fp.ff ? reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix)) : nullptr;
   double* partials = reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix) * (fp.ff ? 2 : 1));
+  if (pieces >= 2 && (dgrid_bn != nullptr || dgrid_c != nullptr)) {
+    // the forward stored the sums at the ends of `pieces` pieces: split the
+    // sightlines the same way and skip the pre-pass over each piece
+    S = pieces;
+    fp.grid.snap = reinterpret_cast<double*>(w + ws_bytes_for(ga.npix, true, fp.ff));
+    fp.grid.pieces = pieces;
+    fp.grid.piece_len = (ga.n_steps + pieces - 1) / pieces;
+    fp.grid.snap_nq = snap_quantities(geom->n_freq, fp.ff);
+  }
   hipError_t e = sm::launch_adjoint(ga, fa, emit_args(field->theta[12]), fp, S, dmaps, phi_end,
                                     em_end, partials, dtheta, dgrid_bn, dgrid_c, stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");

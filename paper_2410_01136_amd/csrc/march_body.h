@@ -55,7 +55,11 @@ constexpr bool exact_freqs(int MF) { return MF == 1 || MF == 3; }
 // Gridded spectral index (VA): the emission of a segment uses the local alpha,
 // its exponent in B_perp and its frequency prefactors (one ratio per
 // frequency to the prefactors of theta[12]), so the I sum is per frequency.
-template <class F, int S, int MF, bool FF = false, bool VA = false, class FA>
+//
+// PC (gridded fields only): also store the piece snapshots of fld.p (the
+// running sums at the piece ends of the grid-gradient reverse pass), so that
+// pass needs no pre-pass over its pieces.
+template <class F, int S, int MF, bool FF = false, bool VA = false, bool PC = false, class FA>
 __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, float* __restrict__ maps,
                                 MapAddr ma, double* __restrict__ phi_end,
@@ -78,10 +82,14 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 #pragma unroll
   for (int f = 0; f < MFF; ++f) accF[f] = 0.0;
 
+  constexpr int MPC = PC ? MF : 1;
+  double tq[MPC], tu[MPC], ti[PC && PF ? MF : 1], tf[PC && FF ? MF : 1];  // PC: this step's terms
   for (int c0 = 0; c0 < g.n_steps; c0 += S) {
     const int n = c0 + sub;
     const bool act = n < g.n_steps;
     const double s = ((double)n + 0.5) * ray.dkpc;  // midpoint of segment n
+    const double carry0 = carry, emc0 = emc;  // PC: sums before this chunk
+    double fincl = 0.0, eincl = 0.0;          // PC: inclusive chunk scans
     // (the shared-read grid brings a gridded alpha with its cell records)
     constexpr bool VA_SHARED = VA && std::is_same_v<F, GridL>;
     double al = 0.0;
@@ -102,6 +110,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       const double incl = group_inclusive_scan<S>(cn, sub);
       psi = carry + incl - 0.5 * cn;
       carry += group_last<S>(incl);
+      fincl = incl;
     }
     float w = 0.0f, emd = 0.0f;  // FF: n_e^2 of this segment, emission measure * dkpc
     if constexpr (FF) {
@@ -114,6 +123,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
         const double incl = group_inclusive_scan<S>((double)w, sub);
         em = emc + incl - 0.5 * (double)w;
         emc += group_last<S>(incl);
+        eincl = incl;
       }
       emd = (float)(em * ray.dkpc);
     }
@@ -142,14 +152,64 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
             const float att = exp2f(-(float)fa.kffl2[f] * emd);
             mI *= att;
             mP *= att;
-            accF[f] += (double)(att * w);
+            const double t = (double)(att * w);
+            accF[f] += t;
+            if constexpr (PC) tf[f] = t;
           }
           zr *= mP;
           zi *= mP;
-          accIf[f] += (double)(mI * e.u);
+          const double t = (double)(mI * e.u);
+          accIf[f] += t;
+          if constexpr (PC) ti[f] = t;
         }
-        accQ[f] += (double)(zr * cs - zi * sn);
-        accU[f] += (double)(zr * sn + zi * cs);
+        const double tq1 = (double)(zr * cs - zi * sn), tu1 = (double)(zr * sn + zi * cs);
+        accQ[f] += tq1;
+        accU[f] += tu1;
+        if constexpr (PC) {
+          tq[f] = tq1;
+          tu[f] = tu1;
+        }
+      }
+    }
+    if constexpr (PC) {
+      // piece ends inside this chunk (those at or beyond the last step are
+      // written after the loop, from the totals): sums over the steps before b
+      for (int k = c0 / fld.p.piece_len + 1;
+           k <= fld.p.pieces && k * fld.p.piece_len <= c0 + S && k * fld.p.piece_len < g.n_steps;
+           ++k) {
+        const int b = k * fld.p.piece_len;
+        const bool before = n < b;
+        double* out = fld.p.snap + (int64_t)(k - 1) * fld.p.snap_nq * ma.stride + ma.off + ray.ring;
+        const int64_t st = ma.stride;
+        const double phib = S == 1 ? carry : carry0 + group_bcast<S>(fincl, b - 1 - c0);
+        if (valid && sub == 0) out[0] = phib;
+#pragma unroll
+        for (int f = 0; f < MF; ++f) {
+          if (exact_freqs(MF) || f < fa.n_freq) {
+            const double pq = group_sum<S>(before ? accQ[f] : accQ[f] - tq[f]);
+            const double pu = group_sum<S>(before ? accU[f] : accU[f] - tu[f]);
+            if (valid && sub == 0) {
+              out[(1 + 2 * f) * st] = pq;
+              out[(2 + 2 * f) * st] = pu;
+            }
+          }
+        }
+        if constexpr (FF) {
+          const int nf = fa.n_freq;
+          const double emb = S == 1 ? emc : emc0 + group_bcast<S>(eincl, b - 1 - c0);
+          if (valid && sub == 0) out[(1 + 2 * nf) * st] = emb;
+#pragma unroll
+          for (int f = 0; f < MF; ++f) {
+            if (exact_freqs(MF) || f < nf) {
+              const double pi = group_sum<S>(before ? accIf[f] : accIf[f] - ti[f]);
+              const double pf = group_sum<S>(before ? accF[f] : accF[f] - tf[f]);
+              if (valid && sub == 0) {
+                out[(2 + 2 * nf + f) * st] = pi;
+                out[(2 + 3 * nf + f) * st] = pf;
+              }
+            }
+          }
+        }
       }
     }
   }
@@ -188,6 +248,35 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     if (phi_end != nullptr) phi_end[ma.off + ray.ring] = carry;
     if constexpr (FF)
       if (em_end != nullptr) em_end[ma.off + ray.ring] = emc;
+  }
+  if constexpr (PC) {
+    // piece ends at or beyond the last step: the totals
+    if (valid && sub == 0) {
+      const int nf = fa.n_freq;
+      const int64_t st = ma.stride;
+      for (int k = max(1, (g.n_steps + fld.p.piece_len - 1) / fld.p.piece_len); k <= fld.p.pieces;
+           ++k) {
+        double* out = fld.p.snap + (int64_t)(k - 1) * fld.p.snap_nq * st + ma.off + ray.ring;
+        out[0] = carry;
+#pragma unroll
+        for (int f = 0; f < MF; ++f) {
+          if (exact_freqs(MF) || f < nf) {
+            out[(1 + 2 * f) * st] = accQ[f];
+            out[(2 + 2 * f) * st] = accU[f];
+          }
+        }
+        if constexpr (FF) {
+          out[(1 + 2 * nf) * st] = emc;
+#pragma unroll
+          for (int f = 0; f < MF; ++f) {
+            if (exact_freqs(MF) || f < nf) {
+              out[(2 + 2 * nf + f) * st] = accIf[f];
+              out[(2 + 3 * nf + f) * st] = accF[f];
+            }
+          }
+        }
+      }
+    }
   }
 }
 
@@ -264,91 +353,123 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     const int len = (g.n_steps + S - 1) / S;
     n_lo = min(sub * len, g.n_steps);
     n_hi = min(n_lo + len, g.n_steps);
-    // per frequency: W = sum z a e^{2 pi i t}, U = sum u a, V = sum w a, with the
-    // phase t and the attenuation a counted from the piece start
-    double A = 0.0, Ak = 0.0, Wr[MF], Wi[MF], Uf[MFF], Vf[MFF];
+    if (fld.p.snap != nullptr) {
+      // The forward stored the running sums at every piece end (S pieces of this
+      // length): the piece's own sums are differences of those at its two ends,
+      // with the absolute phase and attenuation already applied, so
+      //   B_k = Im(sum_f k_f dP_f),  X_k = -sum_f kd_f (gi_f dU_f + cf_f dV_f + Re(h_f dP_f)).
+      const int nf = fa.n_freq;
+      const int64_t st = g.npix;
+      const double* hi_end = fld.p.snap + (int64_t)sub * fld.p.snap_nq * st + ray.ring;
+      const double* lo_end = fld.p.snap + (int64_t)(sub > 0 ? sub - 1 : 0) * fld.p.snap_nq * st + ray.ring;
+      auto lo_at = [&](int j) { return sub > 0 ? lo_end[j * st] : 0.0; };
+      double Bk = 0.0, Xk = 0.0;
 #pragma unroll
-    for (int f = 0; f < MF; ++f) Wr[f] = Wi[f] = 0.0;
-#pragma unroll
-    for (int f = 0; f < MFF; ++f) Uf[f] = Vf[f] = 0.0;
-    for (int n = n_lo; n < n_hi; ++n) {
-      const FV v = fld.eval_at(g, ray, ((double)n + 0.5) * dk);
-      const float bl = v.bx * ray.elx + v.by * ray.ely;
-      const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
-      const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);
-      const double cn = (double)v.ne * bpar;
-      const double psid = (A + 0.5 * cn) * dk;  // Faraday sum from the piece start
-      A += cn;
-      float w = 0.0f, emd = 0.0f;
+      for (int f = 0; f < MF; ++f) {
+        if (f < nf) {
+          const double dPr = hi_end[(1 + 2 * f) * st] - lo_at(1 + 2 * f);
+          const double dPi = hi_end[(2 + 2 * f) * st] - lo_at(2 + 2 * f);
+          Bk += kr[f] * dPi + ki[f] * dPr;
+          if constexpr (FF) {
+            const double dU = hi_end[(2 + 2 * nf + f) * st] - lo_at(2 + 2 * nf + f);
+            const double dV = hi_end[(2 + 3 * nf + f) * st] - lo_at(2 + 3 * nf + f);
+            Xk -= kd[f] * (gi_f[f] * dU + cf[f] * dV + hr[f] * dPr - hi[f] * dPi);
+          }
+        }
+      }
+      E = hi_end[0];
+      suf = group_suffix_scan<S>(Bk, sub) - Bk;
       if constexpr (FF) {
-        w = v.ne * v.ne;
-        emd = (float)((Ak + 0.5 * (double)w) * dk);
-        Ak += (double)w;
+        EM = hi_end[(1 + 2 * nf) * st];
+        sufE = group_suffix_scan<S>(Xk, sub) - Xk;
       }
-      double al = 0.0;
-      VaStep vs{};
-      if constexpr (VA) {
-        al = fld.alpha_at(g, ray, ((double)n + 0.5) * dk, ea.va_alpha_ref);
-        vs = va_step(al, ea);
+    } else {
+      // per frequency: W = sum z a e^{2 pi i t}, U = sum u a, V = sum w a, with the
+      // phase t and the attenuation a counted from the piece start
+      double A = 0.0, Ak = 0.0, Wr[MF], Wi[MF], Uf[MFF], Vf[MFF];
+#pragma unroll
+      for (int f = 0; f < MF; ++f) Wr[f] = Wi[f] = 0.0;
+#pragma unroll
+      for (int f = 0; f < MFF; ++f) Uf[f] = Vf[f] = 0.0;
+      for (int n = n_lo; n < n_hi; ++n) {
+        const FV v = fld.eval_at(g, ray, ((double)n + 0.5) * dk);
+        const float bl = v.bx * ray.elx + v.by * ray.ely;
+        const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
+        const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);
+        const double cn = (double)v.ne * bpar;
+        const double psid = (A + 0.5 * cn) * dk;  // Faraday sum from the piece start
+        A += cn;
+        float w = 0.0f, emd = 0.0f;
+        if constexpr (FF) {
+          w = v.ne * v.ne;
+          emd = (float)((Ak + 0.5 * (double)w) * dk);
+          Ak += (double)w;
+        }
+        double al = 0.0;
+        VaStep vs{};
+        if constexpr (VA) {
+          al = fld.alpha_at(g, ray, ((double)n + 0.5) * dk, ea.va_alpha_ref);
+          vs = va_step(al, ea);
+        }
+        const Emit e =
+            VA ? emission(v.n0, bl, bb, false, vs.eI) : emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
+#pragma unroll
+        for (int f = 0; f < MF; ++f) {
+          if (f < fa.n_freq) {
+            float sn, cs;
+            sincos_turns(psid * fa.kappa[f], &sn, &cs);
+            float zr = e.zr, zi = e.zi;
+            if constexpr (PF) {
+              float mI = 1.0f, mP = 1.0f;
+              if constexpr (VA) {
+                mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
+                mP = mI * vs.prat;
+              }
+              if constexpr (FF) {
+                const float att = exp2f(-(float)fa.kffl2[f] * emd);
+                mI *= att;
+                mP *= att;
+                Vf[f] += (double)(att * w);
+              }
+              zr *= mP;
+              zi *= mP;
+              if constexpr (FF) Uf[f] += (double)(mI * e.u);
+            }
+            Wr[f] += (double)(zr * cs - zi * sn);
+            Wi[f] += (double)(zr * sn + zi * cs);
+          }
+        }
       }
-      const Emit e =
-          VA ? emission(v.n0, bl, bb, false, vs.eI) : emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
+      const double incl = group_inclusive_scan<S>(A, sub);
+      const double psid0 = (incl - A) * dk;  // Faraday sum of the earlier pieces
+      double emincl = 0.0, emd0 = 0.0;
+      if constexpr (FF) {
+        emincl = group_inclusive_scan<S>(Ak, sub);
+        emd0 = (emincl - Ak) * dk;  // emission measure of the earlier pieces
+      }
+      double Bk = 0.0;  // sum of this piece's phase cotangents
+      double Xk = 0.0;  // FF: sum of this piece's emission-measure cotangents
 #pragma unroll
       for (int f = 0; f < MF; ++f) {
         if (f < fa.n_freq) {
           float sn, cs;
-          sincos_turns(psid * fa.kappa[f], &sn, &cs);
-          float zr = e.zr, zi = e.zi;
-          if constexpr (PF) {
-            float mI = 1.0f, mP = 1.0f;
-            if constexpr (VA) {
-              mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
-              mP = mI * vs.prat;
-            }
-            if constexpr (FF) {
-              const float att = exp2f(-(float)fa.kffl2[f] * emd);
-              mI *= att;
-              mP *= att;
-              Vf[f] += (double)(att * w);
-            }
-            zr *= mP;
-            zi *= mP;
-            if constexpr (FF) Uf[f] += (double)(mI * e.u);
+          sincos_turns(psid0 * fa.kappa[f], &sn, &cs);
+          double a0 = 1.0;
+          if constexpr (FF) a0 = (double)exp2f(-(float)(fa.kffl2[f] * emd0));
+          const double rr = kr[f] * cs - ki[f] * sn, ri = kr[f] * sn + ki[f] * cs;
+          Bk += a0 * (rr * Wi[f] + ri * Wr[f]);  // Im(k e^{2 pi i t0} a0 W)
+          if constexpr (FF) {
+            const double Rr = hr[f] * cs - hi[f] * sn, Ri = hr[f] * sn + hi[f] * cs;
+            Xk -= kd[f] * a0 * (gi_f[f] * Uf[f] + cf[f] * Vf[f] + Rr * Wr[f] - Ri * Wi[f]);
           }
-          Wr[f] += (double)(zr * cs - zi * sn);
-          Wi[f] += (double)(zr * sn + zi * cs);
         }
       }
-    }
-    const double incl = group_inclusive_scan<S>(A, sub);
-    const double psid0 = (incl - A) * dk;  // Faraday sum of the earlier pieces
-    double emincl = 0.0, emd0 = 0.0;
-    if constexpr (FF) {
-      emincl = group_inclusive_scan<S>(Ak, sub);
-      emd0 = (emincl - Ak) * dk;  // emission measure of the earlier pieces
-    }
-    double Bk = 0.0;  // sum of this piece's phase cotangents
-    double Xk = 0.0;  // FF: sum of this piece's emission-measure cotangents
-#pragma unroll
-    for (int f = 0; f < MF; ++f) {
-      if (f < fa.n_freq) {
-        float sn, cs;
-        sincos_turns(psid0 * fa.kappa[f], &sn, &cs);
-        double a0 = 1.0;
-        if constexpr (FF) a0 = (double)exp2f(-(float)(fa.kffl2[f] * emd0));
-        const double rr = kr[f] * cs - ki[f] * sn, ri = kr[f] * sn + ki[f] * cs;
-        Bk += a0 * (rr * Wi[f] + ri * Wr[f]);  // Im(k e^{2 pi i t0} a0 W)
-        if constexpr (FF) {
-          const double Rr = hr[f] * cs - hi[f] * sn, Ri = hr[f] * sn + hi[f] * cs;
-          Xk -= kd[f] * a0 * (gi_f[f] * Uf[f] + cf[f] * Vf[f] + Rr * Wr[f] - Ri * Wi[f]);
-        }
+      E = incl;
+      suf = group_suffix_scan<S>(Bk, sub) - Bk;
+      if constexpr (FF) {
+        EM = emincl;
+        sufE = group_suffix_scan<S>(Xk, sub) - Xk;
       }
-    }
-    E = incl;
-    suf = group_suffix_scan<S>(Bk, sub) - Bk;
-    if constexpr (FF) {
-      EM = emincl;
-      sufE = group_suffix_scan<S>(Xk, sub) - Xk;
     }
   } else if (valid) {
     E = phi_end[ma.off + ray.ring];
@@ -385,11 +506,28 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   // every lane of a wavefront runs the same number of iterations (the grid
   // scatter is collective); a short or empty last piece idles through the rest
   const int n_iter = SPLIT ? (g.n_steps + S - 1) / S : SERIAL ? g.n_steps : (g.n_steps + S - 1) / S;
+  auto step_of = [&](int it) { return SERIAL ? n_lo + it : it * S + sub; };
+  // GRID: the corner reads of the step visited next (the one before it along
+  // the sightline) are issued before the current step's work, so that their
+  // latency overlaps it
+  using FetchT = std::conditional_t<GRID, Grid::Fetch, int>;
+  using CellT = std::conditional_t<GRID, Grid::Cell, int>;
+  FetchT fnext{};
+  if constexpr (GRID) fld.fetch(g, ray, ((double)step_of(n_iter - 1) + 0.5) * dk, fnext);
   for (int it = n_iter - 1; it >= 0; --it) {
-    const int n = SERIAL ? n_lo + it : it * S + sub;
+    const int n = step_of(it);
     const bool act = valid && n < n_hi;
     const double s = ((double)n + 0.5) * dk;
-    const FV v = fld.eval_at(g, ray, s);
+    FV v;
+    CellT cell{};
+    if constexpr (GRID) {
+      const FetchT fcur = fnext;
+      if (it > 0) fld.fetch(g, ray, ((double)step_of(it - 1) + 0.5) * dk, fnext);
+      v = fld.interp(g, ray, s, fcur);
+      cell = fcur.c;
+    } else {
+      v = fld.eval_at(g, ray, s);
+    }
     const float bl = v.bx * ray.elx + v.by * ray.ely;
     const float bb = v.bx * ray.ebx + v.by * ray.eby + v.bz * ray.ebz;
     const double bpar = -((double)v.bx * ray.nx + (double)v.by * ray.ny + (double)v.bz * ray.nz);
@@ -528,7 +666,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
         if constexpr (ALPHA_GRAD) tbf[12] += eb.alpha;
       }
     }
-    if constexpr (GRID) fld.accumulate_step(g, ray, s, gv, act, acc, gbn, gc);
+    if constexpr (GRID) fld.accumulate_cell(cell, gv, act, acc, gbn, gc);
   }
   if constexpr (GRID) fld.flush_all(acc, gbn, gc);
   if constexpr (THETA) {

@@ -10,7 +10,8 @@
 
 namespace sm {
 
-template <class F, int S, int MF, bool FF, bool VA>
+// PC: gridded fields only, also store the piece snapshots (fld.p.snap).
+template <class F, int S, int MF, bool FF, bool VA, bool PC = false>
 __global__ __launch_bounds__(256) void k_forward(GeomArgs g, FreqArgs fa, EmitArgs ea, F fld,
                                                  float* __restrict__ maps,
                                                  double* __restrict__ phi_end,
@@ -21,24 +22,34 @@ __global__ __launch_bounds__(256) void k_forward(GeomArgs g, FreqArgs fa, EmitAr
   int64_t q = tid / S;
   const bool valid = q < g.npix;
   if (!valid) q = g.npix - 1;  // idle lanes march a real sightline, results dropped
-  fwd_lane<F, S, MF, FF, VA>(g, fa, ea, fld, q, sub, valid, maps, MapAddr{g.npix, 0}, phi_end,
-                             em_end);
+  fwd_lane<F, S, MF, FF, VA, PC>(g, fa, ea, fld, q, sub, valid, maps, MapAddr{g.npix, 0},
+                                 phi_end, em_end);
 }
 
-template <bool FF, bool VA, class F, int S>
-static hipError_t fwd_mf(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
-                         float* maps, double* phi_end, double* em_end, hipStream_t st) {
+template <bool FF, bool VA, bool PC, class F, int S>
+static hipError_t fwd_mf_pc(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
+                            float* maps, double* phi_end, double* em_end, hipStream_t st) {
   const int64_t nb = march_blocks(g.npix, S);
   const dim3 grid((unsigned)nb), block(256);
   if (fa.n_freq <= 1)
-    k_forward<F, S, 1, FF, VA><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
+    k_forward<F, S, 1, FF, VA, PC><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
   else if (std::is_same_v<F, GridL> && fa.n_freq == 3)  // the three-frequency gridded maps
-    k_forward<F, S, 3, FF, VA><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
+    k_forward<F, S, 3, FF, VA, PC><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
   else if (fa.n_freq <= 4)
-    k_forward<F, S, 4, FF, VA><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
+    k_forward<F, S, 4, FF, VA, PC><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
   else
-    k_forward<F, S, 16, FF, VA><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
+    k_forward<F, S, 16, FF, VA, PC><<<grid, block, 0, st>>>(g, fa, ea, f, maps, phi_end, em_end);
   return hipGetLastError();
+}
+
+// gridded fields write piece snapshots when asked to (fld.p.snap set)
+template <bool FF, bool VA, class F, int S>
+static hipError_t fwd_mf(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
+                         float* maps, double* phi_end, double* em_end, hipStream_t st) {
+  if constexpr (std::is_base_of_v<Grid, F>) {
+    if (f.p.snap != nullptr) return fwd_mf_pc<FF, VA, true, F, S>(g, fa, ea, f, maps, phi_end, em_end, st);
+  }
+  return fwd_mf_pc<FF, VA, false, F, S>(g, fa, ea, f, maps, phi_end, em_end, st);
 }
 
 template <bool FF, bool VA, class F>

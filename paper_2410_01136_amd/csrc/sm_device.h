@@ -349,13 +349,36 @@ struct Grid {
     return eval_at(g, r, s);
   }
   __device__ inline FV eval_at(const GeomArgs& g, const Ray& r, double s) const {
-    const Cell c = cell_at(g, r, s);
+    Fetch f;
+    fetch(g, r, s, f);
+    return interp(g, r, s, f);
+  }
+
+  // The cell of the midpoint at distance s and its corner values, read apart
+  // from the interpolation so that a reverse march can issue the reads of the
+  // next step before it works on the current one.  Corner k has x, y, z
+  // offsets (k & 1, (k >> 1) & 1, k >> 2).
+  struct Fetch {
+    Cell c;
+    float4 v[8];
+    float n0[8];
+  };
+  __device__ inline void fetch(const GeomArgs& g, const Ray& r, double s, Fetch& f) const {
+    f.c = cell_at(g, r, s);
     const int64_t sy = p.n[0], sz = (int64_t)p.n[0] * p.n[1];
-    const float4* gb = p.bn;
-    const float4 v000 = gb[c.base], v100 = gb[c.base + 1];
-    const float4 v010 = gb[c.base + sy], v110 = gb[c.base + sy + 1];
-    const float4 v001 = gb[c.base + sz], v101 = gb[c.base + sz + 1];
-    const float4 v011 = gb[c.base + sy + sz], v111 = gb[c.base + sy + sz + 1];
+    const int64_t o[8] = {0, 1, sy, sy + 1, sz, sz + 1, sy + sz, sy + sz + 1};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f.v[k] = p.bn[f.c.base + o[k]];
+    if (p.c != nullptr) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) f.n0[k] = p.c[f.c.base + o[k]];
+    }
+  }
+
+  __device__ inline FV interp(const GeomArgs& g, const Ray& r, double s, const Fetch& f) const {
+    const Cell& c = f.c;
+    const float4 v000 = f.v[0], v100 = f.v[1], v010 = f.v[2], v110 = f.v[3];
+    const float4 v001 = f.v[4], v101 = f.v[5], v011 = f.v[6], v111 = f.v[7];
     const float wx0 = 1.0f - c.tx, wy0 = 1.0f - c.ty, wz0 = 1.0f - c.tz;
     const float y0z0 = wy0 * wz0, y1z0 = c.ty * wz0;
     const float y0z1 = wy0 * c.tz, y1z1 = c.ty * c.tz;
@@ -374,10 +397,7 @@ struct Grid {
     v.bz = c.inside ? tri(v000.z, v100.z, v010.z, v110.z, v001.z, v101.z, v011.z, v111.z) : 0.0f;
     v.ne = c.inside ? tri(v000.w, v100.w, v010.w, v110.w, v001.w, v101.w, v011.w, v111.w) : 0.0f;
     if (p.c != nullptr) {
-      const float* gc = p.c;
-      v.n0 = c.inside ? tri(gc[c.base], gc[c.base + 1], gc[c.base + sy], gc[c.base + sy + 1],
-                            gc[c.base + sz], gc[c.base + sz + 1], gc[c.base + sy + sz],
-                            gc[c.base + sy + sz + 1])
+      v.n0 = c.inside ? tri(f.n0[0], f.n0[1], f.n0[2], f.n0[3], f.n0[4], f.n0[5], f.n0[6], f.n0[7])
                       : 0.0f;
     } else {
       v.n0 = cr.n0_at(smooth_x(g, r, s, 0), smooth_x(g, r, s, 1),
@@ -546,7 +566,10 @@ struct Grid {
   // at every step): the lanes that enter a new cell first send on the old one.
   __device__ inline void accumulate_step(const GeomArgs& g, const Ray& r, double s, const FV& gv,
                                          bool act, Acc& A, float* gbn, float* gc) const {
-    const Cell c = cell_at(g, r, s);
+    accumulate_cell(cell_at(g, r, s), gv, act, A, gbn, gc);
+  }
+  __device__ inline void accumulate_cell(const Cell& c, const FV& gv, bool act, Acc& A, float* gbn,
+                                         float* gc) const {
     const bool use = act && c.inside;
     flush_wave(A, use && A.base >= 0 && c.base != A.base, gbn, gc);
     if (!use) return;

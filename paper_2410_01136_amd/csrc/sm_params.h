@@ -45,6 +45,16 @@ struct GridArgs {
   // strides of one y row and one z plane in the float4 grid and in the N0 grid
   uint32_t bn_bytes, c_bytes;
   uint32_t sy16, sz16, sy4, sz4;
+  // Piece snapshots of a forward that a grid-gradient reverse pass will follow
+  // (nullptr: none).  The reverse pass cuts each sightline into `pieces`
+  // contiguous pieces of `piece_len` steps; at each piece end b_k = k piece_len
+  // (k = 1 .. pieces, capped at n_steps) the forward stores, per pixel, the
+  // running sums over the steps before b_k: the Faraday sum, per frequency the
+  // Q and U sums, and with free-free the emission-measure sum and per
+  // frequency the I and free-free sums.  Layout [k - 1][quantity][npix] with
+  // `snap_nq` quantities.
+  double* snap;
+  int32_t pieces, piece_len, snap_nq;
 };
 
 // Box of grid nodes in which one workgroup of the grid adjoint accumulates its

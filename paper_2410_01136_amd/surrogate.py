@@ -9,7 +9,10 @@ targets are the gridded fields evaluated by the library itself (trilinear
 interpolation on the GPU), with a mean-squared loss on standardised outputs.
 
 For inference the weights are rounded to BF16 and packed by syn_mlp_pack for
-the fused MFMA march kernel.  `reference_eval` repeats that BF16 computation
+the fused MFMA march kernel.  The plain evaluator (the field the surrogate
+stands in for) judges its map error and is the fallback: `judge` marches a
+probe geometry with both and keeps the surrogate only within stated error
+bounds.  `reference_eval` repeats that BF16 computation
 in plain PyTorch FP32 (BF16-rounded weights and layer inputs, FP32 sums) as
 the check of the kernel.
 """
@@ -169,3 +172,38 @@ def train(target_fn: Callable[[torch.Tensor], torch.Tensor], lo, hi, n_points: i
             if log:
                 log(f"surrogate step {it}: loss {loss_v:.4e}")
     return TrainResult(model=model, seconds=time.time() - t0, final_loss=loss_v, steps=steps)
+
+
+@dataclass
+class Judged:
+    """The field to march with after the plain evaluator judged the surrogate:
+    the surrogate's own field if its map error on the probe stayed within the
+    bounds, else the plain field it stands in for (the fallback)."""
+    field: sm.Field
+    used_surrogate: bool
+    error: dict
+
+
+def map_error(maps: torch.Tensor, ref: torch.Tensor) -> dict:
+    """Relative rms errors of I, Q, U and PI of maps [n_freq][3][npix] against ref."""
+    a, b = maps.double(), ref.double()
+    rms = lambda x: float(torch.sqrt((x * x).mean()))
+    pa, pb = torch.hypot(a[:, 1], a[:, 2]), torch.hypot(b[:, 1], b[:, 2])
+    return {"I_rel_rms": rms(a[:, 0] - b[:, 0]) / rms(b[:, 0]),
+            "Q_rel_rms": rms(a[:, 1] - b[:, 1]) / rms(b[:, 1]),
+            "U_rel_rms": rms(a[:, 2] - b[:, 2]) / rms(b[:, 2]),
+            "PI_rel_rms": rms(pa - pb) / rms(pb)}
+
+
+def judge(surrogate: sm.Field, plain: sm.Field, probe: sm.SynGeom, max_I_rel_rms: float = 0.05,
+          max_PI_rel_rms: float = 0.10) -> Judged:
+    """Marches the probe geometry (e.g. the target sky at a lower N_side) with
+    both fields; the plain evaluator's maps are the reference.  Returns the
+    surrogate's field if its relative rms errors of I and PI are within the
+    bounds, otherwise the plain field."""
+    m = sm.forward(probe, surrogate)
+    r = sm.forward(probe, plain)
+    err = map_error(m, r)
+    ok = err["I_rel_rms"] <= max_I_rel_rms and err["PI_rel_rms"] <= max_PI_rel_rms
+    err["bounds"] = {"I_rel_rms": max_I_rel_rms, "PI_rel_rms": max_PI_rel_rms}
+    return Judged(field=surrogate if ok else plain, used_surrogate=ok, error=err)

@@ -106,9 +106,12 @@ def time_candidate(run: Callable[[], None], reps: int = 5) -> float:
 
 def tune(kernel: int, kind: int, shape, run: Callable[[], None],
          candidates: Iterable[int] = CANDIDATES, reps: int = 5, use_cache: bool = True,
-         write_cache: bool = True, grid_modes: Optional[Iterable[int]] = None) -> Dict[str, object]:
+         write_cache: bool = True, grid_modes: Optional[Iterable[int]] = None,
+         prepare: Optional[Callable[[], None]] = None) -> Dict[str, object]:
     """Times `run` for every lane count (and, given grid_modes, every grid read
-    mode) and applies the fastest.
+    mode) and applies the fastest.  `prepare`, if given, runs untimed after each
+    candidate is applied (e.g. the forward whose stored state the timed
+    reverse pass reads).
 
     shape: (npix, n_steps, n_freq) of the workload, for the cache key.
     Returns {"lanes": best S, "grid_mode": best mode or None, "ms": {label: ms},
@@ -127,14 +130,20 @@ def tune(kernel: int, kind: int, shape, run: Callable[[], None],
         v = cache[key]
         S, mode = (v, None) if isinstance(v, int) else (v[0], v[1])
         apply(S, mode)
+        if prepare is not None:
+            prepare()
         return {"lanes": S, "grid_mode": mode, "ms": {}, "cached": True}
     ms = {}
     for mode in modes:
         for S in candidates:
             apply(S, mode)
+            if prepare is not None:
+                prepare()
             ms[(S, mode)] = time_candidate(run, reps)
     best = min(ms, key=ms.get)
     apply(*best)
+    if prepare is not None:
+        prepare()
     if write_cache:
         cache = load_cache()
         cache[key] = best[0] if best[1] is None else [best[0], best[1]]
@@ -157,10 +166,28 @@ def tune_forward(geom, field, maps=None, ws=None, **kw):
 
 
 def tune_adjoint(geom, field, dmaps, ws, want_theta=True, dgrid_bn=None, dgrid_c=None, **kw):
+    """Tunes the reverse pass.  With a grid gradient the pass reads the sums the
+    forward stored at the ends of its pieces, laid out for the lane count in
+    force when the forward ran: each candidate then gets its own workspace and
+    forward (untimed), and the forward is rerun into `ws` for the winner."""
     npix = 12 * geom.nside ** 2
-    return tune(sm.KERNEL_ADJOINT, field.s.kind, (npix, geom.n_steps, geom.n_freq),
-                lambda: sm.adjoint(geom, field, dmaps, ws, want_theta=want_theta,
-                                   dgrid_bn=dgrid_bn, dgrid_c=dgrid_c), **kw)
+    shape = (npix, geom.n_steps, geom.n_freq)
+    if dgrid_bn is None and dgrid_c is None:
+        return tune(sm.KERNEL_ADJOINT, field.s.kind, shape,
+                    lambda: sm.adjoint(geom, field, dmaps, ws, want_theta=want_theta), **kw)
+    state = {}
+
+    def prepare():
+        w = sm.alloc_workspace(geom, field)
+        sm.forward(geom, field, ws=w)
+        state["ws"] = w
+
+    res = tune(sm.KERNEL_ADJOINT, field.s.kind, shape,
+               lambda: sm.adjoint(geom, field, dmaps, state["ws"], want_theta=want_theta,
+                                  dgrid_bn=dgrid_bn, dgrid_c=dgrid_c), prepare=prepare, **kw)
+    if ws is not None and ws.numel() * ws.element_size() >= sm.workspace_bytes(geom, field, True):
+        sm.forward(geom, field, ws=ws)
+    return res
 
 
 def make_batch(thetas, nsides, geom, use_graph=True, kind=None):

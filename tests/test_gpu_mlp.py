@@ -91,3 +91,26 @@ def test_mlp_adjoint_is_rejected(env):
     dm = torch.zeros((1, 3, 48), dtype=torch.float32, device="cuda")
     with pytest.raises(sm.SynError):
         sm.adjoint(g, f, dm, ws)
+
+
+def test_plain_evaluator_judges_and_replaces_the_surrogate(env, orc):
+    """The surrogate stands in for a gridded field; the plain trilinear march of
+    that field judges its map error on a probe sky and replaces it when the
+    error is beyond the bounds (an untrained network: far beyond), and keeps it
+    when the bounds allow (here, loose bounds)."""
+    sm, S, torch = env
+    reg_bn, reg_c = orc.sample_model16(I.THETA0, (33, 33, 9), I.BOX_LO, I.BOX_HI)
+    plain = sm.grid(I.THETA0, torch.from_numpy(reg_bn).cuda(), torch.from_numpy(reg_c).cuda(),
+                    I.BOX_LO, I.BOX_HI)
+    model = make_model(S, torch, seed=23)
+    mf = S.mlp_field(model, S.pack(model))
+    probe = sm.geom_from(I.geometry("C4", nside=4, n_steps=128))
+    j = S.judge(mf, plain, probe)
+    print("judged (strict):", j.used_surrogate, j.error, flush=True)
+    assert not j.used_surrogate and j.field is plain
+    assert j.error["I_rel_rms"] > j.error["bounds"]["I_rel_rms"] or \
+        j.error["PI_rel_rms"] > j.error["bounds"]["PI_rel_rms"]
+    g = sm.geom_from(I.geometry("C4", nside=8, n_steps=128))
+    assert torch.equal(sm.forward(g, j.field), sm.forward(g, plain))
+    j2 = S.judge(mf, plain, probe, max_I_rel_rms=1e9, max_PI_rel_rms=1e9)
+    assert j2.used_surrogate and j2.field is mf
