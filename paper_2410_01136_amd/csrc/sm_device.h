@@ -455,42 +455,31 @@ struct Grid {
     float* stage = nullptr;  // this wavefront's staging records in LDS
   };
 
-  // Adds value `val` of channel ch (0-3 B and n_e, 4 N0) of corner k of cell
-  // (ix, iy, iz) to the box or to memory.
-  __device__ inline void add_corner(const AdjBox& B, int ix, int iy, int iz, int k, int ch,
-                                    float val, float* gbn, float* gc) const {
-    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-    const int lx = ix - B.b0[0], ly = iy - B.b0[1], lz = iz - B.b0[2];
-    // the cell's 8 corners all inside the box: unsigned compares take lx >= 0 too
-    if (B.lds != nullptr && (unsigned)lx < (unsigned)(B.d[0] - 1) &&
-        (unsigned)ly < (unsigned)(B.d[1] - 1) && (unsigned)lz < (unsigned)(B.d[2] - 1)) {
-      // the box lives in LDS: an LDS atomic rather than a flat one
-      using lds_float = __attribute__((address_space(3))) float;
-      lds_float* l = (lds_float*)(B.lds + 5 * (((lz + dz) * B.d[1] + ly + dy) * B.d[0] + lx + dx) + ch);
-      __hip_atomic_fetch_add(l, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      return;
-    }
-    const int64_t v = (int64_t)(ix + dx) + (int64_t)p.n[0] * ((int64_t)(iy + dy) +
-                                                             (int64_t)p.n[1] * (iz + dz));
-    if (ch < 4) {
-      if (gbn != nullptr) unsafeAtomicAdd(gbn + 4 * v + ch, val);
-    } else if (gc != nullptr && p.c != nullptr) {
-      unsafeAtomicAdd(gc + v, val);
-    }
-  }
-
   // Sends on the accumulators of the lanes with `leave` set (the registers are
   // left as they are).  Collective over the wavefront: the leaving lanes write
   // their records to the wavefront's LDS staging area (up to kStageRecs per
-  // round), then every lane takes one value: for B and n_e, lanes 32 h + 4 k +
-  // ch carry channel ch of corner k of record 2 j + h, so that one atomic
-  // instruction covers two records and the four channels of a node (16
+  // round) -- the 40 sums and, computed once per record, the cell's first node
+  // in the grid and in the workgroup's box (-1 when the cell is not wholly
+  // inside the box) -- then every lane takes one value: for B and n_e, lanes
+  // 32 h + 4 k + ch carry channel ch of corner k of record 2 j + h, so that one
+  // atomic instruction covers two records and the four channels of a node (16
   // contiguous bytes) and the x neighbours share a memory request; for N0,
   // lanes 8 h + k carry corner k of record 8 j + h.
   __device__ inline void flush_wave(const Acc& A, bool leave, float* gbn, float* gc) const {
     const int lane = (int)__lane_id();
     uint64_t m = __builtin_amdgcn_ballot_w64(leave);
-    while (m != 0) {
+    if (m == 0) return;
+    const AdjBox& B = A.box;
+    // node offsets of this lane's corner in the grid and in the box
+    const int kb = (lane >> 2) & 7, kc = lane & 7;
+    auto goff = [&](int k) {
+      return (int64_t)(k & 1) + (int64_t)p.n[0] * ((int64_t)((k >> 1) & 1) + (int64_t)p.n[1] * (k >> 2));
+    };
+    auto loff = [&](int k) { return (k & 1) + B.d[0] * (((k >> 1) & 1) + B.d[1] * (k >> 2)); };
+    const int64_t gob = goff(kb), goc = goff(kc);
+    const int lob = loff(kb), loc = loff(kc);
+    using lds_float = __attribute__((address_space(3))) float;
+    do {
       const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
       const int cnt = min(__popcll(m), kStageRecs);
@@ -503,34 +492,57 @@ struct Grid {
           row[j] = make_float4(A.a[e / 5][e % 5], A.a[(e + 1) / 5][(e + 1) % 5],
                                A.a[(e + 2) / 5][(e + 2) % 5], A.a[(e + 3) / 5][(e + 3) % 5]);
         }
-        row[10] = make_float4(__int_as_float(A.ix), __int_as_float(A.iy), __int_as_float(A.iz), 0.0f);
+        const int lx = A.ix - B.b0[0], ly = A.iy - B.b0[1], lz = A.iz - B.b0[2];
+        // the cell's 8 corners all inside the box: unsigned compares take lx >= 0 too
+        const bool in_box = B.lds != nullptr && (unsigned)lx < (unsigned)(B.d[0] - 1) &&
+                            (unsigned)ly < (unsigned)(B.d[1] - 1) && (unsigned)lz < (unsigned)(B.d[2] - 1);
+        const int lb = in_box ? (lz * B.d[1] + ly) * B.d[0] + lx : -1;
+        row[10] = make_float4(__int_as_float((int)(A.base & 0xffffffff)), __int_as_float((int)(A.base >> 32)),
+                              __int_as_float(lb), 0.0f);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (gbn != nullptr) {
-        const int k = (lane >> 2) & 7, ch = lane & 3;
+        const int ch = lane & 3;
         for (int r0 = 0; r0 < cnt; r0 += 2) {
           const int r = r0 + (lane >> 5);
           if (r < cnt) {
             const float* rec = A.stage + r * kStageFloats;
-            const float val = rec[5 * k + ch];
-            if (val != 0.0f)
-              add_corner(A.box, __float_as_int(rec[40]), __float_as_int(rec[41]),
-                         __float_as_int(rec[42]), k, ch, val, gbn, gc);
+            const float val = rec[5 * kb + ch];
+            const float4 meta = reinterpret_cast<const float4*>(rec)[10];
+            const int lb = __float_as_int(meta.z);
+            if (val != 0.0f) {
+              if (lb >= 0) {
+                lds_float* l = (lds_float*)(B.lds + 5 * (lb + lob) + ch);
+                __hip_atomic_fetch_add(l, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              } else {
+                const int64_t base = (int64_t)(uint32_t)__float_as_int(meta.x) |
+                                     ((int64_t)__float_as_int(meta.y) << 32);
+                unsafeAtomicAdd(gbn + 4 * (base + gob) + ch, val);
+              }
+            }
           }
         }
       }
       if (gc != nullptr && p.c != nullptr) {
-        const int k = lane & 7;
         for (int r0 = 0; r0 < cnt; r0 += 8) {
           const int r = r0 + (lane >> 3);
           if (r < cnt) {
             const float* rec = A.stage + r * kStageFloats;
-            const float val = rec[5 * k + 4];
-            if (val != 0.0f)
-              add_corner(A.box, __float_as_int(rec[40]), __float_as_int(rec[41]),
-                         __float_as_int(rec[42]), k, 4, val, gbn, gc);
+            const float val = rec[5 * kc + 4];
+            const float4 meta = reinterpret_cast<const float4*>(rec)[10];
+            const int lb = __float_as_int(meta.z);
+            if (val != 0.0f) {
+              if (lb >= 0) {
+                lds_float* l = (lds_float*)(B.lds + 5 * (lb + loc) + 4);
+                __hip_atomic_fetch_add(l, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              } else {
+                const int64_t base = (int64_t)(uint32_t)__float_as_int(meta.x) |
+                                     ((int64_t)__float_as_int(meta.y) << 32);
+                unsafeAtomicAdd(gc + base + goc, val);
+              }
+            }
           }
         }
       }
@@ -539,7 +551,7 @@ struct Grid {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (mine) leave = false;
       m = __builtin_amdgcn_ballot_w64(leave);
-    }
+    } while (m != 0);
   }
 
   // Adds a workgroup's LDS box to memory (after a barrier); nodes of the box
