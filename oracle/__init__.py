@@ -101,6 +101,8 @@ def _load():
     lib.or_sample_model16.argtypes = [dp, ctypes.POINTER(ctypes.c_int32), dp, dp,
                                       ctypes.c_void_p, ctypes.c_void_p]
     lib.or_num_threads.restype = ctypes.c_int
+    lib.or_sample_field.argtypes = [fp, ctypes.POINTER(ctypes.c_int32), dp, dp, ctypes.c_void_p,
+                                    ctypes.c_void_p]
     lib.or_set_num_threads.argtypes = [ctypes.c_int]
     lib.or_midpoints.argtypes = [gp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
     lib.or_forward_tabulated.argtypes = [gp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64),
@@ -222,6 +224,21 @@ def sample_model16(theta, n_xyz, lo, hi):
     hi_a = np.ascontiguousarray(hi, dtype=np.float64)
     if lib.or_sample_model16(_dptr(th), n, _dptr(lo_a), _dptr(hi_a), bn.ctypes.data,
                              c.ctypes.data) != 0:
+        raise ValueError("bad grid shape")
+    return bn, c
+
+
+def sample_field(field: Field, n_xyz, lo, hi):
+    """Any field kind on a node-centred grid: (bn [nz][ny][nx][4], c [nz][ny][nx])."""
+    lib = _load()
+    nx, ny, nz = (int(v) for v in n_xyz)
+    bn = np.zeros((nz, ny, nx, 4), dtype=np.float32)
+    c = np.zeros((nz, ny, nx), dtype=np.float32)
+    n = (ctypes.c_int32 * 3)(nx, ny, nz)
+    lo_a = np.ascontiguousarray(lo, dtype=np.float64)
+    hi_a = np.ascontiguousarray(hi, dtype=np.float64)
+    if lib.or_sample_field(ctypes.byref(field.s), n, _dptr(lo_a), _dptr(hi_a), bn.ctypes.data,
+                           c.ctypes.data) != 0:
         raise ValueError("bad grid shape")
     return bn, c
 

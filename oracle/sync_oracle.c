@@ -947,6 +947,32 @@ int or_sample_model16(const double* theta, const int32_t n[3], const double lo[3
   return 0;
 }
 
+/* Any field kind sampled on the nodes of a grid (node i of an axis at
+   lo + i (hi - lo) / (n - 1)), as the grid field generators of Sec. 2.3 are
+   built from a field: out_bn [nz][ny][nx][4] = (Bx, By, Bz, n_e), out_c
+   [nz][ny][nx] = N0 (either may be NULL). */
+int or_sample_field(const or_field* f, const int32_t n[3], const double lo[3], const double hi[3],
+                    float* out_bn, float* out_c) {
+  if (n[0] < 2 || n[1] < 2 || n[2] < 2) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t iz = 0; iz < n[2]; ++iz)
+    for (int64_t iy = 0; iy < n[1]; ++iy)
+      for (int64_t ix = 0; ix < n[0]; ++ix) {
+        const double r[3] = {lo[0] + (hi[0] - lo[0]) * (double)ix / (double)(n[0] - 1),
+                             lo[1] + (hi[1] - lo[1]) * (double)iy / (double)(n[1] - 1),
+                             lo[2] + (hi[2] - lo[2]) * (double)iz / (double)(n[2] - 1)};
+        double B[3], ne, n0;
+        or_fields(f, r, B, &ne, &n0);
+        const int64_t v = ix + n[0] * (iy + n[1] * iz);
+        if (out_bn) {
+          for (int k = 0; k < 3; ++k) out_bn[4 * v + k] = (float)B[k];
+          out_bn[4 * v + 3] = (float)ne;
+        }
+        if (out_c) out_c[v] = (float)n0;
+      }
+  return 0;
+}
+
 /* Thread count of the OpenMP loops over pixels (for timing on a given number
    of host cores). */
 void or_set_num_threads(int n) {
