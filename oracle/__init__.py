@@ -27,6 +27,7 @@ _LIB_OVERRIDE = os.environ.get("SYNC_ORACLE_LIB")
 
 MODEL16, GRID, SPHERE, WMAP = 0, 1, 2, 4
 NPARAM = 16
+SPEC_POWER, SPEC_BROKEN = 0, 1
 MAX_FREQ = 16
 
 
@@ -60,7 +61,9 @@ class _Field(ctypes.Structure):
                 ("grid_n", ctypes.c_int32 * 3), ("grid_lo", ctypes.c_double * 3),
                 ("grid_hi", ctypes.c_double * 3),
                 ("grid_bn", ctypes.c_void_p), ("grid_c", ctypes.c_void_p),
-                ("te_k", ctypes.c_double), ("grid_alpha", ctypes.c_void_p)]
+                ("te_k", ctypes.c_double), ("grid_alpha", ctypes.c_void_p),
+                ("spectrum", ctypes.c_int32), ("alpha_hi", ctypes.c_double),
+                ("gamma_break", ctypes.c_double)]
 
 
 _lib = None
@@ -104,6 +107,14 @@ def _load():
     lib.or_sample_field.argtypes = [fp, ctypes.POINTER(ctypes.c_int32), dp, dp, ctypes.c_void_p,
                                     ctypes.c_void_p]
     lib.or_set_num_threads.argtypes = [ctypes.c_int]
+    for name in ("or_gamma_upper",):
+        getattr(lib, name).argtypes = [ctypes.c_double] * 2
+        getattr(lib, name).restype = ctypes.c_double
+    for name in ("or_synch_F", "or_synch_G", "or_moment_F", "or_moment_G"):
+        getattr(lib, name).argtypes = [ctypes.c_double]
+        getattr(lib, name).restype = ctypes.c_double
+    lib.or_moment_tails.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+    lib.or_j_broken.argtypes = [ctypes.c_double] * 6 + [dp]
     lib.or_midpoints.argtypes = [gp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
     lib.or_forward_tabulated.argtypes = [gp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int64, dp, dp]
@@ -135,10 +146,13 @@ class Field:
     """Field description; keeps the grid arrays alive while in use."""
 
     def __init__(self, kind, theta, grid_bn=None, grid_c=None, grid_lo=None, grid_hi=None,
-                 te_k=0.0, grid_alpha=None):
+                 te_k=0.0, grid_alpha=None, broken=None):
         self.s = _Field()
         self.s.kind = int(kind)
         self.s.te_k = float(te_k)  # > 0: free-free emission and absorption at T_e [K]
+        if broken is not None:  # (alpha_hi, gamma_break): broken power law, theta[12] below
+            self.s.spectrum = SPEC_BROKEN
+            self.s.alpha_hi, self.s.gamma_break = float(broken[0]), float(broken[1])
         th = np.asarray(theta, dtype=np.float64)
         if th.shape != (NPARAM,):
             raise ValueError("theta must have 16 entries")
@@ -276,6 +290,44 @@ def j_I(alpha, nu, bt_gauss, n0):
 
 def j_P(alpha, nu, bt_gauss, n0):
     return _load().or_j_P(alpha, nu, bt_gauss, n0)
+
+
+def gamma_upper(a, y):
+    """Upper incomplete gamma function Gamma(a, y) (not regularised)."""
+    return _load().or_gamma_upper(a, y)
+
+
+def synch_F(x):
+    """F(x) = x int_x^inf K_5/3(z) dz."""
+    return _load().or_synch_F(x)
+
+
+def synch_G(x):
+    """G(x) = x K_2/3(x)."""
+    return _load().or_synch_G(x)
+
+
+def moment_F(mu):
+    return _load().or_moment_F(mu)
+
+
+def moment_G(mu):
+    return _load().or_moment_G(mu)
+
+
+def moment_tails(alpha, xb):
+    """Shares (tF, tG) of the x-moments of order (alpha - 3) / 2 of F and G
+    above xb."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _load().or_moment_tails(alpha, xb, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def j_broken(a1, a2, gamma_break, nu, bt_gauss, n0):
+    """(j_I, j_P, dj_I/dbt, dj_P/dbt) of the broken power-law spectrum."""
+    out = np.zeros(4)
+    _load().or_j_broken(a1, a2, gamma_break, nu, bt_gauss, n0, _dptr(out))
+    return out
 
 
 def digamma(x):

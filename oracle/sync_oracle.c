@@ -15,7 +15,9 @@
  *     construction),
  *   - the fields B, n_e, N0 at each midpoint (analytic model or trilinear
  *     interpolation over a regular grid, Sec. 2.3),
- *   - the emissivities j_I and j_P (Eqs. ji and jp, Sec. 2.1-2.2),
+ *   - the emissivities j_I and j_P (Eqs. ji and jp, Sec. 2.1-2.2), and, as a
+     reading of the fuller CR spectrum left to future work in Sec. 2.1, those
+     of a broken power law (incomplete synchrotron moments, see below),
  *   - the rotation measure as a running integral (Eq. rm) and the angle
  *     chi = RM lambda^2 + chi_0 with chi_0 from Eq. chi (Sec. 2.2),
  *   - the Riemann sums of Eq. int, then the Rayleigh-Jeans brightness
@@ -90,7 +92,12 @@ typedef struct {
   const float* grid_c;  /* [nz][ny][nx] N0 [cm^-3], or NULL -> analytic N0  */
   double te_k;          /* electron temperature [K]; > 0 adds free-free      */
   const float* grid_alpha; /* [nz][ny][nx] CR spectral index, or NULL -> theta[12] */
+  int32_t spectrum;     /* OR_SPEC_POWER (index theta[12]) or OR_SPEC_BROKEN       */
+  double alpha_hi;      /* broken: index above the break                           */
+  double gamma_break;   /* broken: Lorentz factor of the break                     */
 } or_field;
+
+enum { OR_SPEC_POWER = 0, OR_SPEC_BROKEN = 1 };
 
 /* ========================================================================== */
 /* HEALPix RING pixel centres (Gorski et al. 2005)                           */
@@ -483,6 +490,176 @@ double or_j_P(double alpha, double nu, double bt, double n0) {
          tgamma(alpha / 4.0 + 7.0 / 12.0);
 }
 
+/* ========================================================================== */
+/* Broken power-law CR spectrum (Sec. 2.1 leaves spectra beyond one power    */
+/* law to future work; this is a reading)                                    */
+/* ========================================================================== */
+/*
+ * N(gamma) = C gamma^-a1 below the Lorentz factor gamma_b and
+ * C gamma_b^(a2 - a1) gamma^-a2 above it (continuous at gamma_b; C = N0 as in
+ * Eq. ji).  The emissivity is the single-electron spectrum integrated over the
+ * electrons, j = (1 / 4 pi) int N(gamma) P(nu, gamma) dgamma, with
+ * P = sqrt(3) q^3 B / (m c^2) F(nu / nu_c), nu_c = 3 gamma^2 q B / (4 pi m c)
+ * (and G in place of F for the polarised part).  In x = nu / nu_c, gamma^2 =
+ * x0 / x with x0 = 4 pi nu m c / (3 q B): electrons below the break emit at
+ * x > xb = x0 / gamma_b^2.  For one power law of index a the integral is the
+ * complete x-moment of F of order mu = (a - 3) / 2, which gives Eq. ji (and
+ * Eq. jp for G).  For the broken law each segment is an incomplete moment:
+ *
+ *   j_I = j_I(a1) T_F(a1, xb) + gamma_b^(a2 - a1) j_I(a2) (1 - T_F(a2, xb)),
+ *   j_P = the same with j_P and T_G,
+ *
+ * T(a, xb) = int_xb^inf x^mu F(x) dx / int_0^inf x^mu F(x) dx, the share of the
+ * moment above xb.  With F(x) = x int_0^inf e^{-x cosh s} cosh(5s/3)/cosh s ds
+ * and G(x) = x K_2/3(x) = x int_0^inf e^{-x cosh s} cosh(2s/3) ds, the x-integral
+ * over [xb, inf) of x^(mu+1) e^{-x cosh s} is Gamma(mu + 2, xb cosh s) /
+ * cosh^(mu+2) s, so
+ *
+ *   int_xb^inf x^mu F = int_0^inf cosh(5s/3) cosh^-(mu+3) s Gamma(mu+2, xb cosh s) ds
+ *   int_xb^inf x^mu G = int_0^inf cosh(2s/3) cosh^-(mu+2) s Gamma(mu+2, xb cosh s) ds,
+ *
+ * taken by the trapezoidal rule in s (the integrands are even and analytic in
+ * the strip |Im s| < pi/2, so the rule converges geometrically), while the
+ * complete moments are the closed forms behind Eqs. ji and jp.
+ */
+
+/* Upper incomplete gamma function Gamma(a, y), a > 0, y >= 0: Gamma(a) less
+   the power series of the lower function for y < a + 1, else Legendre's
+   continued fraction in its even form, evaluated by the modified Lentz
+   method. */
+double or_gamma_upper(double a, double y) {
+  if (y <= 0.0) return tgamma(a);
+  if (y < a + 1.0) {
+    double term = 1.0 / a, sum = term;
+    for (int k = 1; k < 2000; ++k) {
+      term *= y / (a + k);
+      sum += term;
+      if (term < 1e-17 * sum) break;
+    }
+    return tgamma(a) - sum * exp(a * log(y) - y);
+  }
+  const double tiny = 1e-300;
+  double b = y + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i < 2000; ++i) {
+    const double an = -(double)i * ((double)i - a);
+    b += 2.0;
+    d = an * d + b;
+    if (fabs(d) < tiny) d = tiny;
+    c = b + an / c;
+    if (fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (fabs(del - 1.0) < 1e-16) break;
+  }
+  return exp(a * log(y) - y) * h;
+}
+
+/* Trapezoidal step in s and the cut: terms with x (cosh s - 1) > 60 are below
+   e^-60 of the first and are dropped. */
+static const double OR_S_STEP = 0.125;
+static const double OR_S_CUT = 60.0;
+
+/* Synchrotron functions F(x) = x int_x^inf K_5/3 and G(x) = x K_2/3(x). */
+double or_synch_F(double x) {
+  if (!(x > 0.0)) return 0.0;
+  double sum = 0.0;
+  for (int k = 0;; ++k) {
+    const double s = k * OR_S_STEP, ch = cosh(s);
+    if (x * (ch - 1.0) > OR_S_CUT) break;
+    const double t = exp(-x * ch) * cosh(5.0 * s / 3.0) / ch;
+    sum += (k == 0 ? 0.5 : 1.0) * t;
+  }
+  return x * OR_S_STEP * sum;
+}
+
+double or_synch_G(double x) {
+  if (!(x > 0.0)) return 0.0;
+  double sum = 0.0;
+  for (int k = 0;; ++k) {
+    const double s = k * OR_S_STEP, ch = cosh(s);
+    if (x * (ch - 1.0) > OR_S_CUT) break;
+    sum += (k == 0 ? 0.5 : 1.0) * exp(-x * ch) * cosh(2.0 * s / 3.0);
+  }
+  return x * OR_S_STEP * sum;
+}
+
+/* Complete moments int_0^inf x^mu F(x) dx and int_0^inf x^mu G(x) dx, the
+   Gamma-function factors of Eqs. ji and jp at mu = (alpha - 3) / 2. */
+double or_moment_F(double mu) {
+  return pow(2.0, mu + 1.0) / (mu + 2.0) * tgamma(mu / 2.0 + 7.0 / 3.0) * tgamma(mu / 2.0 + 2.0 / 3.0);
+}
+double or_moment_G(double mu) {
+  return pow(2.0, mu) * tgamma(mu / 2.0 + 4.0 / 3.0) * tgamma(mu / 2.0 + 2.0 / 3.0);
+}
+
+/* Shares of the x-moments of order mu = (alpha - 3) / 2 of F and G that lie
+   above xb: tF, tG in [0, 1] (1 at xb = 0, 0 as xb -> inf). */
+void or_moment_tails(double alpha, double xb, double* tF, double* tG) {
+  if (!(xb > 0.0)) {
+    *tF = *tG = 1.0;
+    return;
+  }
+  if (isinf(xb)) {
+    *tF = *tG = 0.0;
+    return;
+  }
+  const double mu = 0.5 * (alpha - 3.0), a = mu + 2.0;
+  double sF = 0.0, sG = 0.0;
+  for (int k = 0;; ++k) {
+    const double s = k * OR_S_STEP, ch = cosh(s);
+    if (xb * (ch - 1.0) > OR_S_CUT) break;
+    const double w = (k == 0 ? 0.5 : 1.0) * or_gamma_upper(a, xb * ch) * pow(ch, -a);
+    sF += w * cosh(5.0 * s / 3.0) / ch;
+    sG += w * cosh(2.0 * s / 3.0);
+  }
+  *tF = OR_S_STEP * sF / or_moment_F(mu);
+  *tG = OR_S_STEP * sG / or_moment_G(mu);
+}
+
+/* Emissivities of the broken power law (a1 below the break Lorentz factor gb,
+   a2 above it) at B_trans bt [gauss], N0 [cm^-3], nu [Hz]:
+   out = {j_I, j_P, d j_I / d bt, d j_P / d bt}. */
+void or_j_broken(double a1, double a2, double gb, double nu, double bt, double n0, double out[4]) {
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  if (bt <= 0.0) return;
+  const double xb = 4.0 * OR_PI * nu * OR_ME * OR_C / (3.0 * OR_QE * bt * gb * gb);
+  const double norm2 = pow(gb, a2 - a1);
+  const double jI1 = or_j_I(a1, nu, bt, n0), jP1 = or_j_P(a1, nu, bt, n0);
+  const double jI2 = norm2 * or_j_I(a2, nu, bt, n0), jP2 = norm2 * or_j_P(a2, nu, bt, n0);
+  double tF1, tG1, tF2, tG2;
+  or_moment_tails(a1, xb, &tF1, &tG1);
+  or_moment_tails(a2, xb, &tF2, &tG2);
+  out[0] = jI1 * tF1 + jI2 * (1.0 - tF2);
+  out[1] = jP1 * tG1 + jP2 * (1.0 - tG2);
+  /* each j(a) grows as bt^((a+1)/2); xb falls as 1/bt, and the tail share
+     above xb changes by -xb^mu F(xb) / moment per unit xb */
+  const double mu1 = 0.5 * (a1 - 3.0), mu2 = 0.5 * (a2 - 3.0);
+  const double FF = or_synch_F(xb), GG = or_synch_G(xb);
+  const double dtF1 = pow(xb, mu1 + 1.0) * FF / (or_moment_F(mu1) * bt);
+  const double dtG1 = pow(xb, mu1 + 1.0) * GG / (or_moment_G(mu1) * bt);
+  const double dtF2 = pow(xb, mu2 + 1.0) * FF / (or_moment_F(mu2) * bt);
+  const double dtG2 = pow(xb, mu2 + 1.0) * GG / (or_moment_G(mu2) * bt);
+  out[2] = jI1 * ((a1 + 1.0) / (2.0 * bt) * tF1 + dtF1) +
+           jI2 * ((a2 + 1.0) / (2.0 * bt) * (1.0 - tF2) - dtF2);
+  out[3] = jP1 * ((a1 + 1.0) / (2.0 * bt) * tG1 + dtG1) +
+           jP2 * ((a2 + 1.0) / (2.0 * bt) * (1.0 - tG2) - dtG2);
+}
+
+/* Emissivities of the spectrum of f (NULL: one power law) at index alpha
+   (theta[12] or the local gridded index): out as for or_j_broken. */
+static void or_emissivity(const or_field* f, double alpha, double nu, double bt, double n0,
+                          double out[4]) {
+  if (f != NULL && f->spectrum == OR_SPEC_BROKEN) {
+    or_j_broken(alpha, f->alpha_hi, f->gamma_break, nu, bt, n0, out);
+    return;
+  }
+  out[0] = or_j_I(alpha, nu, bt, n0);
+  out[1] = or_j_P(alpha, nu, bt, n0);
+  out[2] = bt > 0.0 ? out[0] * (alpha + 1.0) / (2.0 * bt) : 0.0;
+  out[3] = bt > 0.0 ? out[1] * (alpha + 1.0) / (2.0 * bt) : 0.0;
+}
+
 /* Digamma by upward recurrence to x >= 12 and the asymptotic series
    psi(x) = ln x - 1/(2x) - sum_k B_2k / (2k x^2k) (Abramowitz & Stegun 6.3.18). */
 double or_digamma(double x) {
@@ -630,8 +807,9 @@ static double or_march_source(const or_geom* g, const or_source* src, double alp
       const double nu = g->freq_hz[k];
       const double lam = OR_C / nu;
       const double att = te > 0.0 ? exp(-or_kff(nu, te) * EM) : 1.0;
-      const double jI = or_j_I(a_n, nu, q.Bt, q.n0);
-      const double jP = or_j_P(a_n, nu, q.Bt, q.n0);
+      double j[4];
+      or_emissivity(src->f, a_n, nu, q.Bt, q.n0, j);
+      const double jI = j[0], jP = j[1];
       const double chi = RM * lam * lam + q.chi0;
       I[k] += att * jI * ray.dcm;
       Q[k] += att * jP * cos(2.0 * chi) * ray.dcm;
@@ -663,6 +841,14 @@ static int or_check(const or_geom* g, const or_field* f) {
     return -1;
   if (!(f->te_k >= 0.0) || isinf(f->te_k)) return -1;
   if (f->grid_alpha != NULL && f->kind != OR_GRID) return -1;
+  if (f->spectrum != OR_SPEC_POWER && f->spectrum != OR_SPEC_BROKEN) return -1;
+  if (f->spectrum == OR_SPEC_BROKEN) {
+    /* the moments exist for indices above 1/3; one index per side of the break */
+    if (f->grid_alpha != NULL || !(f->theta[12] > 1.0 / 3.0) || !(f->alpha_hi > 1.0 / 3.0) ||
+        !(f->gamma_break > 0.0) || isinf(f->gamma_break) || isinf(f->alpha_hi) ||
+        isinf(f->theta[12]))
+      return -1;
+  }
   return 0;
 }
 
@@ -778,8 +964,9 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
       const double rj = or_rj(nu);
       const double kff = te > 0.0 ? or_kff(nu, te) : 0.0;
       const double att = te > 0.0 ? exp(-kff * EM[n]) : 1.0;
-      const double jI = or_j_I(alpha, nu, q[n].Bt, q[n].n0);
-      const double jP = or_j_P(alpha, nu, q[n].Bt, q[n].n0);
+      double j[4];
+      or_emissivity(f, alpha, nu, q[n].Bt, q[n].n0, j);
+      const double jI = j[0], jP = j[1];
       const double chi = RM[n] * lam * lam + q[n].chi0;
       const double gI = dm[3 * k + 0] * rj * ray.dcm;
       const double gQ = dm[3 * k + 1] * rj * ray.dcm;
@@ -815,19 +1002,24 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
     for (int k = 0; k < g->n_freq; ++k) {
       const double nu = g->freq_hz[k];
       if (q[n].Bt <= 0.0) continue;
-      const double jI = or_j_I(alpha, nu, q[n].Bt, q[n].n0);
-      const double jP = or_j_P(alpha, nu, q[n].Bt, q[n].n0);
+      double j[4];
+      or_emissivity(f, alpha, nu, q[n].Bt, q[n].n0, j);
+      const double jI = j[0], jP = j[1];
       const double gI = jIb[n * OR_MAX_FREQ + k], gP = jPb[n * OR_MAX_FREQ + k];
-      /* j ~ Bt^{(alpha+1)/2} n0 */
-      Btb += (gI * jI + gP * jP) * (alpha + 1.0) / (2.0 * q[n].Bt);
+      /* j is linear in n0; its B_trans slope comes with the emissivity */
+      Btb += gI * j[2] + gP * j[3];
       if (q[n].n0 != 0.0) {
         n0b += (gI * jI + gP * jP) / q[n].n0;
       } else {
-        n0b += gI * or_j_I(alpha, nu, q[n].Bt, 1.0) + gP * or_j_P(alpha, nu, q[n].Bt, 1.0);
+        double j1[4];
+        or_emissivity(f, alpha, nu, q[n].Bt, 1.0, j1);
+        n0b += gI * j1[0] + gP * j1[1];
       }
-      double dI, dP;
-      or_dlnj_dalpha(alpha, nu, q[n].Bt, &dI, &dP);
-      ab += gI * jI * dI + gP * jP * dP;
+      if (f->spectrum == OR_SPEC_POWER) {
+        double dI, dP;
+        or_dlnj_dalpha(alpha, nu, q[n].Bt, &dI, &dP);
+        ab += gI * jI * dI + gP * jP * dP;
+      }
     }
     double numb = 0.0, denb = 0.0;
     if (q[n].Bt > 0.0) {
@@ -835,7 +1027,9 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
       numb = Btb * q[n].num / q[n].Bt + chi0b[n] * q[n].den / bt2;
       denb = Btb * q[n].den / q[n].Bt - chi0b[n] * q[n].num / bt2;
     }
-    if (!alpha_gridded) tb[12] += ab; /* a gridded index is an input without a gradient */
+    /* a gridded index is an input without a gradient; so are the indices and
+       break of the broken spectrum (ab stays 0) */
+    if (!alpha_gridded) tb[12] += ab;
     /* num = 1e-6 B.e_b, den = -1e-6 B.e_l, blos = -1e-6 B.n  (B in uG) */
     double Bb[3];
     for (int k = 0; k < 3; ++k)
