@@ -60,6 +60,11 @@ enum {
 
 enum { SYN_NPARAM = 16, SYN_MAX_FREQ = 16, SYN_MAX_NSIDE = 8192 };
 
+enum {
+  SYN_SPEC_POWER_LAW = 0, /* one power law of index theta[12] (Eqs. ji, jp) */
+  SYN_SPEC_BROKEN = 1     /* broken power law, see syn_spectrum_table        */
+};
+
 /* Geometry and step schedule (Sec. 2.3).  The sightline of every pixel runs
    from r_obs to the first box face it meets, capped at r_max, and is cut into
    n_steps equal segments sampled at their midpoints. */
@@ -113,6 +118,11 @@ typedef struct syn_field {
   double te_k;                  /* thermal electron temperature [K]; 0 = off  */
   const float* grid_alpha;      /* (device) GRID: CR spectral index per node,
                                    float [nz][ny][nx], or NULL for theta[12]   */
+  int32_t spectrum;             /* SYN_SPEC_*; 0 (power law) when zeroed       */
+  double alpha_hi;              /* SYN_SPEC_BROKEN: index above the break      */
+  double gamma_break;           /* SYN_SPEC_BROKEN: Lorentz factor of the break */
+  const void* spectrum_table;   /* (device) SYN_SPEC_BROKEN: from
+                                   syn_spectrum_table(theta[12], alpha_hi)     */
 } syn_field;
 /* Gridded spectral index (grid_alpha != NULL, GRID fields only; a first step
    toward the full CR spectrum the paper leaves to future work, Sec. 2.1):
@@ -133,6 +143,42 @@ typedef struct syn_field {
    half of its own, as for the rotation measure).  Not available for the MLP
    surrogate (SYN_EUNSUPPORTED) or in batch plans; te_k must be finite and
    >= 0 (SYN_EINVAL).  Gradients flow through n_e; te_k itself gets none. */
+
+/* Broken power-law CR spectrum (spectrum = SYN_SPEC_BROKEN; the paper models
+   the CR electrons with one power law and names fuller spectra as future work,
+   Sec. 2.1): N(gamma) = N0 gamma^-a1 below the Lorentz factor gamma_break and
+   N0 gamma_break^(a2 - a1) gamma^-a2 above it (continuous at the break), with
+   a1 = theta[12] and a2 = alpha_hi.  The emissivities are the single-electron
+   synchrotron spectrum integrated over this N(gamma), which for one index is
+   Eqs. ji and jp; for the broken law each side of the break contributes the
+   part of its x-moment (x = nu / nu_c) on its side of
+   xb = 4 pi nu m c / (3 q B_perp gamma_break^2):
+     j_I = j_I(a1) (1 - S_F(a1, xb)) + gamma_break^(a2 - a1) j_I(a2) S_F(a2, xb),
+   and the same for j_P with the shares S_G of G(x) = x K_2/3(x), S being the
+   share of the moment below xb.  The kernels interpolate S from a table that
+   syn_spectrum_table builds for (a1, a2) once; gamma_break and the frequencies
+   enter per call.  Ranges: 1/3 < a1, a2 <= 6, 1 <= gamma_break <= 1e12, and
+   the break within reach of the FP32 arithmetic at every frequency of the
+   geometry (for B_perp from 2^-20 to 2^20 uG the powers of xb the kernels form
+   stay finite; else SYN_EUNSUPPORTED naming the frequency).  Not with
+   grid_alpha (SYN_EINVAL), the MLP surrogate or batch plans
+   (SYN_EUNSUPPORTED).  Gradients flow through B, n_e and N0; theta[12],
+   alpha_hi and gamma_break receive none (dtheta[12] = 0). */
+
+/* Bytes of a broken power-law table (device memory the caller allocates). */
+size_t syn_spectrum_table_bytes(void);
+
+/* Builds the table of moment shares for indices alpha_lo (the field's
+   theta[12]) and alpha_hi on the host and copies it into table (device,
+   table_bytes >= syn_spectrum_table_bytes(), 16-byte aligned) on stream,
+   which it then synchronises.  The library records the pair of indices with
+   the table's address; syn_forward and syn_adjoint accept a broken-spectrum
+   field only with a table recorded for its theta[12] and alpha_hi (else
+   SYN_EINVAL).  The caller keeps the table alive and unmodified while fields
+   use it.  SYN_EINVAL for indices out of range, a small or misaligned table;
+   SYN_EHIP if the copy fails. */
+syn_status syn_spectrum_table(double alpha_lo, double alpha_hi, void* table, size_t table_bytes,
+                              hipStream_t stream);
 
 /* Bytes of workspace syn_forward needs; with_adjoint != 0 adds what the
    matching syn_adjoint reads (the Faraday sum of every sightline, 8 B per

@@ -22,6 +22,7 @@ LIB_PATH = os.environ.get("SYNMARCH_LIB") or os.path.join(_HERE, "libsynmarch.so
 SYN_OK, SYN_EINVAL, SYN_EUNSUPPORTED, SYN_ENOMEM, SYN_EHIP, SYN_EWORKSPACE = 0, -1, -2, -3, -4, -5
 FIELD_MODEL16, FIELD_GRID, FIELD_SPHERE, FIELD_MLP, FIELD_WMAP = 0, 1, 2, 3, 4
 KERNEL_FORWARD, KERNEL_ADJOINT, KERNEL_BATCH = 0, 1, 2
+SPEC_POWER_LAW, SPEC_BROKEN = 0, 1
 NPARAM, MAX_FREQ = 16, 16
 
 if not os.path.exists(LIB_PATH):
@@ -42,7 +43,9 @@ class SynField(ctypes.Structure):
                 ("grid_n", ctypes.c_int32 * 3), ("grid_lo_kpc", ctypes.c_double * 3),
                 ("grid_hi_kpc", ctypes.c_double * 3), ("grid_bn", ctypes.c_void_p),
                 ("grid_c", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
-                ("te_k", ctypes.c_double), ("grid_alpha", ctypes.c_void_p)]
+                ("te_k", ctypes.c_double), ("grid_alpha", ctypes.c_void_p),
+                ("spectrum", ctypes.c_int32), ("alpha_hi", ctypes.c_double),
+                ("gamma_break", ctypes.c_double), ("spectrum_table", ctypes.c_void_p)]
 
 
 class SynBatchDesc(ctypes.Structure):
@@ -68,6 +71,9 @@ syn_last_error = _sig("syn_last_error", ctypes.c_char_p, [])
 syn_workspace_bytes = _sig("syn_workspace_bytes", _sz, [_G, _F, _i32])
 syn_forward = _sig("syn_forward", _i32, [_G, _F, _vp, _vp, _sz, _vp])
 syn_adjoint = _sig("syn_adjoint", _i32, [_G, _F, _vp, _vp, _sz, _vp, _vp, _vp, _vp])
+syn_spectrum_table_bytes = _sig("syn_spectrum_table_bytes", _sz, [])
+syn_spectrum_table = _sig("syn_spectrum_table", _i32,
+                          [ctypes.c_double, ctypes.c_double, _vp, _sz, _vp])
 syn_chi2_workspace_bytes = _sig("syn_chi2_workspace_bytes", _sz, [_i64, _i32])
 syn_chi2 = _sig("syn_chi2", _i32, [_i64, _i32, _vp, _vp, _dp, _vp, _vp, _vp, _sz, _vp])
 syn_chi2_cotangent = _sig("syn_chi2_cotangent", _i32, [_i64, _i32, _vp, _vp, _dp, _vp, _vp, _vp])
@@ -150,13 +156,35 @@ def geom_from(g) -> SynGeom:
     return make_geom(g.nside, g.n_steps, g.freqs_hz, g.r_obs, g.r_max, g.box_lo, g.box_hi)
 
 
+_spectrum_tables = {}
+
+
+def spectrum_table(alpha_lo: float, alpha_hi: float, device=None, stream=None) -> torch.Tensor:
+    """The device table of a broken power law with indices (alpha_lo, alpha_hi),
+    built once per device and pair by syn_spectrum_table and kept here."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    key = (dev.index, float(alpha_lo), float(alpha_hi))
+    t = _spectrum_tables.get(key)
+    if t is None:
+        nb = int(syn_spectrum_table_bytes())
+        t = torch.empty((nb + 3) // 4, dtype=torch.float32, device=dev)
+        check(syn_spectrum_table(float(alpha_lo), float(alpha_hi), t.data_ptr(), nb, _stream(stream)),
+              "syn_spectrum_table")
+        _spectrum_tables[key] = t
+    return t
+
+
 class Field:
-    """A syn_field plus the tensors it points to (kept alive here)."""
+    """A syn_field plus the tensors it points to (kept alive here).
+
+    broken = (alpha_hi, gamma_break) selects the broken power-law CR spectrum
+    (theta[12] the index below the break); its table comes from
+    spectrum_table()."""
 
     def __init__(self, kind: int, theta, grid_bn: Optional[torch.Tensor] = None,
                  grid_c: Optional[torch.Tensor] = None, lo=None, hi=None,
                  mlp: Optional[torch.Tensor] = None, te_k: float = 0.0,
-                 grid_alpha: Optional[torch.Tensor] = None):
+                 grid_alpha: Optional[torch.Tensor] = None, broken=None):
         self.s = SynField()
         self.s.kind = int(kind)
         self.s.te_k = float(te_k)  # > 0: free-free emission and absorption at T_e [K]
@@ -165,6 +193,12 @@ class Field:
         if th.size != NPARAM:
             raise ValueError("theta must have 16 entries")
         self.s.theta[:] = th.tolist()
+        self.broken, self.spec_table = broken, None
+        if broken is not None:
+            self.s.spectrum = SPEC_BROKEN
+            self.s.alpha_hi, self.s.gamma_break = float(broken[0]), float(broken[1])
+            self.spec_table = spectrum_table(float(th[12]), float(broken[0]))
+            self.s.spectrum_table = self.spec_table.data_ptr()
         self.grid_bn, self.grid_c, self.mlp = grid_bn, grid_c, mlp
         if grid_bn is not None:
             _dev_f32(grid_bn, "grid_bn")
@@ -196,13 +230,20 @@ class Field:
     def with_theta(self, theta) -> "Field":
         return Field(self.s.kind, theta, self.grid_bn, self.grid_c,
                      self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, self.s.te_k,
-                     self.grid_alpha)
+                     self.grid_alpha, self.broken)
 
     def with_te(self, te_k: float) -> "Field":
         """The same field with free-free emission and absorption at T_e = te_k [K]."""
         return Field(self.s.kind, self.theta, self.grid_bn, self.grid_c,
                      self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, te_k,
-                     self.grid_alpha)
+                     self.grid_alpha, self.broken)
+
+    def with_broken(self, broken) -> "Field":
+        """The same field with a broken power-law spectrum (alpha_hi, gamma_break),
+        or None for one power law."""
+        return Field(self.s.kind, self.theta, self.grid_bn, self.grid_c,
+                     self.s.grid_lo_kpc[:], self.s.grid_hi_kpc[:], self.mlp, self.s.te_k,
+                     self.grid_alpha, broken)
 
 
 def model16(theta) -> Field:

@@ -2,6 +2,7 @@
 // shapes and dispatch.  Every check runs on the host before anything is
 // launched; no exception crosses the ABI.
 #include <math.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -170,6 +171,30 @@ sm::M16Args m16_args(const double* th) {
   return m;
 }
 
+// ---- broken power-law tables --------------------------------------------------
+// syn_spectrum_table records the indices it built each table for, per device
+// address; a broken-spectrum field is accepted only with a table recorded for
+// its own indices.
+struct SpecRecord {
+  double a1, a2;
+};
+std::mutex g_spec_mu;
+std::unordered_map<uintptr_t, SpecRecord> g_spec_tables;
+
+void spec_record(const void* t, double a1, double a2) {
+  std::lock_guard<std::mutex> lk(g_spec_mu);
+  if (g_spec_tables.size() >= (1u << 16)) g_spec_tables.clear();
+  g_spec_tables[(uintptr_t)t] = SpecRecord{a1, a2};
+}
+
+bool spec_matches(const void* t, double a1, double a2) {
+  std::lock_guard<std::mutex> lk(g_spec_mu);
+  auto it = g_spec_tables.find((uintptr_t)t);
+  return it != g_spec_tables.end() && it->second.a1 == a1 && it->second.a2 == a2;
+}
+
+bool bp_alpha_ok(double a) { return a > sm::kBpAlphaMin && a <= sm::kBpAlphaMax; }
+
 syn_status check_m16_theta(const double* th) {
   for (int k : {4, 5, 7, 8, 10, 11, 14})
     if (!(th[k] > 0.0)) return fail(SYN_EINVAL, "model16 scale lengths (theta 4,5,7,8,10,11,14) must be > 0");
@@ -192,6 +217,22 @@ syn_status check_field(const syn_field* f, sm::FieldPack* fp, bool for_adjoint) 
   if (f->grid_alpha != nullptr) {
     if (f->kind != SYN_FIELD_GRID) return fail(SYN_EINVAL, "grid_alpha needs a GRID field");
     if (((uintptr_t)f->grid_alpha & 3) != 0) return fail(SYN_EINVAL, "grid_alpha must be 4-byte aligned");
+  }
+  if (f->spectrum != SYN_SPEC_POWER_LAW && f->spectrum != SYN_SPEC_BROKEN)
+    return fail(SYN_EINVAL, "spectrum must be SYN_SPEC_POWER_LAW or SYN_SPEC_BROKEN");
+  if (f->spectrum == SYN_SPEC_BROKEN) {
+    if (f->grid_alpha != nullptr)
+      return fail(SYN_EINVAL, "a broken power law takes its indices from theta[12] and alpha_hi, not grid_alpha");
+    if (f->kind == SYN_FIELD_MLP)
+      return fail(SYN_EUNSUPPORTED, "the broken power law is not available for the MLP surrogate");
+    if (!bp_alpha_ok(f->theta[12]) || !bp_alpha_ok(f->alpha_hi))
+      return fail(SYN_EINVAL, "broken power law: theta[12] and alpha_hi must lie in (1/3, 6]");
+    if (!(f->gamma_break >= 1.0 && f->gamma_break <= 1e12))
+      return fail(SYN_EINVAL, "broken power law: gamma_break must lie in [1, 1e12]");
+    if (f->spectrum_table == nullptr || ((uintptr_t)f->spectrum_table & 15) != 0 ||
+        !spec_matches(f->spectrum_table, f->theta[12], f->alpha_hi))
+      return fail(SYN_EINVAL, "spectrum_table was not filled by syn_spectrum_table for theta[12] and alpha_hi");
+    fp->spec = sm::kSpecBroken;
   }
   switch (f->kind) {
     case SYN_FIELD_MODEL16: {
@@ -350,6 +391,53 @@ sm::EmitArgs emit_args(double alpha) {
   return e;
 }
 
+// Broken power law: the per-frequency constants of FreqArgs and the table and
+// exponents of EmitArgs.  In ln: Eq. ji's prefactor at index a without the
+// factors common to both indices, with B_perp in uG (the kernels' units).
+double bp_ln_prefactor(double a, double base) {
+  return 0.5 * (1.0 - a) * log(base) + 0.5 * (a + 1.0) * log(2.0) - log(a + 1.0) +
+         lgamma(a / 4.0 - 1.0 / 12.0) + lgamma(a / 4.0 + 19.0 / 12.0) + 0.5 * (a + 1.0) * log(1e-6);
+}
+
+syn_status bp_args(const syn_geom* g, const syn_field* f, sm::FreqArgs* fa, sm::EmitArgs* ea) {
+  const double a1 = f->theta[12], a2 = f->alpha_hi, gb = f->gamma_break;
+  const double p1 = sm::bp_power(a1), p2 = sm::bp_power(a2), q = 0.25 * (a2 - a1);
+  ea->bp_tab = reinterpret_cast<const float4*>(f->spectrum_table);
+  ea->bp_h1 = (float)(-0.5 * p1);
+  ea->bp_h2 = (float)(-0.5 * p2);
+  ea->bp_q = (float)q;
+  const double pol = log((a2 + 1.0) / (a2 + 7.0 / 3.0)) - log((a1 + 1.0) / (a1 + 7.0 / 3.0));
+  for (int k = 0; k < g->n_freq; ++k) {
+    const double base = 4.0 * kPi * g->freq_hz[k] * kMe * kC / (3.0 * kQe);
+    const double L = log2(base / (gb * gb * 1e-6));  // log2 of xb B_perp [uG]
+    const double lr = ((a2 - a1) * log(gb) + bp_ln_prefactor(a2, base) - bp_ln_prefactor(a1, base)) / log(2.0);
+    const double lrp = lr + pol / log(2.0);
+    // log2 of every power the kernels form, at both ends of the B_perp range
+    // they allow (B_perp^2 = 2^+-40 uG^2), must stay inside FP32's normal range
+    double worst = fmax(fmax(fabs(p1 * L), fabs(p2 * L)), fmax(fabs(lr), fabs(lrp)));
+    for (double lg : {-40.0, 40.0}) {
+      worst = fmax(worst, fabs(p1 * (L - 0.5 * lg)));
+      worst = fmax(worst, fabs(p2 * (L - 0.5 * lg)));
+      worst = fmax(worst, fabs(lr + q * lg));
+      worst = fmax(worst, fabs(lrp + q * lg));
+    }
+    if (!(worst < 120.0)) {
+      char msg[160];
+      snprintf(msg, sizeof(msg),
+               "broken power law: the break (gamma_break %.3g) is out of the FP32 range of the "
+               "kernels at %.4g Hz",
+               gb, g->freq_hz[k]);
+      return fail(SYN_EUNSUPPORTED, msg);
+    }
+    fa->bp_l[k] = (float)L;
+    fa->bp_k1[k] = (float)exp2(p1 * L);
+    fa->bp_k2[k] = (float)exp2(p2 * L);
+    fa->bp_ri[k] = (float)exp2(lr);
+    fa->bp_rp[k] = (float)exp2(lrp);
+  }
+  return SYN_OK;
+}
+
 size_t ws_phi_bytes(int64_t npix) { return (size_t)((npix * 8 + 255) / 256 * 256); }
 
 // Workspace: the Faraday sum of every sightline, with free-free also its
@@ -409,6 +497,12 @@ uint64_t ws_tag(const syn_geom* g, const syn_field* f) {
   x.add(f->mlp);
   x.add(f->te_k);
   x.add(f->grid_alpha);
+  x.add(f->spectrum);
+  if (f->spectrum == SYN_SPEC_BROKEN) {
+    x.add(f->alpha_hi);
+    x.add(f->gamma_break);
+    x.add(f->spectrum_table);
+  }
   return x.h;
 }
 
@@ -448,6 +542,25 @@ extern "C" {
 int32_t syn_version(void) { return 100; }
 
 const char* syn_last_error(void) { return g_err.c_str(); }
+
+size_t syn_spectrum_table_bytes(void) { return sm::kBpTableBytes; }
+
+syn_status syn_spectrum_table(double alpha_lo, double alpha_hi, void* table, size_t table_bytes,
+                              hipStream_t stream) {
+  if (!bp_alpha_ok(alpha_lo) || !bp_alpha_ok(alpha_hi))
+    return fail(SYN_EINVAL, "broken power law: indices must lie in (1/3, 6]");
+  if (table == nullptr || ((uintptr_t)table & 15) != 0 || table_bytes < sm::kBpTableBytes)
+    return fail(SYN_EINVAL, "table must be a 16-byte aligned device buffer of syn_spectrum_table_bytes()");
+  std::vector<float> host((size_t)sm::kBpNodes * 8);
+  std::string err;
+  if (!sm::bp_build_table(alpha_lo, alpha_hi, host.data(), &err)) return fail(SYN_EINVAL, err);
+  // the copy is synchronised before the host buffer goes
+  hipError_t e = hipMemcpyAsync(table, host.data(), sm::kBpTableBytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "spectrum table copy");
+  spec_record(table, alpha_lo, alpha_hi);
+  return SYN_OK;
+}
 
 size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t with_adjoint) {
   sm::GeomArgs ga;
@@ -522,9 +635,14 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
   }
   sm::FreqArgs fa;
   freq_args(geom, field->theta[12], field->te_k, &fa);
+  sm::EmitArgs ea = emit_args(field->theta[12]);
+  if (fp.spec == sm::kSpecBroken) {
+    s = bp_args(geom, field, &fa, &ea);
+    if (s != SYN_OK) return s;
+  }
   hipError_t e;
   if (field->kind == SYN_FIELD_MLP) {
-    e = sm::launch_forward_mlp(ga, fa, emit_args(field->theta[12]), fp.mlp, maps, phi_end, stream);
+    e = sm::launch_forward_mlp(ga, fa, ea, fp.mlp, maps, phi_end, stream);
   } else {
     int tuned_mode = 0;
     const int S = lanes_for_shape(SYN_KERNEL_FORWARD, field->kind, ga.npix, ga.n_steps,
@@ -540,8 +658,7 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
                      : shared                                    ? sm::kGridShared
                                                                  : sm::kGridBuffer;
     }
-    e = sm::launch_forward(ga, fa, emit_args(field->theta[12]), fp, S, maps, phi_end, em_end,
-                           stream);
+    e = sm::launch_forward(ga, fa, ea, fp, S, maps, phi_end, em_end, stream);
   }
   if (e != hipSuccess) {
     if (ws != nullptr) ws_forget(ws);
@@ -576,6 +693,11 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   if (dtheta == nullptr && dgrid_bn == nullptr && dgrid_c == nullptr) return SYN_OK;
   sm::FreqArgs fa;
   freq_args(geom, field->theta[12], field->te_k, &fa);
+  sm::EmitArgs ea = emit_args(field->theta[12]);
+  if (fp.spec == sm::kSpecBroken) {
+    s = bp_args(geom, field, &fa, &ea);
+    if (s != SYN_OK) return s;
+  }
   int tuned_mode = 0;
   int S = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps, geom->n_freq,
                           &tuned_mode);
@@ -592,8 +714,8 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
     fp.grid.piece_len = (ga.n_steps + pieces - 1) / pieces;
     fp.grid.snap_nq = snap_quantities(geom->n_freq, fp.ff);
   }
-  hipError_t e = sm::launch_adjoint(ga, fa, emit_args(field->theta[12]), fp, S, dmaps, phi_end,
-                                    em_end, partials, dtheta, dgrid_bn, dgrid_c, stream);
+  hipError_t e = sm::launch_adjoint(ga, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta,
+                                    dgrid_bn, dgrid_c, stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return SYN_OK;
 }

@@ -24,10 +24,15 @@ hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs&
                                         gbn, gc, st)
                  : launch_adjoint_va(g, fa, ea, fp, S, dmaps, phi_end, nullptr, partials, dtheta,
                                      gbn, gc, st);
+  if (fp.spec == kSpecBroken)
+    return fp.ff ? launch_adjoint_bp_ff(g, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta,
+                                        gbn, gc, st)
+                 : launch_adjoint_bp(g, fa, ea, fp, S, dmaps, phi_end, nullptr, partials, dtheta,
+                                     gbn, gc, st);
   if (fp.ff)
     return launch_adjoint_ff(g, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta, gbn, gc,
                              st);
-  return launch_adjoint_t<false, false>(g, fa, ea, fp, S, dmaps, phi_end, nullptr, partials,
+  return launch_adjoint_t<false, kSpecPower>(g, fa, ea, fp, S, dmaps, phi_end, nullptr, partials,
                                         dtheta, gbn, gc, st);
 }
 

@@ -7,7 +7,7 @@ hipError_t launch_adjoint_ff(const GeomArgs& g, const FreqArgs& fa, const EmitAr
                              const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
                              const double* em_end, double* partials, double* dtheta, float* gbn,
                              float* gc, hipStream_t st) {
-  return launch_adjoint_t<true, false>(g, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta, gbn,
+  return launch_adjoint_t<true, kSpecPower>(g, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta, gbn,
                                 gc, st);
 }
 

@@ -1,6 +1,6 @@
-// Reverse-march kernels and their launch-shape dispatch, templated on
-// free-free (FF).  Included by march_adj.hip (FF = false) and march_adj_ff.hip
-// (FF = true) so that the two sets of kernels compile in parallel.
+// Reverse-march kernels and their launch-shape dispatch, templated on free-free
+// (FF) and the spectral model (SP).  Included by one march_adj*.hip file per
+// (FF, SP) pair so that the sets of kernels compile in parallel.
 #pragma once
 
 #include <algorithm>
@@ -79,7 +79,7 @@ __device__ inline AdjBox workgroup_box(const GeomArgs& g, const F& fld, int64_t 
   return B;
 }
 
-template <class F, int S, int MF, bool THETA, bool GRID, bool FF, bool VA>
+template <class F, int S, int MF, bool THETA, bool GRID, bool FF, int SP>
 __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitArgs ea, F fld,
                                                  const float* __restrict__ dmaps,
                                                  const double* __restrict__ phi_end,
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitAr
     box = workgroup_box(g, fld, q, lds_dyn, box_cap);
     stage = lds_dyn + 5 * box_cap + (threadIdx.x >> 6) * (kStageRecs * kStageFloats);
   }
-  adj_lane<F, S, MF, THETA, GRID, FF, VA>(g, fa, ea, fld, q, sub, valid, dmaps,
+  adj_lane<F, S, MF, THETA, GRID, FF, SP>(g, fa, ea, fld, q, sub, valid, dmaps,
                                           MapAddr{g.npix, 0}, phi_end, tb, gbn, gc, &box, stage,
                                           em_end);
   if constexpr (GRID) {
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const T* __restrict__ p
   }
 }
 
-template <bool FF, bool VA, class F, int S, int MF, bool TH, bool GR>
+template <bool FF, int SP, class F, int S, int MF, bool TH, bool GR>
 static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
                          const float* dm, const double* pe, const double* ee, double* part,
                          double* dth, float* gbn, float* gc, hipStream_t st) {
@@ -152,7 +152,7 @@ static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
     static PerDevice regs_cache;
     int by_regs = 0;
     e0 = regs_cache.get(&by_regs, [](int* out) {
-      const void* fn = reinterpret_cast<const void*>(&k_adjoint<F, S, MF, TH, GR, FF, VA>);
+      const void* fn = reinterpret_cast<const void*>(&k_adjoint<F, S, MF, TH, GR, FF, SP>);
       hipError_t e = hipFuncSetAttribute(
           fn, hipFuncAttributeMaxDynamicSharedMemorySize,
           (int)((size_t)kAdjBoxNodesMax * 5 * sizeof(float) + kStageBytesPerBlock));
@@ -170,7 +170,7 @@ static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
     cap = adj_box_cap(per_cu);
     lds = (size_t)cap * 5 * sizeof(float) + kStageBytesPerBlock;
   }
-  k_adjoint<F, S, MF, TH, GR, FF, VA><<<dim3((unsigned)nb), dim3(256), lds, st>>>(
+  k_adjoint<F, S, MF, TH, GR, FF, SP><<<dim3((unsigned)nb), dim3(256), lds, st>>>(
       g, fa, ea, f, dm, pe, ee, part, gbn, gc, cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -181,40 +181,40 @@ static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
   return e;
 }
 
-template <bool FF, bool VA, class F, int S, int MF>
+template <bool FF, int SP, class F, int S, int MF>
 static hipError_t adj_flags(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
                             const float* dm, const double* pe, const double* ee, double* part,
                             double* dth, float* gbn, float* gc, hipStream_t st) {
   const bool th = dth != nullptr, gr = (gbn != nullptr || gc != nullptr);
   if constexpr (std::is_same_v<F, Grid>) {
     if (th && gr)
-      return adj_go<FF, VA, F, S, MF, true, true>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
-    if (gr) return adj_go<FF, VA, F, S, MF, false, true>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+      return adj_go<FF, SP, F, S, MF, true, true>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+    if (gr) return adj_go<FF, SP, F, S, MF, false, true>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
   } else {
     if (gr) return hipErrorInvalidValue;  // only gridded fields have grid gradients
   }
-  if (th) return adj_go<FF, VA, F, S, MF, true, false>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+  if (th) return adj_go<FF, SP, F, S, MF, true, false>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
   return hipSuccess;
 }
 
-template <bool FF, bool VA, class F, int S>
+template <bool FF, int SP, class F, int S>
 static hipError_t adj_mf(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
                          const float* dm, const double* pe, const double* ee, double* part,
                          double* dth, float* gbn, float* gc, hipStream_t st) {
-  if (fa.n_freq <= 1) return adj_flags<FF, VA, F, S, 1>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
-  if (fa.n_freq <= 4) return adj_flags<FF, VA, F, S, 4>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
-  return adj_flags<FF, VA, F, S, 16>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+  if (fa.n_freq <= 1) return adj_flags<FF, SP, F, S, 1>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+  if (fa.n_freq <= 4) return adj_flags<FF, SP, F, S, 4>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+  return adj_flags<FF, SP, F, S, 16>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
 }
 
-template <bool FF, bool VA, class F>
+template <bool FF, int SP, class F>
 static hipError_t adj_s(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
                         int S, const float* dm, const double* pe, const double* ee, double* part,
                         double* dth, float* gbn, float* gc, hipStream_t st) {
   switch (S) {
-    case 1: return adj_mf<FF, VA, F, 1>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
-    case 4: return adj_mf<FF, VA, F, 4>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
-    case 16: return adj_mf<FF, VA, F, 16>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
-    case 64: return adj_mf<FF, VA, F, 64>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+    case 1: return adj_mf<FF, SP, F, 1>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+    case 4: return adj_mf<FF, SP, F, 4>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+    case 16: return adj_mf<FF, SP, F, 16>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+    case 64: return adj_mf<FF, SP, F, 64>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -233,22 +233,23 @@ struct WmapNoGrid : Wmap {
   };
 };
 
-// VA: gridded spectral index (grid fields only).
-template <bool FF, bool VA>
+// SP: spectral model (kSpecPower, kSpecGridAlpha: gridded index, grid fields
+// only; kSpecBroken: broken power law).
+template <bool FF, int SP>
 static hipError_t launch_adjoint_t(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                                    const FieldPack& fp, int S, const float* dmaps,
                                    const double* phi_end, const double* em_end, double* partials,
                                    double* dtheta, float* gbn, float* gc, hipStream_t st) {
   if (fp.kind == kGrid)
-    return adj_s<FF, VA>(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, dmaps, phi_end, em_end,
+    return adj_s<FF, SP>(g, fa, ea, Grid{fp.grid, Model16{fp.m16}}, S, dmaps, phi_end, em_end,
                          partials, dtheta, gbn, gc, st);
-  if constexpr (!VA) {
+  if constexpr (SP != kSpecGridAlpha) {
     switch (fp.kind) {
       case kModel16:
-        return adj_s<FF, VA>(g, fa, ea, Model16NoGrid{Model16{fp.m16}}, S, dmaps, phi_end, em_end,
+        return adj_s<FF, SP>(g, fa, ea, Model16NoGrid{Model16{fp.m16}}, S, dmaps, phi_end, em_end,
                              partials, dtheta, nullptr, nullptr, st);
       case kWmap:
-        return adj_s<FF, VA>(g, fa, ea, WmapNoGrid{Wmap{fp.wmap}}, S, dmaps, phi_end, em_end,
+        return adj_s<FF, SP>(g, fa, ea, WmapNoGrid{Wmap{fp.wmap}}, S, dmaps, phi_end, em_end,
                              partials, dtheta, nullptr, nullptr, st);
       default: break;
     }

@@ -7,7 +7,7 @@ hipError_t launch_adjoint_va(const GeomArgs& g, const FreqArgs& fa, const EmitAr
                              const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
                              const double* em_end, double* partials, double* dtheta, float* gbn,
                              float* gc, hipStream_t st) {
-  return launch_adjoint_t<false, true>(g, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta,
+  return launch_adjoint_t<false, kSpecGridAlpha>(g, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta,
                                        gbn, gc, st);
 }
 

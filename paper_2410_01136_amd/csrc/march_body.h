@@ -56,10 +56,16 @@ constexpr bool exact_freqs(int MF) { return MF == 1 || MF == 3; }
 // its exponent in B_perp and its frequency prefactors (one ratio per
 // frequency to the prefactors of theta[12]), so the I sum is per frequency.
 //
+// Spectral model SP: one power law (kSpecPower), a gridded index
+// (kSpecGridAlpha, the VA path above) or a broken power law (kSpecBroken): the
+// emission of the index below the break scaled per frequency by the
+// multipliers of bp_mult (interpolated moment shares), so the I sum is per
+// frequency as well.
+//
 // PC (gridded fields only): also store the piece snapshots of fld.p (the
 // running sums at the piece ends of the grid-gradient reverse pass), so that
 // pass needs no pre-pass over its pieces.
-template <class F, int S, int MF, bool FF = false, bool VA = false, bool PC = false, class FA>
+template <class F, int S, int MF, bool FF = false, int SP = kSpecPower, bool PC = false, class FA>
 __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, float* __restrict__ maps,
                                 MapAddr ma, double* __restrict__ phi_end,
@@ -67,7 +73,8 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   const Ray ray = make_ray(g, q);
   const auto rctx = fld.ray_ctx(g, ray);
   constexpr bool zero_beyond = zero_beyond_path<F>();
-  constexpr bool PF = FF || VA;  // per-frequency I sums
+  constexpr bool VA = SP == kSpecGridAlpha, BP = SP == kSpecBroken;
+  constexpr bool PF = FF || VA || BP;  // per-frequency I sums
   constexpr int MFF = FF ? MF : 1;
   constexpr int MPF = PF ? MF : 1;
   double carry = 0.0;  // Faraday sum (n_e B_par, uG cm^-3) of all earlier chunks
@@ -135,6 +142,8 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     Emit e = VA ? emission(v.n0, bl, bb, false, vs.eI) : emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
     if (!zero_beyond && !act) e.u = e.zr = e.zi = 0.0f;
     if constexpr (!PF) accI += (double)e.u;
+    BpStep bs{};
+    if constexpr (BP) bs = bp_step(bl, bb, ea);
     const double psid = psi * ray.dkpc;
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
@@ -147,6 +156,12 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
           if constexpr (VA) {
             mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
             mP = mI * vs.prat;
+          }
+          if constexpr (BP) {
+            const BpMult bm = bp_mult<false>(bs, fa.bp_l[f], fa.bp_k1[f], fa.bp_k2[f], fa.bp_ri[f],
+                                             fa.bp_rp[f], ea.bp_tab);
+            mI = bm.mI;
+            mP = bm.mP;
           }
           if constexpr (FF) {
             const float att = exp2f(-(float)fa.kffl2[f] * emd);
@@ -295,7 +310,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 // Faraday sum of the earlier pieces, a rotation by its phase turns the latter
 // into the piece's phase-cotangent total, and a suffix scan gives each piece
 // those of the pieces after it.
-template <class F, int S, int MF, bool THETA, bool GRID, bool FF = false, bool VA = false,
+template <class F, int S, int MF, bool THETA, bool GRID, bool FF = false, int SP = kSpecPower,
           class FA>
 __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, const float* __restrict__ dmaps,
@@ -306,9 +321,11 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   const Ray ray = make_ray(g, q);
   const double dk = ray.dkpc;
   constexpr int MFF = FF ? MF : 1;
-  constexpr bool PF = FF || VA;  // per-frequency multipliers of the emission
-  // (with a gridded alpha, theta[12] does not enter the maps: no alpha gradient)
-  constexpr bool ALPHA_GRAD = THETA && !VA;
+  constexpr bool VA = SP == kSpecGridAlpha, BP = SP == kSpecBroken;
+  constexpr bool PF = FF || VA || BP;  // per-frequency multipliers of the emission
+  // (with a gridded alpha, theta[12] does not enter the maps: no alpha
+  // gradient; the indices and break of a broken power law have none either)
+  constexpr bool ALPHA_GRAD = THETA && !VA && !BP;
 
   // per-sightline cotangent constants
   double GI = 0.0;
@@ -413,6 +430,8 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
         }
         const Emit e =
             VA ? emission(v.n0, bl, bb, false, vs.eI) : emission(v.n0, bl, bb, ea.alpha3 != 0, ea.eI);
+        BpStep bs{};
+        if constexpr (BP) bs = bp_step(bl, bb, ea);
 #pragma unroll
         for (int f = 0; f < MF; ++f) {
           if (f < fa.n_freq) {
@@ -424,6 +443,12 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
               if constexpr (VA) {
                 mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
                 mP = mI * vs.prat;
+              }
+              if constexpr (BP) {
+                const BpMult bm = bp_mult<false>(bs, fa.bp_l[f], fa.bp_k1[f], fa.bp_k2[f],
+                                                 fa.bp_ri[f], fa.bp_rp[f], ea.bp_tab);
+                mI = bm.mI;
+                mP = bm.mP;
               }
               if constexpr (FF) {
                 const float att = exp2f(-(float)fa.kffl2[f] * emd);
@@ -567,6 +592,9 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     const bool a3 = VA ? false : ea.alpha3 != 0;
     Emit e = emission(v.n0, bl, bb, a3, eI);
     if (!act) e.u = e.zr = e.zi = 0.0f;
+    BpStep bs{};
+    float xlg = 0.0f;  // BP: d L / d log2 B_perp^2 through the multipliers
+    if constexpr (BP) bs = bp_step(bl, bb, ea);
     // H = sum_f mP_f h_f e^{2 pi i t_f};  K = sum_f mP_f k_f e^{2 pi i t_f}
     // (mI_f, mP_f the per-frequency multipliers of I and Q + iU: the free-free
     // attenuation and the local-alpha prefactor ratio; 1 without either)
@@ -584,16 +612,26 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
         if constexpr (PF) {
           const float hrf = hrs[f] * cs - his[f] * sn, hif = hrs[f] * sn + his[f] * cs;
           const float krf = krs[f] * cs - kis[f] * sn, kif = krs[f] * sn + kis[f] * cs;
-          float mI = 1.0f, mP = 1.0f, att = 1.0f;
+          float mI = 1.0f, mP = 1.0f, att = 1.0f, dmI = 0.0f, dmP = 0.0f;
           if constexpr (VA) {
             mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
             mP = mI * vs.prat;
+          }
+          if constexpr (BP) {
+            const BpMult bm = bp_mult<true>(bs, fa.bp_l[f], fa.bp_k1[f], fa.bp_k2[f], fa.bp_ri[f],
+                                            fa.bp_rp[f], ea.bp_tab);
+            mI = bm.mI;
+            mP = bm.mP;
+            dmI = bm.dI;
+            dmP = bm.dP;
           }
           if constexpr (FF) {
             att = exp2f(-(float)fa.kffl2[f] * emd);
             mI *= att;
             mP *= att;
           }
+          if constexpr (BP)
+            xlg += att * (gis[f] * e.u * dmI + dmP * (hrf * e.zr - hif * e.zi));
           Hr += mP * hrf;
           Hi += mP * hif;
           Kr += mP * krf;
@@ -650,7 +688,16 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
       wbar = (double)Cw + ebar;
     }
     // local reverse of the emission and projections
-    const EmitBar eb = emission_vjp(v.n0, bl, bb, a3, eI, GIe, Hr, -Hi);
+    EmitBar eb = emission_vjp(v.n0, bl, bb, a3, eI, GIe, Hr, -Hi);
+    if constexpr (BP) {
+      // the multipliers' dependence on B_perp: d log2 B_perp^2 / d B_perp^2 = log2(e) / B_perp^2
+      const float bt2 = bl * bl + bb * bb;
+      if (bt2 > 0.0f) {
+        const float xb = xlg * 1.4426950408889634f * frcp(bt2);
+        eb.bl += 2.0f * bl * xb;
+        eb.bb += 2.0f * bb * xb;
+      }
+    }
     float neb = (float)(cbar * bpar);
     if constexpr (FF) neb += (float)(2.0 * wbar) * v.ne;
     const float bparb = (float)(cbar * (double)v.ne);

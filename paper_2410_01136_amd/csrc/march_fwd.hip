@@ -17,8 +17,11 @@ hipError_t launch_forward(const GeomArgs& g, const FreqArgs& fa, const EmitArgs&
   if (fp.grid.alpha != nullptr)
     return fp.ff ? launch_forward_va_ff(g, fa, ea, fp, S, maps, phi_end, em_end, st)
                  : launch_forward_va(g, fa, ea, fp, S, maps, phi_end, nullptr, st);
+  if (fp.spec == kSpecBroken)
+    return fp.ff ? launch_forward_bp_ff(g, fa, ea, fp, S, maps, phi_end, em_end, st)
+                 : launch_forward_bp(g, fa, ea, fp, S, maps, phi_end, nullptr, st);
   if (fp.ff) return launch_forward_ff(g, fa, ea, fp, S, maps, phi_end, em_end, st);
-  return launch_forward_t<false, false>(g, fa, ea, fp, S, maps, phi_end, nullptr, st);
+  return launch_forward_t<false, kSpecPower>(g, fa, ea, fp, S, maps, phi_end, nullptr, st);
 }
 
 }  // namespace sm

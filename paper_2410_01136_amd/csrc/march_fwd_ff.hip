@@ -6,7 +6,7 @@ namespace sm {
 hipError_t launch_forward_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                              const FieldPack& fp, int S, float* maps, double* phi_end,
                              double* em_end, hipStream_t st) {
-  return launch_forward_t<true, false>(g, fa, ea, fp, S, maps, phi_end, em_end, st);
+  return launch_forward_t<true, kSpecPower>(g, fa, ea, fp, S, maps, phi_end, em_end, st);
 }
 
 }  // namespace sm

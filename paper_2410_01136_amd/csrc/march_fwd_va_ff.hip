@@ -6,7 +6,7 @@ namespace sm {
 hipError_t launch_forward_va_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                                 const FieldPack& fp, int S, float* maps, double* phi_end,
                                 double* em_end, hipStream_t st) {
-  return launch_forward_t<true, true>(g, fa, ea, fp, S, maps, phi_end, em_end, st);
+  return launch_forward_t<true, kSpecGridAlpha>(g, fa, ea, fp, S, maps, phi_end, em_end, st);
 }
 
 }  // namespace sm

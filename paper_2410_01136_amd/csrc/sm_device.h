@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "sm_params.h"
+#include "spectrum.h"
 
 namespace sm {
 
@@ -1141,6 +1142,98 @@ __device__ inline float va_ratio(const VaStep& v, double k1l2, double a, const E
   const double x = k1l2 * (a - ea.va_alpha_ref) + v.dg * 1.4426950408889634;
   const double n = floor(x);
   return ldexpf(fexp2((float)(x - n)), (int)n);
+}
+
+// ---------------------------------------------------------------------------
+// Broken power-law spectrum: the emission of the lower law (index alpha_lo =
+// theta[12], the prefactors of FreqArgs) scaled per frequency by
+//   mI = 1 - S_F(lo) + ri b S_F(hi),   mP = 1 - S_G(lo) + rp b S_G(hi),
+// with S the lower shares of spectrum.h at t = log2 xb = bp_l - lg / 2
+// (lg = log2 B_perp^2), b = (B_perp^2)^((alpha_hi - alpha_lo)/4), and
+// S = min(1, 2^(p t) g(t)) from the table's cubic Hermite interpolant g.  The
+// powers of B_perp^2 are shared by the frequencies; 2^(p t) = k c with the
+// per-frequency k = 2^(p bp_l) and the per-step c = (B_perp^2)^(-p/2).
+// ---------------------------------------------------------------------------
+struct BpStep {
+  float lg;          // log2 B_perp^2 [uG^2], held to [-40, 40]
+  float c1, c2;      // (B_perp^2)^(-p_lo/2), (B_perp^2)^(-p_hi/2)
+  float b;           // (B_perp^2)^((alpha_hi - alpha_lo)/4)
+  float h1, h2, q;   // the exponents of c1, c2, b (per unit lg)
+};
+
+__device__ inline BpStep bp_step(float bl, float bb, const EmitArgs& ea) {
+  const float bt2 = bl * bl + bb * bb;
+  BpStep s;
+  // beyond 2^+-20 uG the emission is negligible or out of any model; the clamp
+  // keeps the powers (and their products with the host constants, which the
+  // host checks over this range) finite
+  s.lg = fminf(fmaxf(bt2 > 0.0f ? flog2(bt2) : -40.0f, -40.0f), 40.0f);
+  s.h1 = ea.bp_h1;
+  s.h2 = ea.bp_h2;
+  s.q = ea.bp_q;
+  s.c1 = fexp2(s.h1 * s.lg);
+  s.c2 = fexp2(s.h2 * s.lg);
+  s.b = fexp2(s.q * s.lg);
+  return s;
+}
+
+struct BpMult {
+  float mI, mP;  // multipliers of the lower law's I and Q + iU
+  float dI, dP;  // their derivatives in lg (DERIV only)
+};
+
+template <bool DERIV>
+__device__ inline BpMult bp_mult(const BpStep& s, float l, float k1, float k2, float ri, float rp,
+                                 const float4* __restrict__ tab) {
+  // node and offset from 16 t: the product is exact and so is its split, so the
+  // offset keeps the full precision of t
+  const float m = (l - 0.5f * s.lg) * (float)kBpPerOctave;
+  const float fl = floorf(m);
+  float r = m - fl;
+  int k = (int)fl - (int)(kBpT0 * kBpPerOctave);
+  bool inside = true;
+  if (k < 0) {  // below the table: g held at its first node (the leading power law)
+    k = 0;
+    r = 0.0f;
+    inside = false;
+  } else if (k >= kBpNodes - 1) {  // above it every share is 1 (through the min below)
+    k = kBpNodes - 2;
+    r = 1.0f;
+    inside = false;
+  }
+  const float4 g0 = tab[2 * k], d0 = tab[2 * k + 1], g1 = tab[2 * k + 2], d1 = tab[2 * k + 3];
+  const float r2 = r * r, r3 = r2 * r;
+  const float h00 = 2.0f * r3 - 3.0f * r2 + 1.0f, h10 = r3 - 2.0f * r2 + r;
+  const float h01 = 3.0f * r2 - 2.0f * r3, h11 = r3 - r2;
+  const float gF1 = h00 * g0.x + h10 * d0.x + h01 * g1.x + h11 * d1.x;
+  const float gG1 = h00 * g0.y + h10 * d0.y + h01 * g1.y + h11 * d1.y;
+  const float gF2 = h00 * g0.z + h10 * d0.z + h01 * g1.z + h11 * d1.z;
+  const float gG2 = h00 * g0.w + h10 * d0.w + h01 * g1.w + h11 * d1.w;
+  const float a1 = k1 * s.c1, a2 = k2 * s.c2;  // 2^(p t)
+  const float sF1 = fminf(1.0f, a1 * gF1), sG1 = fminf(1.0f, a1 * gG1);
+  const float sF2 = fminf(1.0f, a2 * gF2), sG2 = fminf(1.0f, a2 * gG2);
+  BpMult o;
+  o.mI = (1.0f - sF1) + ri * (s.b * sF2);
+  o.mP = (1.0f - sG1) + rp * (s.b * sG2);
+  o.dI = o.dP = 0.0f;
+  if constexpr (DERIV) {
+    // d g / d t of the interpolant (zero where g is held), and dt / d lg = -1/2
+    const float e0 = 6.0f * (r2 - r), e1 = 3.0f * r2 - 4.0f * r + 1.0f, e2 = 3.0f * r2 - 2.0f * r;
+    const float sc = inside ? -0.5f * (float)kBpPerOctave : 0.0f;
+    const float tF1 = sc * (e0 * (g0.x - g1.x) + e1 * d0.x + e2 * d1.x);
+    const float tG1 = sc * (e0 * (g0.y - g1.y) + e1 * d0.y + e2 * d1.y);
+    const float tF2 = sc * (e0 * (g0.z - g1.z) + e1 * d0.z + e2 * d1.z);
+    const float tG2 = sc * (e0 * (g0.w - g1.w) + e1 * d0.w + e2 * d1.w);
+    constexpr float ln2 = 0.6931471805599453f;
+    // d S / d lg = 2^(p t) (h ln2 g + g_lg) while S < 1, with h = -p/2
+    const float dF1 = sF1 < 1.0f ? a1 * (s.h1 * ln2 * gF1 + tF1) : 0.0f;
+    const float dG1 = sG1 < 1.0f ? a1 * (s.h1 * ln2 * gG1 + tG1) : 0.0f;
+    const float dF2 = sF2 < 1.0f ? a2 * (s.h2 * ln2 * gF2 + tF2) : 0.0f;
+    const float dG2 = sG2 < 1.0f ? a2 * (s.h2 * ln2 * gG2 + tG2) : 0.0f;
+    o.dI = -dF1 + ri * s.b * (s.q * ln2 * sF2 + dF2);
+    o.dP = -dG1 + rp * s.b * (s.q * ln2 * sG2 + dG2);
+  }
+  return o;
 }
 
 struct Emit {

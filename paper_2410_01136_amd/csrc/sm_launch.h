@@ -64,6 +64,7 @@ struct FieldPack {
   MlpArgs mlp;
   WmapArgs wmap;
   bool ff = false;  // free-free emission and absorption (constants in FreqArgs)
+  int spec = kSpecPower;  // kSpecBroken: broken power law (table and constants in EmitArgs, FreqArgs)
 };
 
 // Number of 256-thread blocks a launch with S lanes per sightline uses.
@@ -83,6 +84,12 @@ hipError_t launch_forward_va(const GeomArgs& g, const FreqArgs& fa, const EmitAr
 hipError_t launch_forward_va_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                                 const FieldPack& fp, int S, float* maps, double* phi_end,
                                 double* em_end, hipStream_t st);
+hipError_t launch_forward_bp(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                             const FieldPack& fp, int S, float* maps, double* phi_end,
+                             double* em_end, hipStream_t st);
+hipError_t launch_forward_bp_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                                const FieldPack& fp, int S, float* maps, double* phi_end,
+                                double* em_end, hipStream_t st);
 
 // partials: [march_blocks(npix, S)][16] doubles; dtheta: device double[16]
 hipError_t launch_adjoint(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
@@ -98,6 +105,14 @@ hipError_t launch_adjoint_va(const GeomArgs& g, const FreqArgs& fa, const EmitAr
                              const double* em_end, double* partials, double* dtheta, float* gbn,
                              float* gc, hipStream_t st);
 hipError_t launch_adjoint_va_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                                const FieldPack& fp, int S, const float* dmaps,
+                                const double* phi_end, const double* em_end, double* partials,
+                                double* dtheta, float* gbn, float* gc, hipStream_t st);
+hipError_t launch_adjoint_bp(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
+                             const FieldPack& fp, int S, const float* dmaps, const double* phi_end,
+                             const double* em_end, double* partials, double* dtheta, float* gbn,
+                             float* gc, hipStream_t st);
+hipError_t launch_adjoint_bp_ff(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea,
                                 const FieldPack& fp, int S, const float* dmaps,
                                 const double* phi_end, const double* em_end, double* partials,
                                 double* dtheta, float* gbn, float* gc, hipStream_t st);

@@ -107,7 +107,23 @@ struct FreqArgs {
   double tff[kMaxFreq];
   // gridded alpha: log2(e) d ln sI / d alpha without the Gamma-function part
   double va_k1l2[kMaxFreq];
+  // broken power law (prefactors sI, sP above are those of alpha_lo = theta[12]):
+  // log2 of xb B_perp [uG], 2^(p_lo bp_l), 2^(p_hi bp_l), and the prefactor
+  // ratios sI(alpha_hi) / sI(alpha_lo), sP(alpha_hi) / sP(alpha_lo) with the
+  // normalisation gamma_b^(alpha_hi - alpha_lo) of the upper law
+  float bp_l[kMaxFreq];
+  float bp_k1[kMaxFreq];
+  float bp_k2[kMaxFreq];
+  float bp_ri[kMaxFreq];
+  float bp_rp[kMaxFreq];
 };
+
+// Spectral model of the CR electrons: one power law of index theta[12], a
+// gridded index, or a broken power law (alpha_lo = theta[12] below the break
+// Lorentz factor, alpha_hi above it).
+constexpr int kSpecPower = 0;
+constexpr int kSpecGridAlpha = 1;
+constexpr int kSpecBroken = 2;
 
 struct EmitArgs {
   int32_t alpha3;  // alpha == 3 exactly: integer powers, no log/exp
@@ -123,6 +139,11 @@ struct EmitArgs {
   // ln y and the Stirling correction terms at them, and the product
   // Q = x1 (x1 + 1) .. (x1 + 5) x2 (x2 + 1) .. (x2 + 5) (alpha + 1)
   double va_y[2], va_iy[2], va_ly[2], va_ser[2], va_iq;  // va_iq = 1 / Q(alpha_ref)
+  // broken power law: the table of spectrum.h (kBpNodes nodes of two float4:
+  // the four g values, then h dg/dt) and, in powers of B_perp^2, -p_lo / 2,
+  // -p_hi / 2 and (alpha_hi - alpha_lo) / 4
+  const float4* bp_tab;
+  float bp_h1, bp_h2, bp_q;
 };
 
 }  // namespace sm

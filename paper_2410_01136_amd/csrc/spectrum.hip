@@ -1,0 +1,136 @@
+// Host-side builder of the broken power-law table (see spectrum.h).
+//
+// The lower shares S(a, xb) are integrated upward in t = log2 x from their
+// leading small-x power law: dS/dt = ln 2 x^(mu + 1) F(x) / M(mu) with M the
+// complete moment (the closed form behind Eq. ji; for G, Eq. jp), six-point
+// Gauss-Legendre per table interval.  The totals at the top of the table must
+// come out at 1: a check of F, G, the quadrature and the closed forms at once.
+#include <cmath>
+#include <vector>
+
+#include "spectrum.h"
+
+namespace sm {
+namespace {
+
+constexpr double kLn2 = 0.6931471805599453;
+
+// F(x) = x int_x^inf K_5/3 and G(x) = x K_2/3(x), x > 0, from K_nu(x) =
+// int_0^inf e^{-x cosh s} cosh(nu s) ds (exchanging the order of integration,
+// int_x^inf K_5/3 = int_0^inf e^{-x cosh s} cosh(5s/3) / cosh s ds).  The
+// integrands are even and analytic in a strip about the real axis, so the
+// trapezoidal rule on the half line with half weight at s = 0 converges
+// geometrically; its step resolves the width ~ x^-1/2 of the peak at s = 0 for
+// large x, and terms below e^-64 of the first are dropped.
+void synch_fg(double x, double* F, double* G) {
+  const double hs = std::fmin(0.1, 0.4 / std::sqrt(x));
+  double sf = 0.0, sg = 0.0;
+  for (int k = 0;; ++k) {
+    const double s = k * hs, c = std::cosh(s);
+    if (x * (c - 1.0) > 64.0) break;
+    const double e = (k == 0 ? 0.5 : 1.0) * std::exp(-x * c);
+    sf += e * std::cosh(5.0 * s / 3.0) / c;
+    sg += e * std::cosh(2.0 * s / 3.0);
+  }
+  *F = x * hs * sf;
+  *G = x * hs * sg;
+}
+
+// Complete moments int_0^inf x^mu F dx and int_0^inf x^mu G dx.
+double moment_f(double mu) {
+  return std::pow(2.0, mu + 1.0) / (mu + 2.0) * std::tgamma(0.5 * mu + 7.0 / 3.0) *
+         std::tgamma(0.5 * mu + 2.0 / 3.0);
+}
+double moment_g(double mu) {
+  return std::pow(2.0, mu) * std::tgamma(0.5 * mu + 4.0 / 3.0) * std::tgamma(0.5 * mu + 2.0 / 3.0);
+}
+
+// Gauss-Legendre abscissae and weights on [0, 1]: roots of P_n by Newton's
+// method from the usual cosine guesses.
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;  // P_0, P_1, then up to P_n by the three-term recurrence
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // (2 / ((1 - z^2) P_n'^2)) / 2 on [0, 1]
+  }
+}
+
+}  // namespace
+
+bool bp_build_table(double a1, double a2, float* nodes, std::string* err) {
+  constexpr int kGl = 6;
+  constexpr int kBelow = 16 * kBpPerOctave;  // intervals below node 0 (t from -56)
+  const double h = 1.0 / kBpPerOctave;
+  const double al[2] = {a1, a2};
+  double mu[2], p[2], mF[2], mG[2];
+  for (int i = 0; i < 2; ++i) {
+    mu[i] = 0.5 * (al[i] - 3.0);
+    p[i] = bp_power(al[i]);
+    mF[i] = moment_f(mu[i]);
+    mG[i] = moment_g(mu[i]);
+  }
+  double gx[kGl], gw[kGl];
+  gauss_legendre(kGl, gx, gw);
+  // start: S(t_s) from the leading power law, int_0^xs x^mu A x^(1/3) dx =
+  // xs^(mu + 1) F(xs) / p to relative O(xs^(2/3))
+  const double ts = kBpT0 - kBelow * h;
+  double xs = std::exp2(ts), Fs, Gs;
+  synch_fg(xs, &Fs, &Gs);
+  double S[4];  // (F, a1), (G, a1), (F, a2), (G, a2)
+  for (int i = 0; i < 2; ++i) {
+    const double xm = std::pow(xs, mu[i] + 1.0);
+    S[2 * i] = xm * Fs / (p[i] * mF[i]);
+    S[2 * i + 1] = xm * Gs / (p[i] * mG[i]);
+  }
+  auto rate = [&](double t, double* d) {  // dS/dt of the four shares at t
+    const double x = std::exp2(t);
+    double F, G;
+    synch_fg(x, &F, &G);
+    for (int i = 0; i < 2; ++i) {
+      const double xm = kLn2 * std::pow(x, mu[i] + 1.0);
+      d[2 * i] = xm * F / mF[i];
+      d[2 * i + 1] = xm * G / mG[i];
+    }
+  };
+  for (int j = -kBelow; j < kBpNodes; ++j) {
+    const double t = kBpT0 + j * h;
+    if (j >= 0) {
+      double d[4];
+      rate(t, d);
+      float* o = nodes + (size_t)j * 8;
+      for (int c = 0; c < 4; ++c) {
+        const double pc = p[c / 2], sc = std::exp2(-pc * t);
+        o[c] = (float)(S[c] * sc);
+        o[4 + c] = (float)(h * (d[c] - pc * kLn2 * S[c]) * sc);
+      }
+    }
+    if (j == kBpNodes - 1) break;
+    for (int k = 0; k < kGl; ++k) {
+      double d[4];
+      rate(t + gx[k] * h, d);
+      for (int c = 0; c < 4; ++c) S[c] += h * gw[k] * d[c];
+    }
+  }
+  // above the table every share is 1 to ~e^-128: the running totals must be
+  for (int c = 0; c < 4; ++c) {
+    if (!(std::fabs(S[c] - 1.0) < 1e-9)) {
+      if (err) *err = "broken power-law table: moment quadrature missed its closed form";
+      return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace sm

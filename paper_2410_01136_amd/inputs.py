@@ -94,6 +94,12 @@ TE_FF = 8000.0
 FF_GRID_FREQS = (0.15e9, 0.3e9, 0.6e9)
 FF_THETA_FREQS = (0.6e9, 0.8e9, 1.0e9)
 
+# Broken power-law CR spectrum of the workloads that use one: (index above the
+# break, Lorentz factor of the break) with theta[12] below it.  A break at
+# gamma ~ 1.2e4 (~6 GeV) puts xb = nu / nu_c(gamma_b) near 0.3 at 1 GHz in a
+# 6 uG field, so the {1, 2.3, 5} GHz maps straddle the steepening.
+BROKEN = (3.6, 1.2e4)
+
 
 def geometry(name: str, **over) -> Geometry:
     """The geometry of a named configuration (keyword overrides allowed)."""

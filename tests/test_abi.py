@@ -272,3 +272,42 @@ def test_grid_alpha_checked_on_host(sm):
     f.s.grid_alpha = 0x1002
     st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, None)
     assert st == sm.SYN_EINVAL and "grid_alpha" in sm.syn_last_error().decode()
+
+
+def test_broken_spectrum_checked_on_host(sm):
+    g = _geom(sm)
+    assert sm.syn_spectrum_table_bytes() == 753 * 32
+    # the table builder's own arguments
+    for lo, hi in ((1.0 / 3.0, 3.0), (3.0, 6.5), (math.nan, 3.0)):
+        assert sm.syn_spectrum_table(lo, hi, 0x1000, 1 << 20, None) == sm.SYN_EINVAL
+        assert "(1/3, 6]" in sm.syn_last_error().decode()
+    assert sm.syn_spectrum_table(3.0, 3.6, None, 1 << 20, None) == sm.SYN_EINVAL
+    assert sm.syn_spectrum_table(3.0, 3.6, 0x1008, 1 << 20, None) == sm.SYN_EINVAL
+    assert sm.syn_spectrum_table(3.0, 3.6, 0x1000, 100, None) == sm.SYN_EINVAL
+
+    def field(kind=sm.FIELD_MODEL16, **kw):
+        f = sm.Field(kind, I.THETA0)
+        f.s.spectrum, f.s.alpha_hi, f.s.gamma_break, f.s.spectrum_table = sm.SPEC_BROKEN, 3.6, 1e4, 0x1000
+        for k, v in kw.items():
+            setattr(f.s, k, v)
+        return f
+
+    def fwd(f):
+        return sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, None)
+
+    # no table was built at that address for these indices
+    assert fwd(field()) == sm.SYN_EINVAL and "spectrum_table" in sm.syn_last_error().decode()
+    assert fwd(field(spectrum=7)) == sm.SYN_EINVAL and "spectrum must" in sm.syn_last_error().decode()
+    assert fwd(field(alpha_hi=0.2)) == sm.SYN_EINVAL and "(1/3, 6]" in sm.syn_last_error().decode()
+    for gb in (0.5, 1e13, math.inf, math.nan):
+        assert fwd(field(gamma_break=gb)) == sm.SYN_EINVAL
+        assert "gamma_break" in sm.syn_last_error().decode()
+    f = field(kind=sm.FIELD_MLP)
+    assert fwd(f) == sm.SYN_EUNSUPPORTED and "MLP" in sm.syn_last_error().decode()
+    f = field(kind=sm.FIELD_GRID, grid_bn=0x1000, grid_alpha=0x2000)
+    f.s.grid_n[:] = [4, 4, 4]
+    f.s.grid_lo_kpc[:] = [-1, -1, -1]
+    f.s.grid_hi_kpc[:] = [1, 1, 1]
+    assert fwd(f) == sm.SYN_EINVAL and "grid_alpha" in sm.syn_last_error().decode()
+    # a zeroed descriptor stays one power law
+    assert sm.SynField().spectrum == sm.SPEC_POWER_LAW

@@ -1,0 +1,260 @@
+"""Broken power-law CR spectrum on the GPU vs the FP64 oracle, through the C ABI.
+
+The kernels interpolate the moment shares from the host-built table; the
+oracle integrates them afresh at every midpoint.  Maps are held to the forward
+tolerances of parity.py (with the FP32 term floor where the analytic disk is
+Faraday-thick, as for the power law), gradients to those of
+test_gpu_adjoint.py; every lane count and grid read path, with and without
+free-free, the full headline shape in the launch configuration the benchmark
+times, a hardening break, equal indices, and the host's range checks."""
+import numpy as np
+import pytest
+
+from paper_2410_01136_amd import inputs as I
+from parity import FP32_TERMS, check_grid_gradient, compare_maps, oracle_geom
+
+pytestmark = pytest.mark.gpu
+
+LANES = [1, 4, 16, 64]
+C0_MAX_FLOOR = 3
+THETA_T = np.array([5.0, -0.25, 0.15, 0.35, 7.0, 1.2, 2.0, 1.4, 9.0,
+                    4.2e-5, 7.5, 1.1, 2.3, 0.028, 0.9, 0.02])
+
+
+@pytest.fixture(scope="module")
+def sm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2410_01136_amd import binding
+    return binding
+
+
+@pytest.fixture
+def lanes(sm):
+    def set_(kind, S, kernel=0):
+        sm.set_lanes_per_ray(kernel, kind, S)
+    yield set_
+    for k in range(3):
+        for kind in range(5):
+            sm.set_lanes_per_ray(k, kind, 0)
+
+
+_REFS = {}
+
+
+def cached(key, fn):
+    """The oracle's result for key, computed once per module (parametrised
+    cases share their reference)."""
+    if key not in _REFS:
+        _REFS[key] = fn()
+    return _REFS[key]
+
+
+def run(sm, g, field):
+    import torch
+    maps = sm.forward(sm.geom_from(g), field)
+    torch.cuda.synchronize()
+    return maps.cpu().numpy()
+
+
+def check(gpu, ref, label, floor=0.0, max_floor=0):
+    ok, rep = compare_maps(gpu, ref, floor=floor, max_floor=max_floor)
+    print(label, rep, flush=True)
+    assert ok, (label, rep)
+
+
+@pytest.mark.parametrize("S", LANES)
+def test_c0_model16(sm, orc, lanes, S):
+    g = I.geometry("C0", freqs_hz=(1.0e9, 2.3e9, 5.0e9))
+    lanes(sm.FIELD_MODEL16, S)
+    ref = cached("c0", lambda: orc.forward(oracle_geom(orc, g),
+                                           orc.Field(orc.MODEL16, I.THETA0, broken=I.BROKEN)))
+    gpu = run(sm, g, sm.Field(sm.FIELD_MODEL16, I.THETA0, broken=I.BROKEN))
+    check(gpu, ref, f"broken C0 S={S}", FP32_TERMS, 3 * C0_MAX_FLOOR)
+    # the break removes emission relative to the low-energy law continued upward
+    plain = run(sm, g, sm.model16(I.THETA0))
+    assert np.all(gpu[:, 0] < plain[:, 0])
+
+
+@pytest.mark.parametrize("S", [1, 16])
+@pytest.mark.parametrize("theta,broken", [
+    (THETA_T, (3.4, 9.0e3)),  # general alpha below the break
+    (I.THETA0, (2.2, 5.0e3)),  # a hardening break
+    (I.THETA0, (3.0, 1.2e4)),  # equal indices
+])
+def test_model16_spectra(sm, orc, lanes, S, theta, broken):
+    g = I.geometry("C0", freqs_hz=(0.7e9, 1.4e9, 5.0e9))
+    lanes(sm.FIELD_MODEL16, S)
+    ref = cached(("m16", theta[12], broken),
+                 lambda: orc.forward(oracle_geom(orc, g), orc.Field(orc.MODEL16, theta, broken=broken)))
+    gpu = run(sm, g, sm.Field(sm.FIELD_MODEL16, theta, broken=broken))
+    check(gpu, ref, f"broken {theta[12]}->{broken} S={S}", FP32_TERMS, 6 * C0_MAX_FLOOR)
+    if broken[0] == theta[12]:
+        # one index on both sides: the power-law march, to FP32 rounding
+        plain = run(sm, g, sm.model16(theta))
+        check(gpu, plain.astype(np.float64), "equal indices vs power law", FP32_TERMS,
+              6 * C0_MAX_FLOOR)
+
+
+def test_wmap_and_sphere(sm, orc):
+    g = I.geometry("G1", n_steps=256, nside=8, freqs_hz=(1.0e9, 2.4e9))
+    th = I.wmap_theta()
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.WMAP, th, broken=I.BROKEN))
+    check(run(sm, g, sm.Field(sm.FIELD_WMAP, th, broken=I.BROKEN)), ref, "broken WMAP")
+    th = I.sphere_theta()
+    g = I.geometry("E1", nside=8, n_steps=128)
+    ref = orc.forward(oracle_geom(orc, g), orc.Field(orc.SPHERE, th, broken=I.BROKEN))
+    check(run(sm, g, sm.Field(sm.FIELD_SPHERE, th, broken=I.BROKEN)), ref, "broken sphere")
+
+
+def small_turbulent_grid(orc, n=(41, 41, 11), seed0=1001):
+    reg_bn, reg_c = orc.sample_model16(I.THETA0, n, I.BOX_LO, I.BOX_HI)
+    bn = I.turbulent_grids(reg_bn, seeds=(seed0, seed0 + 1, seed0 + 2, seed0 + 3))
+    return bn, reg_c
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("S", LANES)
+def test_grid_three_frequencies(sm, orc, lanes, mode, S):
+    import torch
+    g = I.geometry("C1", nside=16, n_steps=200)
+    bn, c = small_turbulent_grid(orc)
+    lanes(sm.FIELD_GRID, S)
+    sm.set_grid_addressing(mode)
+    try:
+        f = sm.Field(sm.FIELD_GRID, I.THETA0, torch.from_numpy(bn).cuda(),
+                     torch.from_numpy(c).cuda(), I.BOX_LO, I.BOX_HI, broken=I.BROKEN)
+        gpu = run(sm, g, f)
+    finally:
+        sm.set_grid_addressing(0)
+    ref = cached("grid3", lambda: orc.forward(oracle_geom(orc, g), orc.Field(
+        orc.GRID, I.THETA0, grid_bn=bn, grid_c=c, grid_lo=I.BOX_LO, grid_hi=I.BOX_HI,
+        broken=I.BROKEN)))
+    check(gpu, ref, f"broken grid mode={mode} S={S}")
+
+
+@pytest.mark.slow
+def test_c1_full_size_sampled(sm, orc, c1_grids):
+    """The full headline shape (N_side 256, 512 steps, {1, 2.3, 5} GHz, 256^3
+    grids) with the broken spectrum, in the launch configuration the benchmark
+    times; the oracle checks 1500 sampled pixels."""
+    import torch
+    g = I.geometry("C1")
+    bn, reg_c = c1_grids
+    f = sm.Field(sm.FIELD_GRID, I.THETA0, torch.from_numpy(bn).cuda(),
+                 torch.from_numpy(reg_c).cuda(), I.BOX_LO, I.BOX_HI, broken=I.BROKEN)
+    gpu = run(sm, g, f)
+    pix = I.sample_pixels(g.npix, 1500, seed=78)
+    ref = orc.forward_pixels(oracle_geom(orc, g), orc.Field(orc.GRID, I.THETA0, grid_bn=bn,
+                                                            grid_c=reg_c, grid_lo=I.BOX_LO,
+                                                            grid_hi=I.BOX_HI, broken=I.BROKEN),
+                             pix)
+    check(gpu[:, :, pix], np.transpose(ref, (1, 2, 0)), "broken C1 full size, sampled")
+    assert np.isfinite(gpu).all()
+
+
+@pytest.mark.parametrize("S", [1, 16])
+def test_free_free(sm, orc, lanes, S):
+    g = I.geometry("C2", nside=16, n_steps=160, freqs_hz=I.FF_THETA_FREQS)
+    lanes(sm.FIELD_MODEL16, S)
+    of = orc.Field(orc.MODEL16, I.THETA0, te_k=I.TE_FF, broken=I.BROKEN)
+    ref = cached("ff", lambda: orc.forward(oracle_geom(orc, g), of))
+    gpu = run(sm, g, sm.Field(sm.FIELD_MODEL16, I.THETA0, te_k=I.TE_FF, broken=I.BROKEN))
+    check(gpu, ref, f"broken + free-free S={S}", FP32_TERMS, g.npix * len(g.freqs_hz) // 1000)
+
+
+@pytest.mark.parametrize("S", [1, 16, 64])
+@pytest.mark.parametrize("te", [0.0, I.TE_FF])
+def test_theta_gradient(sm, orc, lanes, S, te):
+    import torch
+    g = I.geometry("C2", nside=8, n_steps=96, freqs_hz=(0.8e9, 1.4e9))
+    lanes(sm.FIELD_MODEL16, S, kernel=1)
+    field = sm.Field(sm.FIELD_MODEL16, THETA_T, te_k=te, broken=(3.4, 9.0e3))
+    geom = sm.geom_from(g)
+    ws = sm.alloc_workspace(geom, field)
+    sm.forward(geom, field, ws=ws)
+    dm = I.cotangents((2, 3, g.npix), seed=61)
+    dth = sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws).cpu().numpy()
+    rth, _, _ = cached(("theta", te), lambda: orc.adjoint(
+        oracle_geom(orc, g), orc.Field(orc.MODEL16, THETA_T, te_k=te, broken=(3.4, 9.0e3)),
+        dm.astype(np.float64)))
+    assert dth[12] == 0.0 and rth[12] == 0.0
+    sc = np.maximum(np.abs(THETA_T), 1e-2)
+    err = np.abs(dth - rth) * sc
+    scale = np.abs(rth * sc).max()
+    print(f"broken theta-gradient S={S} te={te}: max scaled err / scale {err.max() / scale:.2e}",
+          flush=True)
+    assert np.all(err <= 1e-3 * scale), (err / scale)
+
+
+@pytest.mark.parametrize("S", [1, 4, 16])
+@pytest.mark.parametrize("te", [0.0, I.TE_FF])
+def test_grid_gradient(sm, orc, lanes, S, te):
+    import torch
+    g = I.geometry("C2", nside=8, n_steps=83, freqs_hz=(0.6e9, 1.4e9))
+    bn, c = small_turbulent_grid(orc, n=(17, 17, 9), seed0=6101)
+    if te:
+        bn[..., 3] = np.abs(bn[..., 3]) * 10.0
+    dm = I.cotangents((2, 3, g.npix), seed=62)
+    lanes(sm.FIELD_GRID, S, kernel=1)
+    field = sm.Field(sm.FIELD_GRID, I.THETA0, torch.from_numpy(bn).cuda(),
+                     torch.from_numpy(c).cuda(), I.BOX_LO, I.BOX_HI, te_k=te, broken=I.BROKEN)
+    geom = sm.geom_from(g)
+    ws = sm.alloc_workspace(geom, field)
+    sm.forward(geom, field, ws=ws)
+    dbn, dc = torch.zeros_like(field.grid_bn), torch.zeros_like(field.grid_c)
+    dth = sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws, want_theta=True, dgrid_bn=dbn,
+                     dgrid_c=dc)
+    torch.cuda.synchronize()
+    of = orc.Field(orc.GRID, I.THETA0, grid_bn=bn, grid_c=c, grid_lo=I.BOX_LO, grid_hi=I.BOX_HI,
+                   te_k=te, broken=I.BROKEN)
+    rth, rbn, rc = cached(("grad", te), lambda: orc.adjoint(oracle_geom(orc, g), of,
+                                                            dm.astype(np.float64), want_grid=True))
+    assert dth.cpu().numpy()[12] == 0.0 and rth[12] == 0.0
+    for a, b, lab in ((dbn.cpu().numpy().astype(np.float64), rbn, "bn"),
+                      (dc.cpu().numpy().astype(np.float64), rc, "N0")):
+        check_grid_gradient(a, b, f"broken grid S={S} te={te} {lab}")
+
+
+def test_grid_gradient_without_piece_snapshots(sm, orc, lanes):
+    # a forward run at another lane count stores no snapshots for the reverse
+    # pass's pieces: the pass recomputes them (the pre-pass with the multipliers)
+    import torch
+    g = I.geometry("C2", nside=8, n_steps=83, freqs_hz=(0.6e9, 1.4e9))
+    bn, c = small_turbulent_grid(orc, n=(17, 17, 9), seed0=6201)
+    dm = I.cotangents((2, 3, g.npix), seed=63)
+    field = sm.Field(sm.FIELD_GRID, I.THETA0, torch.from_numpy(bn).cuda(),
+                     torch.from_numpy(c).cuda(), I.BOX_LO, I.BOX_HI, broken=I.BROKEN)
+    geom = sm.geom_from(g)
+    lanes(sm.FIELD_GRID, 1, kernel=1)
+    ws = sm.alloc_workspace(geom, field)
+    sm.forward(geom, field, ws=ws)
+    lanes(sm.FIELD_GRID, 16, kernel=1)
+    dbn = torch.zeros_like(field.grid_bn)
+    sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws, want_theta=False, dgrid_bn=dbn)
+    torch.cuda.synchronize()
+    of = orc.Field(orc.GRID, I.THETA0, grid_bn=bn, grid_c=c, grid_lo=I.BOX_LO, grid_hi=I.BOX_HI,
+                   broken=I.BROKEN)
+    _, rbn, _ = orc.adjoint(oracle_geom(orc, g), of, dm.astype(np.float64), want_grid=True)
+    check_grid_gradient(dbn.cpu().numpy().astype(np.float64), rbn, "broken grid, pre-pass")
+
+
+def test_table_and_range_checks(sm):
+    import torch
+    g = sm.geom_from(I.geometry("C0"))
+    # a table built for other indices is refused
+    t = sm.spectrum_table(2.9, 3.6)
+    f = sm.Field(sm.FIELD_MODEL16, I.THETA0, broken=I.BROKEN)
+    f.s.spectrum_table = t.data_ptr()
+    maps = torch.empty((1, 3, 12 * 16 * 16), dtype=torch.float32, device="cuda")
+    st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), maps.data_ptr(), None, 0, None)
+    assert st == sm.SYN_EINVAL and "spectrum_table" in sm.syn_last_error().decode()
+    # a break out of reach of the FP32 powers at these frequencies
+    far = sm.Field(sm.FIELD_MODEL16, I.THETA0, broken=(6.0, 1e12))
+    gfar = sm.geom_from(I.geometry("C0", freqs_hz=(1e7,)))
+    st = sm.syn_forward(sm.ctypes.byref(gfar), sm.ctypes.byref(far.s), maps.data_ptr(), None, 0,
+                        None)
+    assert st == sm.SYN_EUNSUPPORTED and "FP32 range" in sm.syn_last_error().decode()
+    # the same table serves every break and frequency of its index pair
+    assert sm.spectrum_table(3.0, 3.6).data_ptr() == sm.spectrum_table(3.0, 3.6).data_ptr()
