@@ -148,7 +148,8 @@ def main() -> int:
                     help="profiling aids: 'c1' runs only the timed headline forward launches; "
                          "'c2' only the N_side 64 adjoint workloads (analytic and 128^3 grid); "
                          "'fit' only the grid fit; 'wmap' only the Sec. 3.1 replay; "
-                         "'hmc' only the Sec. 3.2 sampler; 'ff' only the free-free workloads; "
+                         "'hmc' only the Sec. 3.2 sampler; 'ff' only the physics variants "
+                         "(free-free, gridded index, broken spectrum); "
                          "'c4' only the surrogate (training, then its timed launches); "
                          "'sys' only the Sec. 4.1 systematics replay; "
                          "'copy' runs one 1 GiB device-to-device copy (counter calibration)")
@@ -216,7 +217,7 @@ def main() -> int:
         sm.forward(geom, field, maps=maps)
 
     if args.only == "ff":
-        bench_free_free(sm, I, np, torch, args, field)
+        bench_physics_variants(sm, I, np, torch, args, field)
         return 0
     if args.only == "c4":
         bench_surrogate(sm, I, np, torch, args, field)
@@ -282,7 +283,7 @@ def main() -> int:
         out["grid_fit"] = bench_grid_fit(sm, I, np, torch, args)
         out["wmap"] = bench_wmap(sm, I, np, torch, tune, args)
         out["hmc"] = bench_hmc(sm, I, np, torch, args)
-        out["free_free"] = bench_free_free(sm, I, np, torch, args, field)
+        out["physics_variants"] = bench_physics_variants(sm, I, np, torch, args, field)
         out["systematics"] = bench_systematics(sm, I, np, torch, args)
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(sm, I, np, torch, args, field)
@@ -441,13 +442,14 @@ def bench_wmap(sm, I, np, torch, tune, args):
     return res
 
 
-def bench_free_free(sm, I, np, torch, args, grid_field):
+def bench_physics_variants(sm, I, np, torch, args, grid_field):
     """The physics variants: free-free emission and absorption (T_e = 8000 K,
     the thermal electrons of the fields) on the headline gridded workload
     (N_side 256, 512 steps, 256^3 nodes) moved to {150, 300, 600} MHz and on the
     N_side 64 / 768 step analytic theta-gradient workload (forward + adjoint)
-    at {0.6, 0.8, 1.0} GHz, each timed with and without; and the headline
-    forward with a gridded spectral index, timed with and without."""
+    at {0.6, 0.8, 1.0} GHz, each timed with and without; the headline forward
+    with a gridded spectral index, and with a broken power-law spectrum (also
+    the analytic forward + theta-adjoint), each timed with and without."""
     freqs = I.FF_GRID_FREQS
     te = I.TE_FF
     g = I.geometry("C1", freqs_hz=freqs)
@@ -488,13 +490,44 @@ def bench_free_free(sm, I, np, torch, args, grid_field):
     for name, f in (("plain", grid_field), ("alpha_grid", va)):
         _, ev = time_launches(lambda: sm.forward(geom1, f, maps=maps1), args.steps, args.warmup)
         alpha_ms[name] = round(ev, 4)
+    # a broken power-law CR spectrum (index theta[12] = 3 below gamma_b =
+    # 1.2e4, 3.6 above) on the headline forward and on the analytic
+    # forward + theta-adjoint at 1.4 GHz
+    bp = grid_field.with_broken(I.BROKEN)
+    broken_ms = {}
+    for name, f in (("plain", grid_field), ("broken", bp)):
+        _, ev = time_launches(lambda: sm.forward(geom1, f, maps=maps1), args.steps, args.warmup)
+        broken_ms[name] = round(ev, 4)
+    g3 = I.geometry("C2", freqs_hz=(1.4e9,))
+    geom3 = sm.geom_from(g3)
+    dm3 = torch.from_numpy(I.cotangents((1, 3, g3.npix), seed=7002)).cuda()
+    maps3 = torch.empty((1, 3, g3.npix), dtype=torch.float32, device="cuda")
+    broken_theta_ms = {}
+    for name, f in (("plain", sm.model16(I.THETA0)),
+                    ("broken", sm.model16(I.THETA0).with_broken(I.BROKEN))):
+        ws3 = sm.alloc_workspace(geom3, f)
+
+        def fwd_adj3():
+            sm.forward(geom3, f, maps=maps3, ws=ws3)
+            sm.adjoint(geom3, f, dm3, ws3)
+
+        wall, _ = time_launches(fwd_adj3, args.steps, args.warmup)
+        broken_theta_ms[name] = round(wall, 4)
     res = {
         "workload": "T_e 8000 K; 256^3 grid at N_side 256 x 512 steps at {150, 300, 600} MHz and "
                     "analytic model at N_side 64 x 768 steps (forward + theta-adjoint) at "
                     "{0.6, 0.8, 1.0} GHz; "
-                    "gridded spectral index on the 256^3 headline forward at {1, 2.3, 5} GHz",
+                    "gridded spectral index on the 256^3 headline forward at {1, 2.3, 5} GHz; "
+                    "broken power-law spectrum (3 -> 3.6 at gamma 1.2e4) on the headline forward "
+                    "and on the N_side 64 x 768 analytic forward + theta-adjoint at 1.4 GHz",
         "alpha_grid_forward_ms": alpha_ms,
         "alpha_grid_over_plain": round(alpha_ms["alpha_grid"] / alpha_ms["plain"], 3),
+        "broken_forward_ms": broken_ms,
+        "broken_forward_sightline_steps_per_s": float(f"{g1.units / (broken_ms['broken'] * 1e-3):.4e}"),
+        "broken_over_plain": {"grid_forward": round(broken_ms["broken"] / broken_ms["plain"], 3),
+                              "theta_fwd_adj": round(broken_theta_ms["broken"] /
+                                                     broken_theta_ms["plain"], 3)},
+        "broken_theta_fwd_adj_ms": broken_theta_ms,
         "grid_forward_ms": grid_ms,
         "grid_forward_ff_sightline_steps_per_s": float(f"{g.units / (grid_ms['free_free'] * 1e-3):.4e}"),
         "grid_read_path": grid_read_path(sm, g.npix),
@@ -502,7 +535,7 @@ def bench_free_free(sm, I, np, torch, args, grid_field):
         "ff_over_plain": {"grid_forward": round(grid_ms["free_free"] / grid_ms["plain"], 3),
                           "theta_fwd_adj": round(theta_ms["free_free"] / theta_ms["plain"], 3)},
     }
-    log("free-free:", res)
+    log("physics variants:", res)
     return res
 
 
