@@ -192,7 +192,11 @@ size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t
 syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps, void* ws,
                        size_t ws_bytes, hipStream_t stream);
 
-/* Reverse pass of syn_forward: given dmaps (device) = dL/dmaps, float
+/* Reverse pass of syn_forward -- the gradient of the maps with respect to the
+   field model's inputs that the paper obtains by automatic differentiation of
+   the forward (Sec. 1 and Sec. 2.4; a gradient costs a few forwards, Sec. 2.4
+   and Sec. 4.2) and uses for gradient-based inference (Sec. 3.1-3.2) and for
+   optimising gridded fields (Sec. 3.3).  Given dmaps (device) = dL/dmaps, float
    [n_freq][3][npix], returns dL/dtheta in dtheta (device, double[16], written,
    not accumulated; may be NULL) and, for GRID fields, ADDS dL/dgrid into
    dgrid_bn (device, float [nz][ny][nx][4]) and dgrid_c (device, float
@@ -277,10 +281,13 @@ syn_status syn_mlp_pack(const float* fourier, const float* w_in, const float* b_
                         const float* b_out, void* packed_host);
 
 /* ---- many parameter sets in one persistent launch ------------------------ */
-/* A batch is n_sets MODEL16 parameter vectors, each with its own N_side,
-   sharing one geometry (steps, observer, cap, box, frequency).  One plan runs
-   forward, chi^2 against per-set targets and the adjoint for every set in a
-   single captured HIP graph of persistent work-queue kernels. */
+/* The batched evaluation the paper gets from vectorising the forward and its
+   gradient over parameter sets (Sec. 1 and Sec. 3.2: many sampler chains, or
+   leapfrog states, evaluated together), with the chi^2 likelihood of
+   Sec. 3.1.  A batch is n_sets MODEL16 or WMAP parameter vectors, each with its
+   own N_side, sharing one geometry (steps, observer, cap, box, frequency).  One
+   plan runs forward, chi^2 against per-set targets and the adjoint for every
+   set in a single captured HIP graph of persistent work-queue kernels. */
 typedef struct syn_batch_desc {
   int32_t n_sets;              /* 1 .. 65536                                    */
   const int32_t* nside;        /* [n_sets], powers of two                       */
