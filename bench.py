@@ -782,7 +782,7 @@ def bench_surrogate(sm, I, np, torch, args, grid_field):
     achieved = flops / (s_ev * 1e-3) / 1e12
     res = {
         "workload": "N_side 512 (3,145,728 sightlines), 1024 steps, 1 GHz, 40x40x8 kpc box; MLP 3 -> "
-                    "16 Fourier -> 4 x 128 GELU -> 5, BF16 weights, FP32 accumulation",
+                    "16 Fourier -> 4 x 128 cubic-gated linear units -> 5, BF16 weights, FP32 accumulation",
         "train_seconds": round(tr.seconds, 1), "train_steps": tr.steps,
         "train_loss_standardised": tr.final_loss,
         "surrogate_ms": round(s_ev, 2),

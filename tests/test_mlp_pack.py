@@ -90,11 +90,11 @@ def test_packed_network_matches_model(S):
     tt = xt @ torch.from_numpy(fq).T
     feats = torch.cat([torch.sin(2 * math.pi * tt), torch.cos(2 * math.pi * tt)], 1).numpy()
     bf = lambda a: torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
-    gelu = lambda v: torch.nn.functional.gelu(torch.from_numpy(v), approximate="tanh").numpy()
-    h = gelu(bf(feats) @ A0.T + e["b_in"])  # layer 0 columns are in natural feature order
+    act = lambda v: S.act_cubic(torch.from_numpy(v)).numpy()
+    h = act(bf(feats) @ A0.T + e["b_in"])  # layer 0 columns are in natural feature order
     perm = np.array([feature_of_k(k) for k in range(128)])
     for j in range(3):
-        h = gelu(bf(h[:, perm]) @ Ah[j].T + e["b_h"][j])
+        h = act(bf(h[:, perm]) @ Ah[j].T + e["b_h"][j])
     o = bf(h[:, perm]) @ Ao.T  # 32 rows: outputs at {0,1,2,3,8} and {4,5,6,7,12}
     for rows in ([0, 1, 2, 3, 8], [4, 5, 6, 7, 12]):
         out = o[:, rows] + bout
