@@ -115,6 +115,7 @@ def _load():
         getattr(lib, name).restype = ctypes.c_double
     lib.or_moment_tails.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
     lib.or_j_broken.argtypes = [ctypes.c_double] * 6 + [dp]
+    lib.or_dj_broken.argtypes = [ctypes.c_double] * 6 + [dp, dp]
     lib.or_midpoints.argtypes = [gp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
     lib.or_forward_tabulated.argtypes = [gp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int64, dp, dp]
@@ -205,13 +206,15 @@ def forward_pixels(geom: _Geom, field: Field, pix, want_phi=False):
 
 
 def adjoint(geom: _Geom, field: Field, dmaps, want_grid=False):
-    """Gradient of sum(dmaps * maps): (dtheta[16], dgrid_bn, dgrid_c)."""
+    """Gradient of sum(dmaps * maps): (dtheta, dgrid_bn, dgrid_c); dtheta has 16
+    entries, or 18 for a broken spectrum (then [12] is the index below the break,
+    [16] the index above it, [17] ln gamma_break)."""
     lib = _load()
     dm = np.ascontiguousarray(dmaps, dtype=np.float64)
     npix = 12 * geom.nside ** 2
     if dm.shape != (geom.n_freq, 3, npix):
         raise ValueError("dmaps must be [n_freq][3][npix]")
-    dth = np.zeros(NPARAM)
+    dth = np.zeros(NPARAM + 2 if field.s.spectrum == SPEC_BROKEN else NPARAM)
     gbn = gc = None
     nul = ctypes.POINTER(ctypes.c_double)()
     if want_grid and field.s.kind == GRID:
@@ -328,6 +331,13 @@ def j_broken(a1, a2, gamma_break, nu, bt_gauss, n0):
     out = np.zeros(4)
     _load().or_j_broken(a1, a2, gamma_break, nu, bt_gauss, n0, _dptr(out))
     return out
+
+
+def dj_broken(a1, a2, gamma_break, nu, bt_gauss, n0):
+    """d(j_I, j_P)/d(a1, a2, ln gamma_break): two arrays of 3."""
+    dI, dP = np.zeros(3), np.zeros(3)
+    _load().or_dj_broken(a1, a2, gamma_break, nu, bt_gauss, n0, _dptr(dI), _dptr(dP))
+    return dI, dP
 
 
 def digamma(x):

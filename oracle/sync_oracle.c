@@ -646,6 +646,30 @@ void or_j_broken(double a1, double a2, double gb, double nu, double bt, double n
            jP2 * ((a2 + 1.0) / (2.0 * bt) * (1.0 - tG2) - dtG2);
 }
 
+/* Derivatives of (j_I, j_P) of the broken power law with respect to its
+   parameters (a1, a2, ln gb): dI[3], dP[3].  The shares' dependence on the
+   indices has no elementary form, so all three are taken numerically:
+   central differences at steps h and h/2 combined by Richardson
+   extrapolation, (4 D(h/2) - D(h)) / 3, error O(h^4). */
+void or_dj_broken(double a1, double a2, double gb, double nu, double bt, double n0, double dI[3],
+                  double dP[3]) {
+  const double h = 1e-3;
+  for (int k = 0; k < 3; ++k) {
+    double d[2][2];
+    for (int r = 0; r < 2; ++r) {
+      const double hh = r == 0 ? h : 0.5 * h;
+      double jp[4], jm[4];
+      const double pa[3] = {k == 0 ? hh : 0.0, k == 1 ? hh : 0.0, k == 2 ? hh : 0.0};
+      or_j_broken(a1 + pa[0], a2 + pa[1], gb * exp(pa[2]), nu, bt, n0, jp);
+      or_j_broken(a1 - pa[0], a2 - pa[1], gb * exp(-pa[2]), nu, bt, n0, jm);
+      d[r][0] = (jp[0] - jm[0]) / (2.0 * hh);
+      d[r][1] = (jp[1] - jm[1]) / (2.0 * hh);
+    }
+    dI[k] = (4.0 * d[1][0] - d[0][0]) / 3.0;
+    dP[k] = (4.0 * d[1][1] - d[0][1]) / 3.0;
+  }
+}
+
 /* Emissivities of the spectrum of f (NULL: one power law) at index alpha
    (theta[12] or the local gridded index): out as for or_j_broken. */
 static void or_emissivity(const or_field* f, double alpha, double nu, double bt, double n0,
@@ -919,7 +943,7 @@ int or_forward_tabulated(const or_geom* g, double alpha, const int64_t* pix, int
    of (T_I, T_Q, T_U) at this pixel.  Grid gradients go to gbn ([v][4]) and gc
    ([v]) when non-NULL; theta gradients to tb[16]. */
 static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, const double* dm,
-                             double* tb, double* gbn, double* gc) {
+                             double* tb, double* gbn, double* gc, int want_spec) {
   or_ray ray;
   or_make_ray(g, p, &ray);
   const int N = g->n_steps;
@@ -1019,6 +1043,13 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
         double dI, dP;
         or_dlnj_dalpha(alpha, nu, q[n].Bt, &dI, &dP);
         ab += gI * jI * dI + gP * jP * dP;
+      } else if (want_spec) {
+        /* (a1, a2, ln gamma_b): theta[12], then the two entries after theta */
+        double dI[3], dP[3];
+        or_dj_broken(alpha, f->alpha_hi, f->gamma_break, nu, q[n].Bt, q[n].n0, dI, dP);
+        ab += gI * dI[0] + gP * dP[0];
+        tb[OR_NPARAM] += gI * dI[1] + gP * dP[1];
+        tb[OR_NPARAM + 1] += gI * dI[2] + gP * dP[2];
       }
     }
     double numb = 0.0, denb = 0.0;
@@ -1027,8 +1058,7 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
       numb = Btb * q[n].num / q[n].Bt + chi0b[n] * q[n].den / bt2;
       denb = Btb * q[n].den / q[n].Bt - chi0b[n] * q[n].num / bt2;
     }
-    /* a gridded index is an input without a gradient; so are the indices and
-       break of the broken spectrum (ab stays 0) */
+    /* a gridded index is an input without a gradient */
     if (!alpha_gridded) tb[12] += ab;
     /* num = 1e-6 B.e_b, den = -1e-6 B.e_l, blos = -1e-6 B.n  (B in uG) */
     double Bb[3];
@@ -1080,7 +1110,9 @@ static void or_adjoint_pixel(const or_geom* g, const or_field* f, int64_t p, con
 
 /*
  * Gradient of L = sum_{f,s,p} dmaps[f][s][p] * maps[f][s][p] (maps from
- * or_forward) with respect to theta (dtheta[16], may be NULL) and, for grid
+ * or_forward) with respect to theta (dtheta[16], may be NULL; for a broken
+ * power-law spectrum dtheta[18]: theta[12] is the index below the break and
+ * dtheta[16], dtheta[17] are the derivatives in alpha_hi and ln gamma_break) and, for grid
  * fields, the grid values (dgrid_bn [nz][ny][nx][4], dgrid_c [nz][ny][nx]; each
  * may be NULL).  Pixels run in parallel; each thread keeps its own theta sums
  * and grid contributions are added atomically.
@@ -1090,14 +1122,15 @@ int or_adjoint(const or_geom* g, const or_field* f, const double* dmaps, double*
   if (or_check(g, f)) return -1;
   const int64_t npix = 12LL * g->nside * g->nside;
   const int nf = g->n_freq;
-  double tb[OR_NPARAM] = {0};
+  double tb[OR_NPARAM + 2] = {0};
+  const int nt = f->spectrum == OR_SPEC_BROKEN ? OR_NPARAM + 2 : OR_NPARAM;
   int64_t nv = 0;
   if (f->kind == OR_GRID) nv = (int64_t)f->grid_n[0] * f->grid_n[1] * f->grid_n[2];
   if (dgrid_bn) memset(dgrid_bn, 0, sizeof(double) * 4 * (size_t)nv);
   if (dgrid_c) memset(dgrid_c, 0, sizeof(double) * (size_t)nv);
 #pragma omp parallel
   {
-    double tl[OR_NPARAM] = {0};
+    double tl[OR_NPARAM + 2] = {0};
 #pragma omp for schedule(dynamic, 16)
     for (int64_t p = 0; p < npix; ++p) {
       double dm[3 * OR_MAX_FREQ];
@@ -1107,13 +1140,13 @@ int or_adjoint(const or_geom* g, const or_field* f, const double* dmaps, double*
           dm[3 * k + s] = dmaps[((int64_t)k * 3 + s) * npix + p];
           any |= dm[3 * k + s] != 0.0;
         }
-      if (any) or_adjoint_pixel(g, f, p, dm, tl, dgrid_bn, dgrid_c);
+      if (any) or_adjoint_pixel(g, f, p, dm, tl, dgrid_bn, dgrid_c, dtheta != NULL);
     }
 #pragma omp critical
-    for (int k = 0; k < OR_NPARAM; ++k) tb[k] += tl[k];
+    for (int k = 0; k < nt; ++k) tb[k] += tl[k];
   }
   if (dtheta)
-    for (int k = 0; k < OR_NPARAM; ++k) dtheta[k] = tb[k];
+    for (int k = 0; k < nt; ++k) dtheta[k] = tb[k];
   return 0;
 }
 

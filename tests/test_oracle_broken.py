@@ -217,7 +217,7 @@ def test_theta_gradient_matches_finite_differences(orc):
     g = orc.make_geom(4, 48, FREQS, r_max=20.0)
     dm = I.cotangents((2, 3, 192), seed=21).astype(np.float64)
     dth, _, _ = orc.adjoint(g, orc.Field(orc.MODEL16, THETA_T, broken=BROKEN), dm)
-    assert dth[12] == 0.0  # the spectral parameters carry no gradient
+    assert dth.shape == (18,)
 
     def fd(k, rel=1e-5):
         h = rel * max(abs(THETA_T[k]), 1e-2 if k not in (9, 13) else abs(THETA_T[k]))
@@ -231,7 +231,7 @@ def test_theta_gradient_matches_finite_differences(orc):
 
         return (4 * d(h / 2) - d(h)) / 3
 
-    ks = [k for k in range(16) if k != 12]
+    ks = list(range(16))
     ref = {k: fd(k) for k in ks}
     scale = max(abs(ref[k]) * max(abs(THETA_T[k]), 1e-2) for k in ks)
     for k in ks:
@@ -277,3 +277,43 @@ def test_grid_gradient_matches_finite_differences(orc):
         assert abs(fdv - ana) * abs(v0) <= 1e-6 * scale + 1e-9 * abs(ana * v0), (idx, fdv, ana)
         checked += abs(ana * v0) > 1e-3 * scale
     assert checked >= 8
+
+
+def test_spectral_parameter_gradient_matches_finite_differences(orc):
+    """The gradient in (alpha_hi, ln gamma_b) (dtheta[16], [17]) and in the index
+    below the break (dtheta[12]) against central differences of the maps, with
+    and without free-free."""
+    g = orc.make_geom(4, 40, FREQS, r_max=20.0)
+    dm = I.cotangents((2, 3, 192), seed=23).astype(np.float64)
+    for te in (0.0, 8000.0):
+        dth, _, _ = orc.adjoint(g, orc.Field(orc.MODEL16, THETA_T, te_k=te, broken=BROKEN), dm)
+
+        def loss(a1, a2, lng):
+            th = THETA_T.copy()
+            th[12] = a1
+            return _loss(orc, g, orc.Field(orc.MODEL16, th, te_k=te, broken=(a2, math.exp(lng))), dm)
+
+        p0 = np.array([THETA_T[12], BROKEN[0], math.log(BROKEN[1])])
+        for k, idx in ((0, 12), (1, 16), (2, 17)):
+            def d(h):
+                e = np.zeros(3)
+                e[k] = h
+                return (loss(*(p0 + e)) - loss(*(p0 - e))) / (2 * h)
+            h = 1e-3
+            fdv = (4 * d(h / 2) - d(h)) / 3
+            assert dth[idx] == pytest.approx(fdv, rel=1e-6), (te, k, dth[idx], fdv)
+
+
+def test_spectral_derivatives_of_the_emissivity(orc):
+    # the numerical derivatives against an independent closed form where one
+    # exists: with equal indices the gamma_b dependence cancels (d/d ln gb = 0)
+    # and d/da of j at a1 = a2 = a sums to d j(a) / d a of Eq. ji
+    nu, bt = 1.4e9, 5e-6
+    for a in (2.4, 3.0):
+        dI, dP = orc.dj_broken(a, a, 1e4, nu, bt, 1.0)
+        assert abs(dI[2]) <= 1e-9 * orc.j_I(a, nu, bt, 1.0)
+        h = 1e-4
+        ref = (orc.j_I(a + h, nu, bt, 1.0) - orc.j_I(a - h, nu, bt, 1.0)) / (2 * h)
+        assert dI[0] + dI[1] == pytest.approx(ref, rel=1e-6)
+        refp = (orc.j_P(a + h, nu, bt, 1.0) - orc.j_P(a - h, nu, bt, 1.0)) / (2 * h)
+        assert dP[0] + dP[1] == pytest.approx(refp, rel=1e-6)
