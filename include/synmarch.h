@@ -162,8 +162,10 @@ typedef struct syn_field {
    geometry (for B_perp from 2^-20 to 2^20 uG the powers of xb the kernels form
    stay finite; else SYN_EUNSUPPORTED naming the frequency).  Not with
    grid_alpha (SYN_EINVAL), the MLP surrogate or batch plans
-   (SYN_EUNSUPPORTED).  Gradients flow through B, n_e and N0; theta[12],
-   alpha_hi and gamma_break receive none (dtheta[12] = 0). */
+   (SYN_EUNSUPPORTED).  syn_adjoint differentiates the spectrum too: dtheta
+   then holds 18 doubles, dtheta[12] = dL/d alpha_lo (theta[12]), dtheta[16] =
+   dL/d alpha_hi and dtheta[17] = dL/d ln gamma_break (the index derivatives of
+   the moment shares come from a second part of the table). */
 
 /* Bytes of a broken power-law table (device memory the caller allocates). */
 size_t syn_spectrum_table_bytes(void);
@@ -179,6 +181,16 @@ size_t syn_spectrum_table_bytes(void);
    SYN_EHIP if the copy fails. */
 syn_status syn_spectrum_table(double alpha_lo, double alpha_hi, void* table, size_t table_bytes,
                               hipStream_t stream);
+
+/* The same table built into host memory (table (host) float, table_bytes >=
+   syn_spectrum_table_bytes()), for inspection: two parts of 753 nodes x 8
+   floats, node k at t = log2 xb = -40 + k / 16 holding (g_F(lo), g_G(lo),
+   g_F(hi), g_G(hi)) and h dg/dt of each, g = S 2^(-p t), p = a / 2 - 1/6; the
+   second part the same for the derivatives in each function's own index.
+   Fields accept only tables that syn_spectrum_table wrote.  SYN_EINVAL as
+   syn_spectrum_table. */
+syn_status syn_spectrum_table_host(double alpha_lo, double alpha_hi, float* table,
+                                   size_t table_bytes);
 
 /* Bytes of workspace syn_forward needs; with_adjoint != 0 adds what the
    matching syn_adjoint reads (the Faraday sum of every sightline, 8 B per
@@ -197,8 +209,9 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
    the forward (Sec. 1 and Sec. 2.4; a gradient costs a few forwards, Sec. 2.4
    and Sec. 4.2) and uses for gradient-based inference (Sec. 3.1-3.2) and for
    optimising gridded fields (Sec. 3.3).  Given dmaps (device) = dL/dmaps, float
-   [n_freq][3][npix], returns dL/dtheta in dtheta (device, double[16], written,
-   not accumulated; may be NULL) and, for GRID fields, ADDS dL/dgrid into
+   [n_freq][3][npix], returns dL/dtheta in dtheta (device, double[16], or
+   double[18] for a broken power-law spectrum (see above); written, not
+   accumulated; may be NULL) and, for GRID fields, ADDS dL/dgrid into
    dgrid_bn (device, float [nz][ny][nx][4]) and dgrid_c (device, float
    [nz][ny][nx]) when non-NULL (atomic float adds: bitwise order may vary).
    ws must be the workspace of the syn_forward call with the same geom and

@@ -74,6 +74,8 @@ syn_adjoint = _sig("syn_adjoint", _i32, [_G, _F, _vp, _vp, _sz, _vp, _vp, _vp, _
 syn_spectrum_table_bytes = _sig("syn_spectrum_table_bytes", _sz, [])
 syn_spectrum_table = _sig("syn_spectrum_table", _i32,
                           [ctypes.c_double, ctypes.c_double, _vp, _sz, _vp])
+syn_spectrum_table_host = _sig("syn_spectrum_table_host", _i32,
+                               [ctypes.c_double, ctypes.c_double, _vp, _sz])
 syn_chi2_workspace_bytes = _sig("syn_chi2_workspace_bytes", _sz, [_i64, _i32])
 syn_chi2 = _sig("syn_chi2", _i32, [_i64, _i32, _vp, _vp, _dp, _vp, _vp, _vp, _sz, _vp])
 syn_chi2_cotangent = _sig("syn_chi2_cotangent", _i32, [_i64, _i32, _vp, _vp, _dp, _vp, _vp, _vp])
@@ -295,9 +297,12 @@ def forward(geom: SynGeom, field: Field, maps: Optional[torch.Tensor] = None,
 def adjoint(geom: SynGeom, field: Field, dmaps: torch.Tensor, ws: torch.Tensor,
             want_theta: bool = True, dgrid_bn: Optional[torch.Tensor] = None,
             dgrid_c: Optional[torch.Tensor] = None, stream=None):
-    """dL/dtheta (float64 [16] on device, or None); grid gradients ADDED in place."""
+    """dL/dtheta (float64 [16] on device, or None); grid gradients ADDED in place.
+    With a broken power-law spectrum dtheta has 18 entries: [12] the index below
+    the break, [16] the index above it, [17] ln gamma_break."""
     _dev_f32(dmaps, "dmaps")
-    dth = torch.empty(NPARAM, dtype=torch.float64, device=dmaps.device) if want_theta else None
+    nth = NPARAM + 2 if field.s.spectrum == SPEC_BROKEN else NPARAM
+    dth = torch.empty(nth, dtype=torch.float64, device=dmaps.device) if want_theta else None
     if dgrid_bn is not None:
         _dev_f32(dgrid_bn, "dgrid_bn")
     if dgrid_c is not None:
@@ -445,7 +450,8 @@ class SynMarchFn(torch.autograd.Function):
         dth = adjoint(ctx.geom, ctx.field, dmaps, ctx.ws, want_theta=need_th, dgrid_bn=dbn,
                       dgrid_c=dc)
         if dth is not None:
-            dth = dth.to(ctx.theta_device)
+            # (a broken spectrum's two parameters after theta are not inputs here)
+            dth = dth[:NPARAM].to(ctx.theta_device)
         return dth, dbn, dc, None, None
 
 

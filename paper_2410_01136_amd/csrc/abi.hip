@@ -398,6 +398,13 @@ double bp_ln_prefactor(double a, double base) {
   return 0.5 * (1.0 - a) * log(base) + 0.5 * (a + 1.0) * log(2.0) - log(a + 1.0) +
          lgamma(a / 4.0 - 1.0 / 12.0) + lgamma(a / 4.0 + 19.0 / 12.0) + 0.5 * (a + 1.0) * log(1e-6);
 }
+// its derivative in a, and that of ln (j_P / j_I) = ln((a + 1) / (a + 7/3))
+double bp_dln_prefactor(double a, double base) {
+  return -0.5 * log(base) + 0.5 * log(2.0) - 1.0 / (a + 1.0) +
+         0.25 * digamma_host(a / 4.0 - 1.0 / 12.0) + 0.25 * digamma_host(a / 4.0 + 19.0 / 12.0) +
+         0.5 * log(1e-6);
+}
+double bp_dln_pol(double a) { return 1.0 / (a + 1.0) - 1.0 / (a + 7.0 / 3.0); }
 
 syn_status bp_args(const syn_geom* g, const syn_field* f, sm::FreqArgs* fa, sm::EmitArgs* ea) {
   const double a1 = f->theta[12], a2 = f->alpha_hi, gb = f->gamma_break;
@@ -434,6 +441,10 @@ syn_status bp_args(const syn_geom* g, const syn_field* f, sm::FreqArgs* fa, sm::
     fa->bp_k2[k] = (float)exp2(p2 * L);
     fa->bp_ri[k] = (float)exp2(lr);
     fa->bp_rp[k] = (float)exp2(lrp);
+    fa->bp_dri1[k] = (float)(-log(gb) - bp_dln_prefactor(a1, base));
+    fa->bp_dri2[k] = (float)(log(gb) + bp_dln_prefactor(a2, base));
+    fa->bp_drp1[k] = fa->bp_dri1[k] - (float)bp_dln_pol(a1);
+    fa->bp_drp2[k] = fa->bp_dri2[k] + (float)bp_dln_pol(a2);
   }
   return SYN_OK;
 }
@@ -441,11 +452,12 @@ syn_status bp_args(const syn_geom* g, const syn_field* f, sm::FreqArgs* fa, sm::
 size_t ws_phi_bytes(int64_t npix) { return (size_t)((npix * 8 + 255) / 256 * 256); }
 
 // Workspace: the Faraday sum of every sightline, with free-free also its
-// emission-measure sum, then the per-block theta partials.
-size_t ws_bytes_for(int64_t npix, bool adjoint, bool ff) {
+// emission-measure sum, then the per-block theta partials (with a broken
+// spectrum, two more per block: its index above the break and ln gamma_b).
+size_t ws_bytes_for(int64_t npix, bool adjoint, bool ff, bool bp) {
   if (!adjoint) return 0;
   return ws_phi_bytes(npix) * (ff ? 2 : 1) +
-         (size_t)sm::march_blocks(npix, 64) * sm::kNParam * sizeof(double);
+         (size_t)sm::march_blocks(npix, 64) * (sm::kNParam + (bp ? 2 : 0)) * sizeof(double);
 }
 
 // Piece snapshots for a grid-gradient reverse pass of `pieces` pieces (see
@@ -545,15 +557,26 @@ const char* syn_last_error(void) { return g_err.c_str(); }
 
 size_t syn_spectrum_table_bytes(void) { return sm::kBpTableBytes; }
 
+syn_status syn_spectrum_table_host(double alpha_lo, double alpha_hi, float* table,
+                                   size_t table_bytes) {
+  if (!bp_alpha_ok(alpha_lo) || !bp_alpha_ok(alpha_hi))
+    return fail(SYN_EINVAL, "broken power law: indices must lie in (1/3, 6]");
+  if (table == nullptr || table_bytes < sm::kBpTableBytes)
+    return fail(SYN_EINVAL, "table must hold syn_spectrum_table_bytes() bytes");
+  std::string err;
+  if (!sm::bp_build_table(alpha_lo, alpha_hi, table, &err)) return fail(SYN_EINVAL, err);
+  return SYN_OK;
+}
+
 syn_status syn_spectrum_table(double alpha_lo, double alpha_hi, void* table, size_t table_bytes,
                               hipStream_t stream) {
   if (!bp_alpha_ok(alpha_lo) || !bp_alpha_ok(alpha_hi))
     return fail(SYN_EINVAL, "broken power law: indices must lie in (1/3, 6]");
   if (table == nullptr || ((uintptr_t)table & 15) != 0 || table_bytes < sm::kBpTableBytes)
     return fail(SYN_EINVAL, "table must be a 16-byte aligned device buffer of syn_spectrum_table_bytes()");
-  std::vector<float> host((size_t)sm::kBpNodes * 8);
-  std::string err;
-  if (!sm::bp_build_table(alpha_lo, alpha_hi, host.data(), &err)) return fail(SYN_EINVAL, err);
+  std::vector<float> host(sm::kBpTableBytes / sizeof(float));
+  const syn_status s = syn_spectrum_table_host(alpha_lo, alpha_hi, host.data(), sm::kBpTableBytes);
+  if (s != SYN_OK) return s;
   // the copy is synchronised before the host buffer goes
   hipError_t e = hipMemcpyAsync(table, host.data(), sm::kBpTableBytes, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -568,7 +591,7 @@ size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t
   if (check_geom(geom, &ga) != SYN_OK) return 0;
   if (check_field(field, &fp, false) != SYN_OK) return 0;
   if (with_adjoint == 0) return 0;
-  size_t b = ws_bytes_for(ga.npix, true, fp.ff);
+  size_t b = ws_bytes_for(ga.npix, true, fp.ff, fp.spec == sm::kSpecBroken);
   if (field->kind == SYN_FIELD_GRID) {
     int tm = 0;
     const int pieces = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps,
@@ -614,7 +637,7 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
   double* em_end = nullptr;
   int pieces = 0;  // snapshots stored for a grid-gradient reverse pass of this many pieces
   if (ws != nullptr) {
-    const size_t base = ws_bytes_for(ga.npix, true, fp.ff);
+    const size_t base = ws_bytes_for(ga.npix, true, fp.ff, fp.spec == sm::kSpecBroken);
     if (ws_bytes < base || ((uintptr_t)ws & 7) != 0)
       return fail(SYN_EWORKSPACE, "workspace smaller than syn_workspace_bytes(...,1) or misaligned");
     phi_end = static_cast<double*>(ws);
@@ -678,7 +701,8 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   s = check_field(field, &fp, true);
   if (s != SYN_OK) return s;
   if (dmaps == nullptr || ((uintptr_t)dmaps & 3) != 0) return fail(SYN_EINVAL, "dmaps must be a 4-byte aligned device pointer");
-  if (ws == nullptr || ws_bytes < ws_bytes_for(ga.npix, true, fp.ff) || ((uintptr_t)ws & 7) != 0)
+  const bool bp = fp.spec == sm::kSpecBroken;
+  if (ws == nullptr || ws_bytes < ws_bytes_for(ga.npix, true, fp.ff, bp) || ((uintptr_t)ws & 7) != 0)
     return fail(SYN_EWORKSPACE, "adjoint needs the workspace of the matching forward");
   if (field->kind != SYN_FIELD_GRID && (dgrid_bn != nullptr || dgrid_c != nullptr))
     return fail(SYN_EINVAL, "grid gradients need a GRID field");
@@ -709,7 +733,7 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
     // the forward stored the sums at the ends of `pieces` pieces: split the
     // sightlines the same way and skip the pre-pass over each piece
     S = pieces;
-    fp.grid.snap = reinterpret_cast<double*>(w + ws_bytes_for(ga.npix, true, fp.ff));
+    fp.grid.snap = reinterpret_cast<double*>(w + ws_bytes_for(ga.npix, true, fp.ff, bp));
     fp.grid.pieces = pieces;
     fp.grid.piece_len = (ga.n_steps + pieces - 1) / pieces;
     fp.grid.snap_nq = snap_quantities(geom->n_freq, fp.ff);

@@ -92,9 +92,11 @@ __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitAr
   int64_t q = tid / S;
   const bool valid = q < g.npix;
   if (!valid) q = g.npix - 1;
-  double tb[THETA ? kNParam : 1];
+  // theta partials; a broken spectrum adds its two parameters after theta
+  constexpr int NPT = THETA ? (SP == kSpecBroken ? kNParam + 2 : kNParam) : 1;
+  double tb[NPT];
 #pragma unroll
-  for (int k = 0; k < (THETA ? kNParam : 1); ++k) tb[k] = 0.0;
+  for (int k = 0; k < NPT; ++k) tb[k] = 0.0;
   AdjBox box;
   float* stage = nullptr;
   if constexpr (GRID) {
@@ -111,25 +113,29 @@ __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitAr
     fld.flush_box(box, gbn, gc, threadIdx.x, 256);
   }
   if constexpr (THETA) {
-    const double r = block_reduce16(tb, threadIdx.x);
-    if (threadIdx.x < kNParam) partials[blk * kNParam + threadIdx.x] = r;
+    const double r = block_reduce<NPT>(tb, threadIdx.x);
+    if (threadIdx.x < NPT) partials[blk * NPT + threadIdx.x] = r;
   }
 }
 
-// Sums the per-block partials in a fixed order: 16 strided lanes per
-// parameter, then a fixed tree.
-template <class T>
+// Sums the per-block partials (NP per block) in a fixed order: G strided
+// groups of lanes per parameter, then a fixed sum over the groups.
+template <class T, int NP = kNParam>
 __global__ __launch_bounds__(256) void k_reduce_partials(const T* __restrict__ partials,
                                                          int64_t nblk, T* __restrict__ out) {
-  __shared__ T red[16][17];
-  const int k = threadIdx.x & 15, j = threadIdx.x >> 4;
+  constexpr int L = NP <= 16 ? 16 : 32;  // lanes per group (>= NP)
+  constexpr int G = 256 / L;
+  static_assert(NP <= 32, "at most 32 parameters");
+  __shared__ T red[G][L + 1];
+  const int k = threadIdx.x & (L - 1), j = threadIdx.x / L;
   T acc = 0.0;
-  for (int64_t b = j; b < nblk; b += 16) acc += partials[b * kNParam + k];
+  if (k < NP)
+    for (int64_t b = j; b < nblk; b += G) acc += partials[b * NP + k];
   red[j][k] = acc;
   __syncthreads();
-  if (threadIdx.x < 16) {
+  if (threadIdx.x < NP) {
     T s = 0.0;
-    for (int jj = 0; jj < 16; ++jj) s += red[jj][threadIdx.x];
+    for (int jj = 0; jj < G; ++jj) s += red[jj][threadIdx.x];
     out[threadIdx.x] = s;
   }
 }
@@ -175,7 +181,8 @@ static hipError_t adj_go(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (TH) {
-    k_reduce_partials<double><<<dim3(1), dim3(256), 0, st>>>(part, nb, dth);
+    constexpr int NPT = SP == kSpecBroken ? kNParam + 2 : kNParam;
+    k_reduce_partials<double, NPT><<<dim3(1), dim3(256), 0, st>>>(part, nb, dth);
     e = hipGetLastError();
   }
   return e;

@@ -324,8 +324,10 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   constexpr bool VA = SP == kSpecGridAlpha, BP = SP == kSpecBroken;
   constexpr bool PF = FF || VA || BP;  // per-frequency multipliers of the emission
   // (with a gridded alpha, theta[12] does not enter the maps: no alpha
-  // gradient; the indices and break of a broken power law have none either)
-  constexpr bool ALPHA_GRAD = THETA && !VA && !BP;
+  // gradient); a broken power law adds the gradient in its index above the
+  // break and in ln gamma_b as tb[kNParam], tb[kNParam + 1]
+  constexpr bool ALPHA_GRAD = THETA && !VA;
+  constexpr bool SPEC_GRAD = THETA && BP;
 
   // per-sightline cotangent constants
   double GI = 0.0;
@@ -505,6 +507,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   float tbf[THETA ? kNParam : 1];
 #pragma unroll
   for (int k = 0; k < (THETA ? kNParam : 1); ++k) tbf[k] = 0.0f;
+  float spg[3] = {0.0f, 0.0f, 0.0f};  // SPEC_GRAD: d L / d (alpha_lo, alpha_hi, ln gamma_b)
   constexpr int MPF = PF ? MF : 1;
   // A step's cotangent rotations and multipliers, and this lane's alpha sums,
   // are FP32: each step's terms are FP32 products; the sums over steps that
@@ -617,9 +620,11 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
             mI = va_ratio(vs, fa.va_k1l2[f], al, ea);
             mP = mI * vs.prat;
           }
+          BpMult bm{};
           if constexpr (BP) {
-            const BpMult bm = bp_mult<true>(bs, fa.bp_l[f], fa.bp_k1[f], fa.bp_k2[f], fa.bp_ri[f],
-                                            fa.bp_rp[f], ea.bp_tab);
+            bm = bp_mult<true, SPEC_GRAD>(
+                bs, fa.bp_l[f], fa.bp_k1[f], fa.bp_k2[f], fa.bp_ri[f], fa.bp_rp[f], ea.bp_tab,
+                BpSpecArgs{fa.bp_dri1[f], fa.bp_dri2[f], fa.bp_drp1[f], fa.bp_drp2[f]});
             mI = bm.mI;
             mP = bm.mP;
             dmI = bm.dI;
@@ -630,8 +635,15 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
             mI *= att;
             mP *= att;
           }
-          if constexpr (BP)
-            xlg += att * (gis[f] * e.u * dmI + dmP * (hrf * e.zr - hif * e.zi));
+          if constexpr (BP) {
+            // cotangents of this step's multipliers of I and of Q + iU
+            const float wI = att * gis[f] * e.u, wP = att * (hrf * e.zr - hif * e.zi);
+            xlg += wI * dmI + wP * dmP;
+            if constexpr (SPEC_GRAD) {
+#pragma unroll
+              for (int j = 0; j < 3; ++j) spg[j] += wI * bm.sI[j] + wP * bm.sP[j];
+            }
+          }
           Hr += mP * hrf;
           Hi += mP * hif;
           Kr += mP * krf;
@@ -720,6 +732,11 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 #pragma unroll
     for (int k = 0; k < kNParam; ++k) tb[k] += (double)tbf[k];
   }
+  if constexpr (SPEC_GRAD) {
+    tb[12] += (double)spg[0];
+    tb[kNParam] += (double)spg[1];
+    tb[kNParam + 1] += (double)spg[2];
+  }
 
   if constexpr (ALPHA_GRAD) {
     // alpha also enters the per-frequency prefactors: d ln s / d alpha * this lane's share
@@ -734,13 +751,14 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   }
 }
 
-// Sums tb[16] over the 256 threads of a block in a fixed order (wavefront
-// butterfly, then the four waves); thread k < 16 returns the total of k.
-__device__ inline double block_reduce16(const double* tb, int k_out) {
-  __shared__ double red[4][kNParam];
+// Sums tb[NP] over the 256 threads of a block in a fixed order (wavefront
+// butterfly, then the four waves); thread k < NP returns the total of k.
+template <int NP>
+__device__ inline double block_reduce(const double* tb, int k_out) {
+  __shared__ double red[4][NP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < kNParam; ++k) {
+  for (int k = 0; k < NP; ++k) {
     double v = tb[k];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -748,9 +766,12 @@ __device__ inline double block_reduce16(const double* tb, int k_out) {
   }
   __syncthreads();
   double r = 0.0;
-  if (k_out < kNParam) r = (red[0][k_out] + red[1][k_out]) + (red[2][k_out] + red[3][k_out]);
+  if (k_out < NP) r = (red[0][k_out] + red[1][k_out]) + (red[2][k_out] + red[3][k_out]);
   __syncthreads();
   return r;
+}
+__device__ inline double block_reduce16(const double* tb, int k_out) {
+  return block_reduce<kNParam>(tb, k_out);
 }
 
 }  // namespace sm

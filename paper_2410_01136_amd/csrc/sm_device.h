@@ -1178,16 +1178,23 @@ __device__ inline BpStep bp_step(float bl, float bb, const EmitArgs& ea) {
 }
 
 struct BpMult {
-  float mI, mP;  // multipliers of the lower law's I and Q + iU
-  float dI, dP;  // their derivatives in lg (DERIV only)
+  float mI, mP;      // multipliers of the lower law's I and Q + iU
+  float dI, dP;      // their derivatives in lg (DERIV only)
+  float sI[3], sP[3];  // their derivatives in (alpha_lo, alpha_hi, ln gamma_b) (SPEC only)
 };
 
-template <bool DERIV>
+// Per-frequency constants of the gradient in the spectral parameters.
+struct BpSpecArgs {
+  float dri1, dri2, drp1, drp2;
+};
+
+template <bool DERIV, bool SPEC = false>
 __device__ inline BpMult bp_mult(const BpStep& s, float l, float k1, float k2, float ri, float rp,
-                                 const float4* __restrict__ tab) {
+                                 const float4* __restrict__ tab, BpSpecArgs sa = {}) {
   // node and offset from 16 t: the product is exact and so is its split, so the
   // offset keeps the full precision of t
-  const float m = (l - 0.5f * s.lg) * (float)kBpPerOctave;
+  const float tt = l - 0.5f * s.lg;  // t = log2 xb
+  const float m = tt * (float)kBpPerOctave;
   const float fl = floorf(m);
   float r = m - fl;
   int k = (int)fl - (int)(kBpT0 * kBpPerOctave);
@@ -1232,6 +1239,40 @@ __device__ inline BpMult bp_mult(const BpStep& s, float l, float k1, float k2, f
     const float dG2 = sG2 < 1.0f ? a2 * (s.h2 * ln2 * gG2 + tG2) : 0.0f;
     o.dI = -dF1 + ri * s.b * (s.q * ln2 * sF2 + dF2);
     o.dP = -dG1 + rp * s.b * (s.q * ln2 * sG2 + dG2);
+    if constexpr (SPEC) {
+      // the index derivatives of g from the table's second part, and per share
+      // dS/da = 2^(p t) (t ln2 / 2 g + dg/da), dS/dt = 2^(p t) (p ln2 g + dg/dt)
+      // while S < 1 (dp/da = 1/2); t moves by -2 / ln2 per unit of ln gamma_b,
+      // b by +-lg ln2 / 4 per unit of alpha_hi / alpha_lo, and the prefactor
+      // ratios by the host's d ln r / da and by alpha_hi - alpha_lo per unit
+      // of ln gamma_b
+      const float4* __restrict__ t2 = tab + 2 * kBpNodes;
+      const float4 a0 = t2[2 * k], e0v = t2[2 * k + 1], a1v = t2[2 * k + 2], e1v = t2[2 * k + 3];
+      const float aF1 = h00 * a0.x + h10 * e0v.x + h01 * a1v.x + h11 * e1v.x;
+      const float aG1 = h00 * a0.y + h10 * e0v.y + h01 * a1v.y + h11 * e1v.y;
+      const float aF2 = h00 * a0.z + h10 * e0v.z + h01 * a1v.z + h11 * e1v.z;
+      const float aG2 = h00 * a0.w + h10 * e0v.w + h01 * a1v.w + h11 * e1v.w;
+      const float p1 = -2.0f * s.h1, p2 = -2.0f * s.h2, dal = 4.0f * s.q;
+      const float ht = 0.5f * ln2 * tt;
+      // dg/dt = -2 dg/dlg (the t-derivatives above are per unit lg)
+      const float saF1 = sF1 < 1.0f ? a1 * (ht * gF1 + aF1) : 0.0f;
+      const float saG1 = sG1 < 1.0f ? a1 * (ht * gG1 + aG1) : 0.0f;
+      const float saF2 = sF2 < 1.0f ? a2 * (ht * gF2 + aF2) : 0.0f;
+      const float saG2 = sG2 < 1.0f ? a2 * (ht * gG2 + aG2) : 0.0f;
+      const float stF1 = sF1 < 1.0f ? a1 * (p1 * ln2 * gF1 - 2.0f * tF1) : 0.0f;
+      const float stG1 = sG1 < 1.0f ? a1 * (p1 * ln2 * gG1 - 2.0f * tG1) : 0.0f;
+      const float stF2 = sF2 < 1.0f ? a2 * (p2 * ln2 * gF2 - 2.0f * tF2) : 0.0f;
+      const float stG2 = sG2 < 1.0f ? a2 * (p2 * ln2 * gG2 - 2.0f * tG2) : 0.0f;
+      constexpr float kg = -2.0f / ln2;  // dt / d ln gamma_b
+      const float lgl = 0.25f * ln2 * s.lg;
+      const float rbI = ri * s.b, rbP = rp * s.b;
+      o.sI[0] = -saF1 + rbI * sF2 * (sa.dri1 - lgl);
+      o.sP[0] = -saG1 + rbP * sG2 * (sa.drp1 - lgl);
+      o.sI[1] = rbI * (sF2 * (sa.dri2 + lgl) + saF2);
+      o.sP[1] = rbP * (sG2 * (sa.drp2 + lgl) + saG2);
+      o.sI[2] = -kg * stF1 + rbI * (dal * sF2 + kg * stF2);
+      o.sP[2] = -kg * stG1 + rbP * (dal * sG2 + kg * stG2);
+    }
   }
   return o;
 }

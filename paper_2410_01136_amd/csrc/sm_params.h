@@ -116,6 +116,12 @@ struct FreqArgs {
   float bp_k2[kMaxFreq];
   float bp_ri[kMaxFreq];
   float bp_rp[kMaxFreq];
+  // d ln(bp_ri) / d alpha_lo, d ln(bp_ri) / d alpha_hi, and the same of bp_rp
+  // (gradient in the spectral parameters)
+  float bp_dri1[kMaxFreq];
+  float bp_dri2[kMaxFreq];
+  float bp_drp1[kMaxFreq];
+  float bp_drp2[kMaxFreq];
 };
 
 // Spectral model of the CR electrons: one power law of index theta[12], a

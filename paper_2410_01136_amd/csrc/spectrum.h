@@ -19,6 +19,10 @@
 // (F, a1), (G, a1), (F, a2), (G, a2): a cubic Hermite interpolant in t per
 // function.  Below the first node g is held constant (the leading power law,
 // next order ~ xb^(2/3) ~ 1e-8 there); above the last S = 1 to ~e^-128.
+//
+// A second part of the table, for the gradient in the indices, holds per node
+// dg/da (each function's derivative in its own index) and h d2g/da dt, laid
+// out like the first part and interpolated the same way.
 #pragma once
 
 #include <cstddef>
@@ -30,12 +34,14 @@ namespace sm {
 constexpr double kBpT0 = -40.0;                 // log2 xb of node 0
 constexpr int kBpPerOctave = 16;                // nodes per unit of t
 constexpr int kBpNodes = 47 * kBpPerOctave + 1;  // t in [-40, 7]
-constexpr size_t kBpTableBytes = (size_t)kBpNodes * 8 * sizeof(float);
+constexpr size_t kBpPartFloats = (size_t)kBpNodes * 8;  // one part: nodes x two float4
+constexpr size_t kBpTableBytes = 2 * kBpPartFloats * sizeof(float);
 // the indices the table is built for: above the pole of Eq. ji's Gamma
 // function at 1/3, and up to 6 (the FP32 powers of the kernels stay in range)
 constexpr double kBpAlphaMin = 1.0 / 3.0, kBpAlphaMax = 6.0;
 
-// Fills nodes[kBpNodes][8] = (g_F1, g_G1, g_F2, g_G2, h dg_F1/dt, ..) for
+// Fills nodes[2][kBpNodes][8]: part 0 (g_F1, g_G1, g_F2, g_G2, h dg_F1/dt, ..),
+// part 1 (dg_F1/da1, dg_G1/da1, dg_F2/da2, dg_G2/da2, h d2g_F1/da1 dt, ..) for
 // indices a1, a2.  Returns false with a message if the moments it integrates
 // do not reach their closed forms (a self-check of the quadrature).
 bool bp_build_table(double a1, double a2, float* nodes, std::string* err);

@@ -3,8 +3,11 @@
 // The lower shares S(a, xb) are integrated upward in t = log2 x from their
 // leading small-x power law: dS/dt = ln 2 x^(mu + 1) F(x) / M(mu) with M the
 // complete moment (the closed form behind Eq. ji; for G, Eq. jp), six-point
-// Gauss-Legendre per table interval.  The totals at the top of the table must
-// come out at 1: a check of F, G, the quadrature and the closed forms at once.
+// Gauss-Legendre per table interval.  Their derivatives in the index a
+// (mu = (a - 3) / 2) are integrated alongside: d/da of the integrand is the
+// integrand times (t ln 2 / 2 - d ln M / da).  The totals at the top of the
+// table must come out at 1 and their index derivatives at 0: a check of F, G,
+// the quadrature and the closed forms at once.
 #include <cmath>
 #include <vector>
 
@@ -45,6 +48,25 @@ double moment_g(double mu) {
   return std::pow(2.0, mu) * std::tgamma(0.5 * mu + 4.0 / 3.0) * std::tgamma(0.5 * mu + 2.0 / 3.0);
 }
 
+// Digamma: upward recurrence to x >= 10, then the asymptotic series
+// ln x - 1/(2x) - sum B_2k / (2k x^2k) to the x^-10 term.
+double digamma(double x) {
+  double acc = 0.0;
+  for (; x < 10.0; x += 1.0) acc -= 1.0 / x;
+  const double r = 1.0 / (x * x);
+  return acc + std::log(x) - 0.5 / x -
+         r * (1.0 / 12.0 - r * (1.0 / 120.0 - r * (1.0 / 252.0 - r * (1.0 / 240.0 - r / 132.0))));
+}
+
+// d ln M / d mu of the two complete moments
+double dlnmoment_f(double mu) {
+  return std::log(2.0) - 1.0 / (mu + 2.0) + 0.5 * digamma(0.5 * mu + 7.0 / 3.0) +
+         0.5 * digamma(0.5 * mu + 2.0 / 3.0);
+}
+double dlnmoment_g(double mu) {
+  return std::log(2.0) + 0.5 * digamma(0.5 * mu + 4.0 / 3.0) + 0.5 * digamma(0.5 * mu + 2.0 / 3.0);
+}
+
 // Gauss-Legendre abscissae and weights on [0, 1]: roots of P_n by Newton's
 // method from the usual cosine guesses.
 void gauss_legendre(int n, double* x, double* w) {
@@ -74,27 +96,34 @@ bool bp_build_table(double a1, double a2, float* nodes, std::string* err) {
   constexpr int kBelow = 16 * kBpPerOctave;  // intervals below node 0 (t from -56)
   const double h = 1.0 / kBpPerOctave;
   const double al[2] = {a1, a2};
-  double mu[2], p[2], mF[2], mG[2];
+  double mu[2], p[2], mF[2], mG[2], dF[2], dG[2];
   for (int i = 0; i < 2; ++i) {
     mu[i] = 0.5 * (al[i] - 3.0);
     p[i] = bp_power(al[i]);
     mF[i] = moment_f(mu[i]);
     mG[i] = moment_g(mu[i]);
+    dF[i] = 0.5 * dlnmoment_f(mu[i]);  // d ln M / da
+    dG[i] = 0.5 * dlnmoment_g(mu[i]);
   }
   double gx[kGl], gw[kGl];
   gauss_legendre(kGl, gx, gw);
   // start: S(t_s) from the leading power law, int_0^xs x^mu A x^(1/3) dx =
-  // xs^(mu + 1) F(xs) / p to relative O(xs^(2/3))
+  // xs^(mu + 1) F(xs) / p to relative O(xs^(2/3)); its index derivative from
+  // the same form
   const double ts = kBpT0 - kBelow * h;
   double xs = std::exp2(ts), Fs, Gs;
   synch_fg(xs, &Fs, &Gs);
-  double S[4];  // (F, a1), (G, a1), (F, a2), (G, a2)
+  double S[4], Sa[4];  // (F, a1), (G, a1), (F, a2), (G, a2) and d/da of each
   for (int i = 0; i < 2; ++i) {
     const double xm = std::pow(xs, mu[i] + 1.0);
     S[2 * i] = xm * Fs / (p[i] * mF[i]);
     S[2 * i + 1] = xm * Gs / (p[i] * mG[i]);
+    const double common = 0.5 * ts * kLn2 - 0.5 / p[i];
+    Sa[2 * i] = S[2 * i] * (common - dF[i]);
+    Sa[2 * i + 1] = S[2 * i + 1] * (common - dG[i]);
   }
-  auto rate = [&](double t, double* d) {  // dS/dt of the four shares at t
+  // dS/dt and d2S/da dt of the four shares at t
+  auto rate = [&](double t, double* d, double* da) {
     const double x = std::exp2(t);
     double F, G;
     synch_fg(x, &F, &G);
@@ -102,30 +131,43 @@ bool bp_build_table(double a1, double a2, float* nodes, std::string* err) {
       const double xm = kLn2 * std::pow(x, mu[i] + 1.0);
       d[2 * i] = xm * F / mF[i];
       d[2 * i + 1] = xm * G / mG[i];
+      da[2 * i] = d[2 * i] * (0.5 * t * kLn2 - dF[i]);
+      da[2 * i + 1] = d[2 * i + 1] * (0.5 * t * kLn2 - dG[i]);
     }
   };
+  float* part1 = nodes + kBpPartFloats;
   for (int j = -kBelow; j < kBpNodes; ++j) {
     const double t = kBpT0 + j * h;
     if (j >= 0) {
-      double d[4];
-      rate(t, d);
+      double d[4], da[4];
+      rate(t, d, da);
       float* o = nodes + (size_t)j * 8;
+      float* oa = part1 + (size_t)j * 8;
       for (int c = 0; c < 4; ++c) {
-        const double pc = p[c / 2], sc = std::exp2(-pc * t);
-        o[c] = (float)(S[c] * sc);
-        o[4 + c] = (float)(h * (d[c] - pc * kLn2 * S[c]) * sc);
+        // g = S E, E = 2^(-p t), dE/da = -(t ln2 / 2) E
+        const double pc = p[c / 2], E = std::exp2(-pc * t);
+        const double gt = (d[c] - pc * kLn2 * S[c]) * E;
+        o[c] = (float)(S[c] * E);
+        o[4 + c] = (float)(h * gt);
+        oa[c] = (float)((Sa[c] - 0.5 * t * kLn2 * S[c]) * E);
+        oa[4 + c] = (float)(h * ((da[c] - 0.5 * kLn2 * S[c] - pc * kLn2 * Sa[c]) * E -
+                                 0.5 * t * kLn2 * gt));
       }
     }
     if (j == kBpNodes - 1) break;
     for (int k = 0; k < kGl; ++k) {
-      double d[4];
-      rate(t + gx[k] * h, d);
-      for (int c = 0; c < 4; ++c) S[c] += h * gw[k] * d[c];
+      double d[4], da[4];
+      rate(t + gx[k] * h, d, da);
+      for (int c = 0; c < 4; ++c) {
+        S[c] += h * gw[k] * d[c];
+        Sa[c] += h * gw[k] * da[c];
+      }
     }
   }
-  // above the table every share is 1 to ~e^-128: the running totals must be
+  // above the table every share is 1 to ~e^-128 whatever the index: the running
+  // totals must be 1 and their index derivatives 0
   for (int c = 0; c < 4; ++c) {
-    if (!(std::fabs(S[c] - 1.0) < 1e-9)) {
+    if (!(std::fabs(S[c] - 1.0) < 1e-9) || !(std::fabs(Sa[c]) < 1e-8)) {
       if (err) *err = "broken power-law table: moment quadrature missed its closed form";
       return false;
     }

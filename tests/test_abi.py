@@ -276,7 +276,7 @@ def test_grid_alpha_checked_on_host(sm):
 
 def test_broken_spectrum_checked_on_host(sm):
     g = _geom(sm)
-    assert sm.syn_spectrum_table_bytes() == 753 * 32
+    assert sm.syn_spectrum_table_bytes() == 2 * 753 * 32  # values, then index derivatives
     # the table builder's own arguments
     for lo, hi in ((1.0 / 3.0, 3.0), (3.0, 6.5), (math.nan, 3.0)):
         assert sm.syn_spectrum_table(lo, hi, 0x1000, 1 << 20, None) == sm.SYN_EINVAL

@@ -1,7 +1,9 @@
 """Broken power-law CR spectrum on the GPU vs the FP64 oracle, through the C ABI.
 
-The kernels interpolate the moment shares from the host-built table; the
-oracle integrates them afresh at every midpoint.  Maps are held to the forward
+The kernels interpolate the moment shares (and their derivatives in the
+indices) from the host-built table; the oracle integrates them afresh at every
+midpoint and differentiates the emissivity numerically in the spectral
+parameters.  Maps are held to the forward
 tolerances of parity.py (with the FP32 term floor where the analytic disk is
 Faraday-thick, as for the power law), gradients to those of
 test_gpu_adjoint.py; every lane count and grid read path, with and without
@@ -179,13 +181,18 @@ def test_theta_gradient(sm, orc, lanes, S, te):
     rth, _, _ = cached(("theta", te), lambda: orc.adjoint(
         oracle_geom(orc, g), orc.Field(orc.MODEL16, THETA_T, te_k=te, broken=(3.4, 9.0e3)),
         dm.astype(np.float64)))
-    assert dth[12] == 0.0 and rth[12] == 0.0
-    sc = np.maximum(np.abs(THETA_T), 1e-2)
+    # 16 theta entries, then the spectrum's alpha_hi and ln gamma_b (theta[12] is
+    # its index below the break)
+    assert dth.shape == (18,) and rth.shape == (18,)
+    sc = np.concatenate([np.maximum(np.abs(THETA_T), 1e-2), [3.4, 1.0]])
     err = np.abs(dth - rth) * sc
     scale = np.abs(rth * sc).max()
-    print(f"broken theta-gradient S={S} te={te}: max scaled err / scale {err.max() / scale:.2e}",
+    print(f"broken theta-gradient S={S} te={te}: max scaled err / scale {err.max() / scale:.2e}; "
+          f"spectral (a_lo, a_hi, ln g_b) GPU {dth[[12, 16, 17]]} oracle {rth[[12, 16, 17]]}",
           flush=True)
     assert np.all(err <= 1e-3 * scale), (err / scale)
+    for k in (12, 16, 17):  # each spectral derivative on its own scale too
+        assert abs(dth[k] - rth[k]) <= 1e-3 * abs(rth[k]), (k, dth[k], rth[k])
 
 
 @pytest.mark.parametrize("S", [1, 4, 16])
@@ -211,7 +218,9 @@ def test_grid_gradient(sm, orc, lanes, S, te):
                    te_k=te, broken=I.BROKEN)
     rth, rbn, rc = cached(("grad", te), lambda: orc.adjoint(oracle_geom(orc, g), of,
                                                             dm.astype(np.float64), want_grid=True))
-    assert dth.cpu().numpy()[12] == 0.0 and rth[12] == 0.0
+    d = dth.cpu().numpy()
+    for k in (12, 16, 17):  # the spectrum's parameters
+        assert abs(d[k] - rth[k]) <= 1e-3 * abs(rth[k]), (k, d[k], rth[k])
     for a, b, lab in ((dbn.cpu().numpy().astype(np.float64), rbn, "bn"),
                       (dc.cpu().numpy().astype(np.float64), rc, "N0")):
         check_grid_gradient(a, b, f"broken grid S={S} te={te} {lab}")
