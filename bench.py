@@ -143,7 +143,8 @@ def main() -> int:
     ap.add_argument("--fit-lr", type=float, default=0.05, help="Adam step size of the grid fit [uG]")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample")
-    ap.add_argument("--only", choices=("c1", "c2", "c4", "fit", "wmap", "hmc", "ff", "sys", "copy"),
+    ap.add_argument("--only", choices=("c1", "c2", "c4", "fit", "wmap", "hmc", "ff", "sys", "shmc",
+                                       "copy"),
                     default=None,
                     help="profiling aids: 'c1' runs only the timed headline forward launches; "
                          "'c2' only the N_side 64 adjoint workloads (analytic and 128^3 grid); "
@@ -152,6 +153,7 @@ def main() -> int:
                          "(free-free, gridded index, broken spectrum); "
                          "'c4' only the surrogate (training, then its timed launches); "
                          "'sys' only the Sec. 4.1 systematics replay; "
+                         "'shmc' only the HMC over a broken spectrum's parameters; "
                          "'copy' runs one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -194,6 +196,9 @@ def main() -> int:
         return 0
     if args.only == "sys":
         bench_systematics(sm, I, np, torch, args)
+        return 0
+    if args.only == "shmc":
+        bench_spectrum_hmc(sm, I, np, torch, args)
         return 0
 
     # ---------------------------------------------------------------- C1 inputs
@@ -285,6 +290,7 @@ def main() -> int:
         out["hmc"] = bench_hmc(sm, I, np, torch, args)
         out["physics_variants"] = bench_physics_variants(sm, I, np, torch, args, field)
         out["systematics"] = bench_systematics(sm, I, np, torch, args)
+        out["spectrum_hmc"] = bench_spectrum_hmc(sm, I, np, torch, args)
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(sm, I, np, torch, args, field)
 
@@ -536,6 +542,51 @@ def bench_physics_variants(sm, I, np, torch, args, grid_field):
                           "theta_fwd_adj": round(theta_ms["free_free"] / theta_ms["plain"], 3)},
     }
     log("physics variants:", res)
+    return res
+
+
+def bench_spectrum_hmc(sm, I, np, torch, args):
+    """Inference over a CR spectrum (the purpose Sec. 2.1 gives a fuller
+    spectrum): HMC over a broken power law's (alpha_lo, alpha_hi, ln gamma_b)
+    from mock I/Q/U maps at {0.4, 1.4, 5, 15} GHz with 1% noise (N_side 16, 256
+    steps, the 16-parameter disk model), one forward + chi^2 + adjoint per chain
+    and leapfrog step, dense mass matrix from the Laplace approximation."""
+    import math
+    from paper_2410_01136_amd import hmc as H
+    g = I.geometry("C0", freqs_hz=(0.4e9, 1.4e9, 5.0e9, 15.0e9))
+    truth = np.array([I.THETA0[12], I.BROKEN[0], math.log(I.BROKEN[1])])
+    m = sm.forward(sm.geom_from(g), sm.Field(sm.FIELD_MODEL16, I.THETA0, broken=I.BROKEN))
+    m = m.cpu().numpy().astype(np.float64)
+    sigma = 0.01 * np.sqrt((m ** 2).mean(axis=-1))
+    rng = np.random.default_rng(8201)
+    target = m + rng.standard_normal(m.shape) * sigma[..., None]
+    bounds = [(2.0, 4.5), (2.0, 5.0), (math.log(1e3), math.log(1e6))]
+    post = H.SpectrumPosterior(g, I.THETA0, target, (1.0 / sigma ** 2).reshape(-1), bounds)
+    inv_mass = H.laplace_inv_mass(post, truth, np.full(3, 1e-3))
+    sd = np.sqrt(np.diag(inv_mass))
+    n_chains, n_iter, n_leap, burn = 4, 60, 5, 15
+    q0 = truth + 0.5 * sd * rng.standard_normal((n_chains, 3))
+    post(q0)  # warm-up
+    torch.cuda.synchronize()
+    e0 = post.evals
+    t0 = time.perf_counter()
+    out = H.hmc(post, q0, n_iter=n_iter, step=0.4, n_leap=n_leap, inv_mass=inv_mass, rng=rng)
+    secs = time.perf_counter() - t0
+    s = out["samples"][burn:].reshape(-1, 3)
+    names = ["alpha_lo", "alpha_hi", "ln_gamma_break"]
+    res = {
+        "workload": "HMC over a broken power-law CR spectrum (alpha_lo, alpha_hi, ln gamma_b) from "
+                    "mock I/Q/U at {0.4, 1.4, 5, 15} GHz, 1% noise, N_side 16 x 256 steps",
+        "chains": n_chains, "iterations": n_iter, "leapfrog_steps": n_leap,
+        "seconds": round(secs, 2),
+        "likelihood_gradient_evals_per_s": round((post.evals - e0) / secs, 1),
+        "acceptance": round(float(out["accept"][burn:].mean()), 3),
+        "posterior_mean": {k: float(f"{v:.6g}") for k, v in zip(names, s.mean(0))},
+        "posterior_sd": {k: float(f"{v:.3g}") for k, v in zip(names, s.std(0))},
+        "laplace_sd": {k: float(f"{v:.3g}") for k, v in zip(names, sd)},
+        "truth": {k: float(v) for k, v in zip(names, truth)},
+    }
+    log("spectrum HMC:", res)
     return res
 
 

@@ -9,6 +9,7 @@
 // table must come out at 1 and their index derivatives at 0: a check of F, G,
 // the quadrature and the closed forms at once.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "spectrum.h"
@@ -89,11 +90,45 @@ void gauss_legendre(int n, double* x, double* w) {
   }
 }
 
+constexpr int kGl = 6;
+constexpr int kBelow = 16 * kBpPerOctave;  // intervals below node 0 (t from -56)
+
+// F and G do not depend on the indices: their values at every point the
+// builder visits (the start, the nodes and the Gauss-Legendre points of each
+// interval) are computed once per process and shared by all tables.
+struct FgTable {
+  double gx[kGl], gw[kGl];
+  double fs, gs;                 // at the start, t = -56
+  std::vector<double> fn, gn;    // at the nodes
+  std::vector<double> fq, gq;    // at the quadrature points, [interval][kGl]
+};
+
+const FgTable& fg_table() {
+  static FgTable T;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const double h = 1.0 / kBpPerOctave;
+    gauss_legendre(kGl, T.gx, T.gw);
+    synch_fg(std::exp2(kBpT0 - kBelow * h), &T.fs, &T.gs);
+    const int nint = kBelow + kBpNodes - 1;
+    T.fn.resize(kBpNodes);
+    T.gn.resize(kBpNodes);
+    T.fq.resize((size_t)nint * kGl);
+    T.gq.resize((size_t)nint * kGl);
+    for (int j = 0; j < kBpNodes; ++j) synch_fg(std::exp2(kBpT0 + j * h), &T.fn[j], &T.gn[j]);
+    for (int i = 0; i < nint; ++i) {
+      const double t = kBpT0 + (i - kBelow) * h;
+      for (int k = 0; k < kGl; ++k)
+        synch_fg(std::exp2(t + T.gx[k] * h), &T.fq[(size_t)i * kGl + k], &T.gq[(size_t)i * kGl + k]);
+    }
+  });
+  return T;
+}
+
 }  // namespace
 
 bool bp_build_table(double a1, double a2, float* nodes, std::string* err) {
-  constexpr int kGl = 6;
-  constexpr int kBelow = 16 * kBpPerOctave;  // intervals below node 0 (t from -56)
+  const FgTable& T = fg_table();
   const double h = 1.0 / kBpPerOctave;
   const double al[2] = {a1, a2};
   double mu[2], p[2], mF[2], mG[2], dF[2], dG[2];
@@ -105,14 +140,11 @@ bool bp_build_table(double a1, double a2, float* nodes, std::string* err) {
     dF[i] = 0.5 * dlnmoment_f(mu[i]);  // d ln M / da
     dG[i] = 0.5 * dlnmoment_g(mu[i]);
   }
-  double gx[kGl], gw[kGl];
-  gauss_legendre(kGl, gx, gw);
   // start: S(t_s) from the leading power law, int_0^xs x^mu A x^(1/3) dx =
   // xs^(mu + 1) F(xs) / p to relative O(xs^(2/3)); its index derivative from
   // the same form
   const double ts = kBpT0 - kBelow * h;
-  double xs = std::exp2(ts), Fs, Gs;
-  synch_fg(xs, &Fs, &Gs);
+  const double xs = std::exp2(ts), Fs = T.fs, Gs = T.gs;
   double S[4], Sa[4];  // (F, a1), (G, a1), (F, a2), (G, a2) and d/da of each
   for (int i = 0; i < 2; ++i) {
     const double xm = std::pow(xs, mu[i] + 1.0);
@@ -122,11 +154,9 @@ bool bp_build_table(double a1, double a2, float* nodes, std::string* err) {
     Sa[2 * i] = S[2 * i] * (common - dF[i]);
     Sa[2 * i + 1] = S[2 * i + 1] * (common - dG[i]);
   }
-  // dS/dt and d2S/da dt of the four shares at t
-  auto rate = [&](double t, double* d, double* da) {
+  // dS/dt and d2S/da dt of the four shares at t, where F(2^t) = F, G(2^t) = G
+  auto rate = [&](double t, double F, double G, double* d, double* da) {
     const double x = std::exp2(t);
-    double F, G;
-    synch_fg(x, &F, &G);
     for (int i = 0; i < 2; ++i) {
       const double xm = kLn2 * std::pow(x, mu[i] + 1.0);
       d[2 * i] = xm * F / mF[i];
@@ -140,7 +170,7 @@ bool bp_build_table(double a1, double a2, float* nodes, std::string* err) {
     const double t = kBpT0 + j * h;
     if (j >= 0) {
       double d[4], da[4];
-      rate(t, d, da);
+      rate(t, T.fn[j], T.gn[j], d, da);
       float* o = nodes + (size_t)j * 8;
       float* oa = part1 + (size_t)j * 8;
       for (int c = 0; c < 4; ++c) {
@@ -155,12 +185,13 @@ bool bp_build_table(double a1, double a2, float* nodes, std::string* err) {
       }
     }
     if (j == kBpNodes - 1) break;
+    const size_t iq = (size_t)(j + kBelow) * kGl;
     for (int k = 0; k < kGl; ++k) {
       double d[4], da[4];
-      rate(t + gx[k] * h, d, da);
+      rate(t + T.gx[k] * h, T.fq[iq + k], T.gq[iq + k], d, da);
       for (int c = 0; c < 4; ++c) {
-        S[c] += h * gw[k] * d[c];
-        Sa[c] += h * gw[k] * da[c];
+        S[c] += h * T.gw[k] * d[c];
+        Sa[c] += h * T.gw[k] * da[c];
       }
     }
   }

@@ -87,6 +87,63 @@ class BatchPosterior:
             self.plan = ctypes.c_void_p()
 
 
+class SpectrumPosterior:
+    """U(q) = chi^2 / 2 of multi-frequency I/Q/U maps and dU/dq for the broken
+    power-law CR spectrum's parameters q = (alpha_lo, alpha_hi, ln gamma_b) --
+    the inference over CR spectra with gradient-based sampling that Sec. 2.1
+    names as the purpose of a fuller spectrum.  Flat prior inside `bounds`.
+
+    Chains are evaluated one after another (forward, chi^2, adjoint through the
+    C ABI); each evaluation rebuilds the spectrum table for its indices into
+    one device buffer (syn_spectrum_table: ~0.3 ms on the host after the
+    first).  geom: inputs.Geometry; theta: the field's 16 parameters (theta[12]
+    is replaced by alpha_lo); target: maps [n_freq][3][npix]; inv_sigma2:
+    [n_freq * 3] weights.
+    """
+
+    def __init__(self, geom, theta, target, inv_sigma2, bounds, kind: int = sm.FIELD_MODEL16):
+        self.g = sm.geom_from(geom)
+        self.theta = np.asarray(theta, dtype=np.float64).copy()
+        self.kind = int(kind)
+        self.bounds = np.asarray(bounds, dtype=np.float64)
+        self.target = torch.as_tensor(np.asarray(target, dtype=np.float32)).cuda().contiguous()
+        self.inv = np.asarray(inv_sigma2, dtype=np.float64).reshape(-1)
+        nb = int(sm.syn_spectrum_table_bytes())
+        self.table = torch.empty((nb + 3) // 4, dtype=torch.float32, device="cuda")
+        self.nb = nb
+        self.maps = torch.empty_like(self.target)
+        self.ws = sm.alloc_workspace(self.g, self._field(self.bounds.mean(axis=1)))
+        self.evals = 0
+
+    def _field(self, q):
+        th = self.theta.copy()
+        th[12] = q[0]
+        f = sm.Field(self.kind, th)
+        f.s.spectrum, f.s.alpha_hi, f.s.gamma_break = sm.SPEC_BROKEN, float(q[1]), float(np.exp(q[2]))
+        f.s.spectrum_table = self.table.data_ptr()
+        sm.check(sm.syn_spectrum_table(float(q[0]), float(q[1]), self.table.data_ptr(), self.nb,
+                                       sm._stream()), "syn_spectrum_table")
+        return f
+
+    def one(self, q):
+        f = self._field(q)
+        sm.forward(self.g, f, maps=self.maps, ws=self.ws)
+        chi2, dm = sm.chi2(self.maps, self.target, self.inv)
+        dth = sm.adjoint(self.g, f, dm, self.ws)
+        self.evals += 1
+        d = dth.cpu().numpy()
+        return 0.5 * float(chi2.cpu()[0]), 0.5 * d[[12, 16, 17]]
+
+    def __call__(self, Q: np.ndarray):
+        Q = np.atleast_2d(np.asarray(Q, dtype=np.float64))
+        U = np.full(Q.shape[0], np.inf)
+        G = np.zeros_like(Q)
+        for i, q in enumerate(Q):
+            if np.all((q >= self.bounds[:, 0]) & (q <= self.bounds[:, 1])):
+                U[i], G[i] = self.one(q)
+        return U, G
+
+
 def hmc(potential: Callable, q0: np.ndarray, n_iter: int, step: float, n_leap: int,
         inv_mass: np.ndarray, rng: np.random.Generator):
     """Hamiltonian Monte Carlo for all chains at once.
