@@ -7,8 +7,10 @@
 // cubic-gated linear unit, x S((x + 2) / 4) with S(s) = 3 s^2 - 2 s^3 on [0, 1]
 // (clamped): the shape of GELU (its gate approximates the normal CDF, slope 3/8
 // against 0.40 at 0) in six full-rate instructions, where the tanh form of GELU
-// costs an exp and a reciprocal at a quarter of the rate.  BF16 weights and
-// layer inputs, FP32 accumulation (v_mfma_f32_32x32x16_bf16), FP32 biases.
+// costs an exp and a reciprocal at a quarter of the rate.  FP16 weights,
+// biases and layer inputs, FP32 accumulation (v_mfma_f32_32x32x16_f16, the same
+// dense rate as BF16 on this chip); the bias and the gate run on packed FP16
+// pairs (v_pk_fma_f16, v_pk_mul_f16), two activations per instruction.
 //
 // Tiling.  One wavefront evaluates 64 points as two blocks of 32 (A: points
 // 0..31, B: points 32..63), both at once: each weight fragment read from LDS
@@ -31,6 +33,8 @@
 // 64 c + p, so the Faraday prefix of Eq. rm is a full-wavefront scan.
 #include <string.h>
 
+#include <cmath>
+
 #include "../../include/synmarch.h"
 #include "march_body.h"
 #include "mlp_layout.h"
@@ -38,17 +42,21 @@
 
 namespace sm {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ inline f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+__device__ inline f32x16 mfma(f16x8 a, f16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-// Cubic-gated linear unit: x S(s), s = clamp(x / 4 + 1/2, 0, 1), S = s^2 (3 - 2 s).
-__device__ inline float act_cubic(float x) {
-  const float s = __builtin_amdgcn_fmed3f(fmaf(x, 0.25f, 0.5f), 0.0f, 1.0f);
-  return x * (s * s * fmaf(-2.0f, s, 3.0f));
+// Cubic-gated linear unit on a pair of FP16 values: x S(s), s = clamp(x / 4 +
+// 1/2, 0, 1), S = s^2 (3 - 2 s); each operation rounds to FP16 (x / 4 and 2 s
+// are exact, so the fused forms round once like the separate ones).
+__device__ inline h2v act_cubic2(h2v x) {
+  h2v s = x * (h2v)(0.25f16) + (h2v)(0.5f16);
+  s = __builtin_elementwise_min(__builtin_elementwise_max(s, (h2v)(0.0f16)), (h2v)(1.0f16));
+  return x * (s * s * ((h2v)(3.0f16) - (h2v)(2.0f16) * s));
 }
 
 // sin and cos of 2 pi t in FP32: reduced to [-1/2, 1/2] turn, then the
@@ -71,25 +79,33 @@ __device__ inline void stage_weights(const void* packed, unsigned char* lds, int
 // supplies features k = 16 t + 8 h + i, i.e. sin (t = 0) and cos (t = 1) of
 // frequencies 8 h + i.
 __device__ inline void fourier_operand(const float* fq, float x, float y, float z, int h,
-                                       bf16x8* op) {
+                                       f16x8* op) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const float* b = fq + 3 * (8 * h + i);
     const float t = fmaf(b[0], x, fmaf(b[1], y, b[2] * z));
     float s, c;
     sincos_turns_f(t, &s, &c);
-    op[0][i] = (__bf16)s;
-    op[1][i] = (__bf16)c;
+    op[0][i] = (_Float16)s;
+    op[1][i] = (_Float16)c;
   }
 }
 
 // Bias + activation of a 32-row accumulator block, converted into the next
-// layer's B operands (two k-steps per row block).
-__device__ inline void activate(const f32x16& acc, const float* bias16, bf16x8* op2) {
+// layer's B operands (two k-steps per row block): the accumulator rounded to
+// FP16, the FP16 bias added, the gate applied, all on packed pairs.
+__device__ inline void activate(const f32x16& acc, const h2v* bias8, f16x8* op2) {
 #pragma unroll
   for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) op2[j][i] = (__bf16)act_cubic(acc[8 * j + i] + bias16[8 * j + i]);
+    for (int i = 0; i < 8; i += 2) {
+      h2v x;
+      x.x = (_Float16)acc[8 * j + i];
+      x.y = (_Float16)acc[8 * j + i + 1];
+      const h2v y = act_cubic2(x + bias8[(8 * j + i) / 2]);
+      op2[j][i] = y.x;
+      op2[j][i + 1] = y.y;
+    }
 }
 
 // One layer for both point blocks: X (block A) and XB (block B) in, YA and YB
@@ -98,19 +114,19 @@ __device__ inline void activate(const f32x16& acc, const float* bias16, bf16x8* 
 // fragment loads above the activation (which would need more registers than
 // two wavefronts per SIMD have).
 template <int KS>
-__device__ inline void pair_layer(const bf16x8* W, const float* bias, int lane, int h,
-                                  const bf16x8* XA, const bf16x8* XB, bf16x8* YA, bf16x8* YB) {
+__device__ inline void pair_layer(const f16x8* W, const h2v* bias, int lane, int h,
+                                  const f16x8* XA, const f16x8* XB, f16x8* YA, f16x8* YB) {
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     f32x16 a = {}, b = {};
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
-      const bf16x8 w = W[(rb * KS + t) * 64 + lane];
+      const f16x8 w = W[(rb * KS + t) * 64 + lane];
       a = mfma(w, XA[t], a);
       b = mfma(w, XB[t], b);
     }
-    activate(a, bias + (rb * 2 + h) * 16, &YA[2 * rb]);
-    activate(b, bias + (rb * 2 + h) * 16, &YB[2 * rb]);
+    activate(a, bias + (rb * 2 + h) * 8, &YA[2 * rb]);
+    activate(b, bias + (rb * 2 + h) * 8, &YB[2 * rb]);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -122,24 +138,25 @@ __device__ inline void mlp_tile(const unsigned char* lds, int lane, float xa, fl
                                 float xb, float yb, float zb, float out[5]) {
   const int h = lane >> 5;
   const float* fq = reinterpret_cast<const float*>(lds + kMlpOffFourier);
-  bf16x8 XA[8], XB[8], YA[8], YB[8];
+  f16x8 XA[8], XB[8], YA[8], YB[8];
   fourier_operand(fq, xa, ya, za, h, XA);
   fourier_operand(fq, xb, yb, zb, h, XB);
-  const float* bias = reinterpret_cast<const float*>(lds + kMlpOffBias);
-  pair_layer<2>(reinterpret_cast<const bf16x8*>(lds + kMlpOffW0), bias, lane, h, XA, XB, YA, YB);
-  pair_layer<8>(reinterpret_cast<const bf16x8*>(lds + kMlpOffW1), bias + kMlpBiasFloatsPerLayer,
-                lane, h, YA, YB, XA, XB);
-  pair_layer<8>(reinterpret_cast<const bf16x8*>(lds + kMlpOffW1 + kMlpHiddenBytes),
-                bias + 2 * kMlpBiasFloatsPerLayer, lane, h, XA, XB, YA, YB);
-  pair_layer<8>(reinterpret_cast<const bf16x8*>(lds + kMlpOffW1 + 2 * kMlpHiddenBytes),
-                bias + 3 * kMlpBiasFloatsPerLayer, lane, h, YA, YB, XA, XB);
+  const h2v* bias = reinterpret_cast<const h2v*>(lds + kMlpOffBias);  // pairs: 64 per layer
+  constexpr int kPairs = kMlpBiasPerLayer / 2;
+  pair_layer<2>(reinterpret_cast<const f16x8*>(lds + kMlpOffW0), bias, lane, h, XA, XB, YA, YB);
+  pair_layer<8>(reinterpret_cast<const f16x8*>(lds + kMlpOffW1), bias + kPairs, lane, h, YA, YB,
+                XA, XB);
+  pair_layer<8>(reinterpret_cast<const f16x8*>(lds + kMlpOffW1 + kMlpHiddenBytes),
+                bias + 2 * kPairs, lane, h, XA, XB, YA, YB);
+  pair_layer<8>(reinterpret_cast<const f16x8*>(lds + kMlpOffW1 + 2 * kMlpHiddenBytes),
+                bias + 3 * kPairs, lane, h, YA, YB, XA, XB);
   // output layer: registers 0..4 hold the 5 outputs in the lanes of the
   // block's half (see the file comment)
-  const bf16x8* W = reinterpret_cast<const bf16x8*>(lds + kMlpOffWout);
+  const f16x8* W = reinterpret_cast<const f16x8*>(lds + kMlpOffWout);
   f32x16 oa = {}, ob = {};
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
-    const bf16x8 w = W[t * 64 + lane];
+    const f16x8 w = W[t * 64 + lane];
     oa = mfma(w, XA[t], oa);
     ob = mfma(w, XB[t], ob);
   }
@@ -315,14 +332,23 @@ hipError_t launch_eval_mlp(const MlpArgs& m, int64_t n, const float* xyz, float*
 // Host-side packing.
 // ---------------------------------------------------------------------------
 
-// float -> bf16 bits, round to nearest even (NaN kept quiet).
-static uint16_t to_bf16(float f) {
+// float -> IEEE binary16 bits, round to nearest even: overflow to +-inf, NaN
+// kept quiet, subnormals rounded on the 2^-24 grid.
+static uint16_t to_f16(float f) {
   uint32_t u;
   memcpy(&u, &f, 4);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
-  const uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return (uint16_t)(u >> 16);
+  const uint32_t sign = (u >> 16) & 0x8000u, a = u & 0x7fffffffu;
+  if (a >= 0x7f800000u) return (uint16_t)(sign | (a > 0x7f800000u ? 0x7e00u : 0x7c00u));
+  if (a >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);  // 65520 and up round to inf
+  if (a < 0x38800000u) {  // below 2^-14: a multiple of 2^-24 (the product is exact)
+    float v;
+    memcpy(&v, &a, 4);
+    return (uint16_t)(sign | (uint32_t)std::nearbyint(v * 16777216.0f));
+  }
+  uint32_t h = (((a >> 23) - 112u) << 10) | ((a & 0x7fffffu) >> 13);
+  const uint32_t rem = a & 0x1fffu;
+  if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ++h;  // a carry into the exponent is right
+  return (uint16_t)(sign | h);
 }
 
 // Input feature held in element i of the B operand of k-step t by lane half h,
@@ -357,7 +383,7 @@ syn_status syn_mlp_pack(const float* fourier, const float* w_in, const float* b_
       for (int l = 0; l < 64; ++l)
         for (int i = 0; i < 8; ++i) {
           const int mrow = 32 * rb + (l % 32), k = 16 * t + 8 * (l / 32) + i;
-          W0[(((rb * 2 + t) * 64) + l) * 8 + i] = to_bf16(w_in[mrow * 32 + k]);
+          W0[(((rb * 2 + t) * 64) + l) * 8 + i] = to_f16(w_in[mrow * 32 + k]);
         }
   // hidden layers: A[m][k] = W[m][feature(k)]
   for (int layer = 0; layer < 3; ++layer) {
@@ -369,7 +395,7 @@ syn_status syn_mlp_pack(const float* fourier, const float* w_in, const float* b_
           for (int i = 0; i < 8; ++i) {
             const int mrow = 32 * rb + (l % 32);
             W[(((rb * 8 + t) * 64) + l) * 8 + i] =
-                to_bf16(src[mrow * 128 + mlp_feature_of_k(t, l / 32, i)]);
+                to_f16(src[mrow * 128 + mlp_feature_of_k(t, l / 32, i)]);
           }
   }
   // output layer: outputs 0..4 at rows {0,1,2,3,8} and again at {4,5,6,7,12}
@@ -383,16 +409,16 @@ syn_status syn_mlp_pack(const float* fourier, const float* w_in, const float* b_
         for (int k = 0; k < 5; ++k)
           if (rowA[k] == mrow || rowB[k] == mrow) o = k;
         const float v = o >= 0 ? w_out[o * 128 + mlp_feature_of_k(t, l / 32, i)] : 0.0f;
-        WO[((t * 64) + l) * 8 + i] = to_bf16(v);
+        WO[((t * 64) + l) * 8 + i] = to_f16(v);
       }
   // biases in accumulator order: [layer][rb][h][r]
-  float* bias = reinterpret_cast<float*>(P + kMlpOffBias);
+  uint16_t* bias = reinterpret_cast<uint16_t*>(P + kMlpOffBias);
   for (int layer = 0; layer < 4; ++layer) {
     const float* bsrc = layer == 0 ? b_in : b_h + (layer - 1) * 128;
     for (int rb = 0; rb < 4; ++rb)
       for (int h = 0; h < 2; ++h)
         for (int r = 0; r < 16; ++r)
-          bias[layer * kMlpBiasFloatsPerLayer + (rb * 2 + h) * 16 + r] = bsrc[32 * rb + acc_row(r, h)];
+          bias[layer * kMlpBiasPerLayer + (rb * 2 + h) * 16 + r] = to_f16(bsrc[32 * rb + acc_row(r, h)]);
   }
   float* bo = reinterpret_cast<float*>(P + kMlpOffBout);
   for (int k = 0; k < 5; ++k) bo[k] = b_out[k];

@@ -9,13 +9,13 @@ act_cubic), and a linear output.  It is trained in PyTorch on points sampled uni
 targets are the gridded fields evaluated by the library itself (trilinear
 interpolation on the GPU), with a mean-squared loss on standardised outputs.
 
-For inference the weights are rounded to BF16 and packed by syn_mlp_pack for
-the fused MFMA march kernel.  The plain evaluator (the field the surrogate
+For inference the weights and biases are rounded to FP16 and packed by
+syn_mlp_pack for the fused MFMA march kernel, which evaluates the gate in FP16.  The plain evaluator (the field the surrogate
 stands in for) judges its map error and is the fallback: `judge` marches a
 probe geometry with both and keeps the surrogate only within stated error
-bounds.  `reference_eval` repeats that BF16 computation
-in plain PyTorch FP32 (BF16-rounded weights and layer inputs, FP32 sums) as
-the check of the kernel.
+bounds.  `reference_eval` repeats that FP16 computation in plain PyTorch
+(FP16-rounded weights and layer inputs, FP32 sums, the bias and gate in FP16)
+as the check of the kernel.
 """
 from __future__ import annotations
 
@@ -38,6 +38,15 @@ def act_cubic(x: torch.Tensor) -> torch.Tensor:
     trained and evaluated with it."""
     s = torch.clamp(x * 0.25 + 0.5, 0.0, 1.0)
     return x * (s * s * (3.0 - 2.0 * s))
+
+
+def layer_f16(acc: torch.Tensor, bias: torch.Tensor) -> torch.Tensor:
+    """The kernel's bias and activation: the FP32 accumulator rounded to FP16,
+    the FP16 bias added and the gate applied in FP16 arithmetic (every
+    operation rounded to FP16); returned as FP32 values."""
+    x = acc.to(torch.float16) + bias.to(torch.float16)
+    s = torch.clamp(x * 0.25 + 0.5, 0.0, 1.0)
+    return (x * (s * s * (3.0 - 2.0 * s))).to(torch.float32)
 
 
 class CubicGate(nn.Module):
@@ -118,14 +127,14 @@ def mlp_field(model: FieldMLP, packed: torch.Tensor, alpha: float = 3.0) -> sm.F
     return sm.Field(sm.FIELD_MLP, th, lo=model.lo.tolist(), hi=model.hi.tolist(), mlp=packed)
 
 
-def _bf16(t: torch.Tensor) -> torch.Tensor:
-    return t.to(torch.bfloat16).to(torch.float32)
+def _f16(t: torch.Tensor) -> torch.Tensor:
+    return t.to(torch.float16).to(torch.float32)
 
 
 @torch.no_grad()
 def reference_eval(model: FieldMLP, r: torch.Tensor) -> torch.Tensor:
-    """The kernel's arithmetic in plain PyTorch: BF16-rounded weights and layer
-    inputs, FP32 sums and biases, the cubic gate; returns (B_x, B_y, B_z, n_e, N0)."""
+    """The kernel's arithmetic in plain PyTorch: FP16-rounded weights and layer
+    inputs, FP32 sums, bias and cubic gate in FP16; returns (B_x, B_y, B_z, n_e, N0)."""
     e = model.export()
     dev = r.device
     T = lambda a: torch.from_numpy(a).to(dev)
@@ -134,9 +143,10 @@ def reference_eval(model: FieldMLP, r: torch.Tensor) -> torch.Tensor:
     h = torch.cat([torch.sin(2 * math.pi * t), torch.cos(2 * math.pi * t)], dim=-1)
     ws = [T(e["w_in"])] + [T(w) for w in e["w_h"]]
     bs = [T(e["b_in"])] + [T(b) for b in e["b_h"]]
+    h = _f16(h)
     for w, b in zip(ws, bs):
-        h = act_cubic(_bf16(h) @ _bf16(w).T + b)
-    o = _bf16(h) @ _bf16(T(e["w_out"])).T + T(e["b_out"])
+        h = layer_f16(h @ _f16(w).T, b)
+    o = h @ _f16(T(e["w_out"])).T + T(e["b_out"])
     return torch.cat([o[:, :3], torch.exp(o[:, 3:5])], dim=-1)
 
 

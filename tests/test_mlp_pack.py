@@ -1,7 +1,7 @@
 """The packed layout of the MLP surrogate, checked on the CPU.
 
 The packer (C ABI, syn_mlp_pack) stores each layer as the A-operand fragments
-of v_mfma_f32_32x32x16_bf16 with the input features permuted into the order in
+of v_mfma_f32_32x32x16_f16 with the input features permuted into the order in
 which the previous layer's accumulator rows sit in the lanes.  This test
 undoes the packing with the hardware operand layout (lane l, element i of a
 k-step t holds row l % 32 and column 16 t + 8 (l // 32) + i; accumulator
@@ -21,8 +21,8 @@ def S():
     return surrogate
 
 
-def bf16_bits_to_f32(u16):
-    return (u16.astype(np.uint32) << 16).view(np.float32)
+def f16_bits_to_f32(u16):
+    return u16.view(np.float16).astype(np.float32)
 
 
 OFF_FOURIER, OFF_W0 = 0, 256
@@ -31,7 +31,7 @@ HID_BYTES = 4 * 8 * 64 * 8 * 2
 OFF_W1 = OFF_W0 + W0_BYTES
 OFF_WOUT = OFF_W1 + 3 * HID_BYTES
 OFF_BIAS = OFF_WOUT + 8 * 64 * 8 * 2
-OFF_BOUT = OFF_BIAS + 4 * 128 * 4
+OFF_BOUT = OFF_BIAS + 4 * 128 * 2
 
 
 def acc_row(r, h):
@@ -40,7 +40,7 @@ def acc_row(r, h):
 
 def unpack_layer(P, off, n_rb, n_t):
     """A matrix [32 n_rb][16 n_t] as seen by the matrix unit (column order = k)."""
-    frag = bf16_bits_to_f32(np.frombuffer(P, dtype=np.uint16, count=n_rb * n_t * 64 * 8,
+    frag = f16_bits_to_f32(np.frombuffer(P, dtype=np.uint16, count=n_rb * n_t * 64 * 8,
                                           offset=off)).reshape(n_rb, n_t, 64, 8)
     A = np.zeros((32 * n_rb, 16 * n_t), dtype=np.float64)
     for rb in range(n_rb):
@@ -70,16 +70,18 @@ def test_packed_network_matches_model(S):
     A0 = unpack_layer(P, OFF_W0, 4, 2)
     Ah = [unpack_layer(P, OFF_W1 + j * HID_BYTES, 4, 8) for j in range(3)]
     Ao = unpack_layer(P, OFF_WOUT, 1, 8)
-    bias = np.frombuffer(P, dtype=np.float32, count=4 * 128, offset=OFF_BIAS).reshape(4, 4, 2, 16)
+    bias = np.frombuffer(P, dtype=np.float16, count=4 * 128, offset=OFF_BIAS).reshape(4, 4, 2, 16)
     bout = np.frombuffer(P, dtype=np.float32, count=5, offset=OFF_BOUT)
     # biases in accumulator order
     e = model.export()
+    # the packer rounds to FP16 as numpy does (round to nearest even)
+    np.testing.assert_array_equal(A0, e["w_in"].astype(np.float16).astype(np.float64))
     for layer in range(4):
         b = e["b_in"] if layer == 0 else e["b_h"][layer - 1]
         for rb in range(4):
             for h in range(2):
                 for r in range(16):
-                    assert bias[layer, rb, h, r] == np.float32(b[32 * rb + acc_row(r, h)])
+                    assert bias[layer, rb, h, r] == np.float16(b[32 * rb + acc_row(r, h)])
     # run 200 points through the unpacked matrices (feature order = k order)
     rng = np.random.default_rng(3)
     r = rng.uniform(I.BOX_LO, I.BOX_HI, size=(200, 3))
@@ -89,18 +91,20 @@ def test_packed_network_matches_model(S):
     xt = 2.0 * (rt - model.lo) / (model.hi - model.lo) - 1.0
     tt = xt @ torch.from_numpy(fq).T
     feats = torch.cat([torch.sin(2 * math.pi * tt), torch.cos(2 * math.pi * tt)], 1).numpy()
-    bf = lambda a: torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
-    act = lambda v: S.act_cubic(torch.from_numpy(v)).numpy()
-    h = act(bf(feats) @ A0.T + e["b_in"])  # layer 0 columns are in natural feature order
+    f16 = lambda a: a.astype(np.float16).astype(np.float64)
+    # the kernel's bias and gate in FP16 (acc rounded, FP16 bias added, FP16 ops)
+    act = lambda acc, b: S.layer_f16(torch.from_numpy(acc.astype(np.float32)),
+                                     torch.from_numpy(b.astype(np.float32))).numpy().astype(np.float64)
+    h = act(f16(feats) @ A0.T, e["b_in"])  # layer 0 columns are in natural feature order
     perm = np.array([feature_of_k(k) for k in range(128)])
     for j in range(3):
-        h = act(bf(h[:, perm]) @ Ah[j].T + e["b_h"][j])
-    o = bf(h[:, perm]) @ Ao.T  # 32 rows: outputs at {0,1,2,3,8} and {4,5,6,7,12}
+        h = act(h[:, perm] @ Ah[j].T, e["b_h"][j])
+    o = h[:, perm] @ Ao.T  # 32 rows: outputs at {0,1,2,3,8} and {4,5,6,7,12}
     for rows in ([0, 1, 2, 3, 8], [4, 5, 6, 7, 12]):
         out = o[:, rows] + bout
         ref = S.reference_eval(model, torch.from_numpy(r).float()).numpy()
         ref_raw = np.concatenate([ref[:, :3], np.log(ref[:, 3:5])], 1)
-        # BF16 rounding-boundary flips stay at the 1e-3 level; a misplaced weight or
+        # FP16 rounding-boundary flips stay at the 1e-3 level; a misplaced weight or
         # permutation would give errors of the order of the outputs themselves
         err = np.abs(out - ref_raw)
         assert np.all(err <= 5e-3 * np.abs(ref_raw).max(0)), err.max(0)
@@ -110,7 +114,7 @@ def test_packed_network_matches_model(S):
     assert np.all(Ao[others] == 0)
 
 
-def test_bf16_reference_close_to_fp32_model(S):
+def test_f16_reference_close_to_fp32_model(S):
     model = S.FieldMLP(I.BOX_LO, I.BOX_HI, seed=12)
     r = torch.from_numpy(np.random.default_rng(4).uniform(I.BOX_LO, I.BOX_HI, (500, 3))).float()
     ref = S.reference_eval(model, r)
