@@ -2,15 +2,16 @@
 // fused into the sightline march.
 //
 // Network: x^ = 2 (r - lo) / (hi - lo) - 1; 32 Fourier features sin(2 pi b_f.x^),
-// cos(2 pi b_f.x^) (f < 16); 4 hidden layers of width 128 with tanh-form GELU;
+// cos(2 pi b_f.x^) (f < 16); 4 hidden layers of width 128 with a GELU-shaped gate;
 // a linear output of 5 = (Bx, By, Bz [uG], ln n_e, ln N0).  The activation is a
 // cubic-gated linear unit, x S((x + 2) / 4) with S(s) = 3 s^2 - 2 s^3 on [0, 1]
 // (clamped): the shape of GELU (its gate approximates the normal CDF, slope 3/8
 // against 0.40 at 0) in six full-rate instructions, where the tanh form of GELU
-// costs an exp and a reciprocal at a quarter of the rate.  FP16 weights,
-// biases and layer inputs, FP32 accumulation (v_mfma_f32_32x32x16_f16, the same
-// dense rate as BF16 on this chip); the bias and the gate run on packed FP16
-// pairs (v_pk_fma_f16, v_pk_mul_f16), two activations per instruction.
+// costs an exp and a reciprocal at a quarter of the rate.  FP16 weights and
+// layer inputs, FP32 accumulation (v_mfma_f32_32x32x16_f16, the same dense rate
+// as BF16 on this chip); the FP32 bias is the addend of each row block's first
+// product, and the gate runs on packed FP16 pairs (v_pk_fma_f16,
+// v_pk_mul_f16), two activations per instruction.
 //
 // Tiling.  One wavefront evaluates 64 points as two blocks of 32 (A: points
 // 0..31, B: points 32..63), both at once: each weight fragment read from LDS
@@ -91,10 +92,10 @@ __device__ inline void fourier_operand(const float* fq, float x, float y, float 
   }
 }
 
-// Bias + activation of a 32-row accumulator block, converted into the next
-// layer's B operands (two k-steps per row block): the accumulator rounded to
-// FP16, the FP16 bias added, the gate applied, all on packed pairs.
-__device__ inline void activate(const f32x16& acc, const h2v* bias8, f16x8* op2) {
+// Activation of a 32-row accumulator block (bias included), converted into the
+// next layer's B operands (two k-steps per row block): the accumulator rounded
+// to FP16 and the gate applied on packed pairs.
+__device__ inline void activate(const f32x16& acc, f16x8* op2) {
 #pragma unroll
   for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -102,7 +103,7 @@ __device__ inline void activate(const f32x16& acc, const h2v* bias8, f16x8* op2)
       h2v x;
       x.x = (_Float16)acc[8 * j + i];
       x.y = (_Float16)acc[8 * j + i + 1];
-      const h2v y = act_cubic2(x + bias8[(8 * j + i) / 2]);
+      const h2v y = act_cubic2(x);
       op2[j][i] = y.x;
       op2[j][i + 1] = y.y;
     }
@@ -114,19 +115,22 @@ __device__ inline void activate(const f32x16& acc, const h2v* bias8, f16x8* op2)
 // fragment loads above the activation (which would need more registers than
 // two wavefronts per SIMD have).
 template <int KS>
-__device__ inline void pair_layer(const f16x8* W, const h2v* bias, int lane, int h,
+__device__ inline void pair_layer(const f16x8* W, const f32x16* bias, int lane, int h,
                                   const f16x8* XA, const f16x8* XB, f16x8* YA, f16x8* YB) {
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
-    f32x16 a = {}, b = {};
+    // the bias enters as the first product's addend (FP32, no vector instruction)
+    const f32x16 c = bias[rb * 2 + h];
+    const f16x8 w0 = W[rb * KS * 64 + lane];
+    f32x16 a = mfma(w0, XA[0], c), b = mfma(w0, XB[0], c);
 #pragma unroll
-    for (int t = 0; t < KS; ++t) {
+    for (int t = 1; t < KS; ++t) {
       const f16x8 w = W[(rb * KS + t) * 64 + lane];
       a = mfma(w, XA[t], a);
       b = mfma(w, XB[t], b);
     }
-    activate(a, bias + (rb * 2 + h) * 8, &YA[2 * rb]);
-    activate(b, bias + (rb * 2 + h) * 8, &YB[2 * rb]);
+    activate(a, &YA[2 * rb]);
+    activate(b, &YB[2 * rb]);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -141,15 +145,15 @@ __device__ inline void mlp_tile(const unsigned char* lds, int lane, float xa, fl
   f16x8 XA[8], XB[8], YA[8], YB[8];
   fourier_operand(fq, xa, ya, za, h, XA);
   fourier_operand(fq, xb, yb, zb, h, XB);
-  const h2v* bias = reinterpret_cast<const h2v*>(lds + kMlpOffBias);  // pairs: 64 per layer
-  constexpr int kPairs = kMlpBiasPerLayer / 2;
+  const f32x16* bias = reinterpret_cast<const f32x16*>(lds + kMlpOffBias);  // [layer][rb][h]
+  constexpr int kBlk = kMlpBiasPerLayer / 16;
   pair_layer<2>(reinterpret_cast<const f16x8*>(lds + kMlpOffW0), bias, lane, h, XA, XB, YA, YB);
-  pair_layer<8>(reinterpret_cast<const f16x8*>(lds + kMlpOffW1), bias + kPairs, lane, h, YA, YB,
+  pair_layer<8>(reinterpret_cast<const f16x8*>(lds + kMlpOffW1), bias + kBlk, lane, h, YA, YB,
                 XA, XB);
   pair_layer<8>(reinterpret_cast<const f16x8*>(lds + kMlpOffW1 + kMlpHiddenBytes),
-                bias + 2 * kPairs, lane, h, XA, XB, YA, YB);
+                bias + 2 * kBlk, lane, h, XA, XB, YA, YB);
   pair_layer<8>(reinterpret_cast<const f16x8*>(lds + kMlpOffW1 + 2 * kMlpHiddenBytes),
-                bias + 3 * kPairs, lane, h, YA, YB, XA, XB);
+                bias + 3 * kBlk, lane, h, YA, YB, XA, XB);
   // output layer: registers 0..4 hold the 5 outputs in the lanes of the
   // block's half (see the file comment)
   const f16x8* W = reinterpret_cast<const f16x8*>(lds + kMlpOffWout);
@@ -412,13 +416,13 @@ syn_status syn_mlp_pack(const float* fourier, const float* w_in, const float* b_
         WO[((t * 64) + l) * 8 + i] = to_f16(v);
       }
   // biases in accumulator order: [layer][rb][h][r]
-  uint16_t* bias = reinterpret_cast<uint16_t*>(P + kMlpOffBias);
+  float* bias = reinterpret_cast<float*>(P + kMlpOffBias);
   for (int layer = 0; layer < 4; ++layer) {
     const float* bsrc = layer == 0 ? b_in : b_h + (layer - 1) * 128;
     for (int rb = 0; rb < 4; ++rb)
       for (int h = 0; h < 2; ++h)
         for (int r = 0; r < 16; ++r)
-          bias[layer * kMlpBiasPerLayer + (rb * 2 + h) * 16 + r] = to_f16(bsrc[32 * rb + acc_row(r, h)]);
+          bias[layer * kMlpBiasPerLayer + (rb * 2 + h) * 16 + r] = bsrc[32 * rb + acc_row(r, h)];
   }
   float* bo = reinterpret_cast<float*>(P + kMlpOffBout);
   for (int k = 0; k < 5; ++k) bo[k] = b_out[k];

@@ -11,9 +11,9 @@ constexpr int kMlpOffW1 = kMlpOffW0 + kMlpW0Bytes;      // fp16 [layer 3][rb 4][
 constexpr int kMlpHiddenBytes = 4 * 8 * 64 * 8 * 2;     // 32 KiB per layer
 constexpr int kMlpOffWout = kMlpOffW1 + 3 * kMlpHiddenBytes;  // fp16 [t 8][lane 64][8]
 constexpr int kMlpWoutBytes = 8 * 64 * 8 * 2;           // 8 KiB
-constexpr int kMlpOffBias = kMlpOffWout + kMlpWoutBytes;  // fp16 [layer 4][rb 4][h 2][r 16]
+constexpr int kMlpOffBias = kMlpOffWout + kMlpWoutBytes;  // float [layer 4][rb 4][h 2][r 16]
 constexpr int kMlpBiasPerLayer = 4 * 2 * 16;
-constexpr int kMlpOffBout = kMlpOffBias + 4 * kMlpBiasPerLayer * 2;  // float [5] (+pad)
+constexpr int kMlpOffBout = kMlpOffBias + 4 * kMlpBiasPerLayer * 4;  // float [5] (+pad)
 constexpr int kMlpBytes = kMlpOffBout + 64;
 
 static_assert(kMlpBytes % 16 == 0, "packed MLP must be a whole number of 16-byte words");

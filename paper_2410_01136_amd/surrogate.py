@@ -9,12 +9,13 @@ act_cubic), and a linear output.  It is trained in PyTorch on points sampled uni
 targets are the gridded fields evaluated by the library itself (trilinear
 interpolation on the GPU), with a mean-squared loss on standardised outputs.
 
-For inference the weights and biases are rounded to FP16 and packed by
-syn_mlp_pack for the fused MFMA march kernel, which evaluates the gate in FP16.  The plain evaluator (the field the surrogate
+For inference the weights are rounded to FP16 and packed by syn_mlp_pack for
+the fused MFMA march kernel (FP32 biases and sums), which evaluates the gate in
+FP16.  The plain evaluator (the field the surrogate
 stands in for) judges its map error and is the fallback: `judge` marches a
 probe geometry with both and keeps the surrogate only within stated error
 bounds.  `reference_eval` repeats that FP16 computation in plain PyTorch
-(FP16-rounded weights and layer inputs, FP32 sums, the bias and gate in FP16)
+(FP16-rounded weights and layer inputs, FP32 sums and biases, the gate in FP16)
 as the check of the kernel.
 """
 from __future__ import annotations
@@ -41,10 +42,10 @@ def act_cubic(x: torch.Tensor) -> torch.Tensor:
 
 
 def layer_f16(acc: torch.Tensor, bias: torch.Tensor) -> torch.Tensor:
-    """The kernel's bias and activation: the FP32 accumulator rounded to FP16,
-    the FP16 bias added and the gate applied in FP16 arithmetic (every
-    operation rounded to FP16); returned as FP32 values."""
-    x = acc.to(torch.float16) + bias.to(torch.float16)
+    """The kernel's bias and activation: the FP32 bias added to the FP32
+    accumulator, the sum rounded to FP16 and the gate applied in FP16
+    arithmetic (every operation rounded to FP16); returned as FP32 values."""
+    x = (acc + bias.float()).to(torch.float16)
     s = torch.clamp(x * 0.25 + 0.5, 0.0, 1.0)
     return (x * (s * s * (3.0 - 2.0 * s))).to(torch.float32)
 
@@ -134,7 +135,7 @@ def _f16(t: torch.Tensor) -> torch.Tensor:
 @torch.no_grad()
 def reference_eval(model: FieldMLP, r: torch.Tensor) -> torch.Tensor:
     """The kernel's arithmetic in plain PyTorch: FP16-rounded weights and layer
-    inputs, FP32 sums, bias and cubic gate in FP16; returns (B_x, B_y, B_z, n_e, N0)."""
+    inputs, FP32 sums and biases, cubic gate in FP16; returns (B_x, B_y, B_z, n_e, N0)."""
     e = model.export()
     dev = r.device
     T = lambda a: torch.from_numpy(a).to(dev)

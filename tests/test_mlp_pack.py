@@ -31,7 +31,7 @@ HID_BYTES = 4 * 8 * 64 * 8 * 2
 OFF_W1 = OFF_W0 + W0_BYTES
 OFF_WOUT = OFF_W1 + 3 * HID_BYTES
 OFF_BIAS = OFF_WOUT + 8 * 64 * 8 * 2
-OFF_BOUT = OFF_BIAS + 4 * 128 * 2
+OFF_BOUT = OFF_BIAS + 4 * 128 * 4
 
 
 def acc_row(r, h):
@@ -70,7 +70,7 @@ def test_packed_network_matches_model(S):
     A0 = unpack_layer(P, OFF_W0, 4, 2)
     Ah = [unpack_layer(P, OFF_W1 + j * HID_BYTES, 4, 8) for j in range(3)]
     Ao = unpack_layer(P, OFF_WOUT, 1, 8)
-    bias = np.frombuffer(P, dtype=np.float16, count=4 * 128, offset=OFF_BIAS).reshape(4, 4, 2, 16)
+    bias = np.frombuffer(P, dtype=np.float32, count=4 * 128, offset=OFF_BIAS).reshape(4, 4, 2, 16)
     bout = np.frombuffer(P, dtype=np.float32, count=5, offset=OFF_BOUT)
     # biases in accumulator order
     e = model.export()
@@ -81,18 +81,18 @@ def test_packed_network_matches_model(S):
         for rb in range(4):
             for h in range(2):
                 for r in range(16):
-                    assert bias[layer, rb, h, r] == np.float16(b[32 * rb + acc_row(r, h)])
+                    assert bias[layer, rb, h, r] == np.float32(b[32 * rb + acc_row(r, h)])
     # run 200 points through the unpacked matrices (feature order = k order)
     rng = np.random.default_rng(3)
     r = rng.uniform(I.BOX_LO, I.BOX_HI, size=(200, 3))
     # features exactly as the reference computes them (FP32), so both start from
-    # identical BF16 inputs; later layers differ only by summation order
+    # identical FP16 inputs; later layers differ only by summation order
     rt = torch.from_numpy(r).float()
     xt = 2.0 * (rt - model.lo) / (model.hi - model.lo) - 1.0
     tt = xt @ torch.from_numpy(fq).T
     feats = torch.cat([torch.sin(2 * math.pi * tt), torch.cos(2 * math.pi * tt)], 1).numpy()
     f16 = lambda a: a.astype(np.float16).astype(np.float64)
-    # the kernel's bias and gate in FP16 (acc rounded, FP16 bias added, FP16 ops)
+    # the kernel's bias and gate (FP32 bias in the sum, rounded to FP16, FP16 gate)
     act = lambda acc, b: S.layer_f16(torch.from_numpy(acc.astype(np.float32)),
                                      torch.from_numpy(b.astype(np.float32))).numpy().astype(np.float64)
     h = act(f16(feats) @ A0.T, e["b_in"])  # layer 0 columns are in natural feature order
