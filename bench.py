@@ -34,7 +34,7 @@ METRIC = "sightline-steps/s (pix×steps×freqs) fwd & adjoint vs plain, at state
 # v_fma_f64 (whose peak is 78.6 TFLOP/s) and reach 124 TFLOP/s at 8 wavefronts
 # per SIMD, so the kernels, built without packed FP32, are priced against it.
 PEAK_FP32_TFLOPS = 157.3
-PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense
+PEAK_F16_MFMA_TFLOPS = 2500.0  # dense FP16 (and BF16)
 PEAK_HBM_GBS = 8000.0
 # Algorithmic work per (sightline, step), counted from the method as the survey
 # of the path prices it (arithmetic operations and transcendentals, 1 each):
@@ -801,7 +801,7 @@ def bench_batched(sm, I, np, torch, tune, args):
 
 def bench_surrogate(sm, I, np, torch, args, grid_field):
     """C4: coordinate MLP trained on 1e7 points of the gridded fields, fused into the
-    march (BF16 MFMA, FP32 accumulation) at N_side 512, 1024 steps, 1 GHz; timed and
+    march (FP16 MFMA, FP32 accumulation) at N_side 512, 1024 steps, 1 GHz; timed and
     compared with the plain trilinear march of the same fields on the same GPU."""
     from paper_2410_01136_amd import surrogate as S
     tr = S.train(lambda pts: sm.eval_fields(grid_field, pts), I.BOX_LO, I.BOX_HI,
@@ -833,14 +833,14 @@ def bench_surrogate(sm, I, np, torch, args, grid_field):
     achieved = flops / (s_ev * 1e-3) / 1e12
     res = {
         "workload": "N_side 512 (3,145,728 sightlines), 1024 steps, 1 GHz, 40x40x8 kpc box; MLP 3 -> "
-                    "16 Fourier -> 4 x 128 cubic-gated linear units -> 5, BF16 weights, FP32 accumulation",
+                    "16 Fourier -> 4 x 128 cubic-gated linear units -> 5, FP16 weights, FP32 bias and accumulation",
         "train_seconds": round(tr.seconds, 1), "train_steps": tr.steps,
         "train_loss_standardised": tr.final_loss,
         "surrogate_ms": round(s_ev, 2),
         "surrogate_sightline_steps_per_s": float(f"{units / (s_ev * 1e-3):.4e}"),
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4),
-                     "traffic": None, "kernel": "sm::k_forward_mlp (v_mfma_f32_32x32x16_bf16)",
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_F16_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_F16_MFMA_TFLOPS, 4),
+                     "traffic": None, "kernel": "sm::k_forward_mlp (v_mfma_f32_32x32x16_f16)",
                      "flop_per_unit": FLOP_MLP_PER_STEP, "units_per_launch": units,
                      "launch_ms": round(s_ev, 3)},
         "plain_trilinear_ms": round(p_ev, 3),

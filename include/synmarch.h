@@ -282,9 +282,10 @@ syn_status syn_eval_fields(const syn_field* field, int64_t n, const float* xyz, 
 /* ---- coordinate-MLP surrogate of the fields ------------------------------ */
 /* Network: x^ = 2 (r - lo) / (hi - lo) - 1; features sin(2 pi b_k . x^),
    cos(2 pi b_k . x^) for 16 frequency vectors b_k; 4 hidden layers of width
-   128 with tanh-form GELU, x sigmoid(2y) with y = sqrt(2/pi)(x + 0.044715 x^3);
-   a linear output of 5 = (Bx, By, Bz [uG], ln n_e, ln N0).  Weights are BF16 with FP32 biases; products accumulate in
-   FP32 on the matrix cores.  syn_mlp_pack converts host FP32 arrays
+   128 with the cubic-gated unit x S(s), s = clamp(x / 4 + 1/2, 0, 1),
+   S = s^2 (3 - 2 s); a linear output of 5 = (Bx, By, Bz [uG], ln n_e, ln N0).
+   Weights and layer inputs are FP16, biases FP32; products accumulate in FP32
+   on the matrix cores and the gate is evaluated in FP16.  syn_mlp_pack converts host FP32 arrays
    (w_in [128][32], b_in [128], w_h [3][128][128], b_h [3][128], w_out
    [5][128], b_out [5], fourier [16][3]) into the packed device layout;
    syn_mlp_packed_bytes gives its size. */

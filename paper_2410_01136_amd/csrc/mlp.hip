@@ -22,7 +22,7 @@
 // column per 32-row block) is exactly the B operand the next layer needs, once
 // the next layer's weight columns are permuted to the order in which the rows
 // sit in the lanes -- so activations never leave the registers.  The weights
-// (118 KB packed) are staged once per workgroup in LDS; A-operand fragments
+// (117 KB packed) are staged once per workgroup in LDS; A-operand fragments
 // are read with one 16-byte LDS load each, once per 64-point tile.  A layer's
 // outputs go to a second operand buffer, so each 32-row block is activated as
 // soon as its products are done.

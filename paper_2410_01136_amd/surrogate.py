@@ -111,7 +111,7 @@ class FieldMLP(nn.Module):
 
 
 def pack(model: FieldMLP, device="cuda") -> torch.Tensor:
-    """BF16-packed weights on the device (layout of syn_mlp_pack)."""
+    """FP16-packed weights on the device (layout of syn_mlp_pack)."""
     e = model.export()
     nbytes = int(sm.syn_mlp_packed_bytes())
     host = np.zeros(nbytes, dtype=np.uint8)
