@@ -346,7 +346,8 @@ void syn_batch_destroy(syn_batch* plan);
 /* Kernel families tuned by the autotuner. */
 enum { SYN_KERNEL_FORWARD = 0, SYN_KERNEL_ADJOINT = 1, SYN_KERNEL_BATCH = 2 };
 
-/* Lanes per sightline S (1, 4, 16 or 64): consecutive steps of one sightline
+/* Lanes per sightline S (1, 4, 8, 16 or 64; the batch kernels take 1, 4, 16
+   or 64): consecutive steps of one sightline
    are spread over S lanes and their Faraday sums are combined with a
    wavefront prefix scan.  An adjoint that returns a grid gradient instead
    gives each of the S lanes a contiguous piece of ceil(n_steps / S) steps
@@ -379,7 +380,8 @@ int32_t syn_get_grid_addressing(void);
    object whose keys are
      "<device name>|<build id>|k<kernel>|f<field kind>|p<npix>|n<n_steps>|q<n_freq>"
    (with a trailing "|g" when the value carries a grid read mode) and whose
-   values are a lane count (1, 4, 16, 64) or [lane count, grid read mode 2|3].
+   values are a lane count (1, 4, 8, 16, 64; 8 not for batch entries) or
+   [lane count, grid read mode 2|3].
    Entries whose build id is not this library's (syn_build_id: a hash of the
    sources it was built from) are stale and skipped; the rest replace the
    table.  From then on a syn_forward, syn_adjoint or syn_batch_create whose

@@ -74,8 +74,8 @@ std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 64-bit, 2 buffer per l
 int default_lanes(int kernel, int kind, int64_t npix) {
   if (kernel == SYN_KERNEL_BATCH) return 1;
   if (kernel == SYN_KERNEL_ADJOINT) {
-    // grid gradients: four contiguous pieces per sightline
-    if (kind == SYN_FIELD_GRID) return 4;
+    // grid gradients: eight contiguous pieces per sightline
+    if (kind == SYN_FIELD_GRID) return 8;
     return npix < (1 << 14) ? 16 : 4;
   }
   if (npix < (1 << 14)) return 64;
@@ -823,8 +823,10 @@ syn_status syn_eval_fields(const syn_field* field, int64_t n, const float* xyz, 
 syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lanes) {
   if (kernel < 0 || kernel > 2 || field_kind < 0 || field_kind > 4)
     return fail(SYN_EINVAL, "unknown kernel family or field kind");
-  if (!(lanes == 0 || lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64))
-    return fail(SYN_EINVAL, "lanes per sightline must be 0, 1, 4, 16 or 64");
+  if (!(lanes == 0 || sm::lanes_valid(kernel, lanes)))
+    return fail(SYN_EINVAL, kernel == SYN_KERNEL_BATCH
+                                ? "lanes per sightline of the batch kernels must be 0, 1, 4, 16 or 64"
+                                : "lanes per sightline must be 0, 1, 4, 8, 16 or 64");
   g_lanes[kernel][field_kind].store(lanes);
   return SYN_OK;
 }

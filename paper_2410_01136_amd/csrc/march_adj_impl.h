@@ -220,6 +220,7 @@ static hipError_t adj_s(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& e
   switch (S) {
     case 1: return adj_mf<FF, SP, F, 1>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
     case 4: return adj_mf<FF, SP, F, 4>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
+    case 8: return adj_mf<FF, SP, F, 8>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
     case 16: return adj_mf<FF, SP, F, 16>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
     case 64: return adj_mf<FF, SP, F, 64>(g, fa, ea, f, dm, pe, ee, part, dth, gbn, gc, st);
     default: return hipErrorInvalidValue;

@@ -58,6 +58,7 @@ static hipError_t fwd_s(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& e
   switch (S) {
     case 1: return fwd_mf<FF, SP, F, 1>(g, fa, ea, f, maps, phi_end, em_end, st);
     case 4: return fwd_mf<FF, SP, F, 4>(g, fa, ea, f, maps, phi_end, em_end, st);
+    case 8: return fwd_mf<FF, SP, F, 8>(g, fa, ea, f, maps, phi_end, em_end, st);
     case 16: return fwd_mf<FF, SP, F, 16>(g, fa, ea, f, maps, phi_end, em_end, st);
     case 64: return fwd_mf<FF, SP, F, 64>(g, fa, ea, f, maps, phi_end, em_end, st);
     default: return hipErrorInvalidValue;

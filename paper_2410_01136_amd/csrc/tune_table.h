@@ -12,6 +12,9 @@ const char* build_id();
 bool tune_load(const char* path, int* kept, std::string* err);
 void tune_clear();
 int tune_entries();
+// Lane counts a kernel family launches with: 1, 4, 8, 16 or 64 lanes per
+// sightline (the batch kernels: 1, 4, 16 or 64).
+bool lanes_valid(long long kernel, long long lanes);
 // Lanes per sightline and grid read mode (0: none) tuned for this exact shape
 // on the current device, if the table holds one.
 bool tune_lookup(int kernel, int kind, long long npix, long long steps, long long freqs,

@@ -131,7 +131,6 @@ bool parse_key(const std::string& key, Entry* e, std::string* build_id, bool* gr
          e->steps >= 1 && e->freqs >= 1;
 }
 
-bool valid_lanes(long long s) { return s == 1 || s == 4 || s == 16 || s == 64; }
 
 // Name of the current device, cached per ordinal; empty without a device.
 std::string current_device_name() {
@@ -158,6 +157,11 @@ std::string current_device_name() {
 }  // namespace
 
 const char* build_id() { return SYN_BUILD_ID; }
+
+bool lanes_valid(long long kernel, long long lanes) {
+  if (lanes == 8) return kernel == 0 || kernel == 1;  // forward and reverse marches only
+  return lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64;
+}
 
 bool tune_load(const char* path, int* kept, std::string* err) {
   FILE* f = std::fopen(path, "rb");
@@ -210,14 +214,15 @@ bool tune_load(const char* path, int* kept, std::string* err) {
       *err = "tuning file: " + r.err;
       return false;
     }
-    if (!valid_lanes(lanes)) {
-      *err = "tuning file: lane count must be 1, 4, 16 or 64 (key " + key + ")";
-      return false;
-    }
     Entry e;
     bool grid_flag = false;
     if (!parse_key(key, &e, &id, &grid_flag) || grid_flag != (mode != 0)) {
       *err = "tuning file: malformed key " + key;
+      return false;
+    }
+    if (!lanes_valid(e.kernel, lanes)) {
+      *err = "tuning file: lane count must be 1, 4, 8, 16 or 64 (1, 4, 16 or 64 for the batch "
+             "kernels; key " + key + ")";
       return false;
     }
     e.lanes = (int)lanes;

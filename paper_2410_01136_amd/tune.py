@@ -23,7 +23,8 @@ import torch
 
 from . import binding as sm
 
-CANDIDATES = (1, 4, 16, 64)
+CANDIDATES = (1, 4, 8, 16, 64)  # lanes per sightline of the forward and reverse marches
+BATCH_CANDIDATES = (1, 4, 16, 64)  # the persistent many-set kernels
 # grid read modes tried for gridded forwards (syn_set_grid_addressing):
 # 2 = per-lane buffer reads, 3 = cell reads shared through LDS
 GRID_MODES = (2, 3)
@@ -53,15 +54,23 @@ def _key(kernel: int, kind: int, npix: int, n_steps: int, n_freq: int) -> str:
     return f"{dev}|{source_hash()}|k{kernel}|f{kind}|p{npix}|n{n_steps}|q{n_freq}"
 
 
-def _lane_count(v) -> bool:
-    return isinstance(v, int) and not isinstance(v, bool) and v in CANDIDATES
+def _kernel_of(key: str) -> Optional[int]:
+    for part in key.split("|"):
+        if len(part) > 1 and part[0] == "k" and part[1:].isdigit():
+            return int(part[1:])
+    return None
 
 
-def _valid(v) -> bool:
+def _lane_count(v, kernel: Optional[int]) -> bool:
+    allowed = BATCH_CANDIDATES if kernel == sm.KERNEL_BATCH else CANDIDATES
+    return isinstance(v, int) and not isinstance(v, bool) and v in allowed
+
+
+def _valid(v, kernel: Optional[int] = None) -> bool:
     # a lane count, or [lane count, grid read mode]
-    if _lane_count(v):
+    if _lane_count(v, kernel):
         return True
-    return (isinstance(v, list) and len(v) == 2 and _lane_count(v[0])
+    return (isinstance(v, list) and len(v) == 2 and _lane_count(v[0], kernel)
             and isinstance(v[1], int) and not isinstance(v[1], bool) and v[1] in GRID_MODES)
 
 
@@ -76,7 +85,7 @@ def load_cache(path: Optional[str] = None) -> Dict[str, object]:
         return {}
     if not isinstance(d, dict):
         return {}
-    return {k: v for k, v in d.items() if isinstance(k, str) and _valid(v)}
+    return {k: v for k, v in d.items() if isinstance(k, str) and _valid(v, _kernel_of(k))}
 
 
 def save_cache(d: Dict[str, int], path: Optional[str] = None) -> None:
@@ -209,7 +218,7 @@ def make_batch(thetas, nsides, geom, use_graph=True, kind=None):
     return plan
 
 
-def tune_batch(thetas, nsides, geom, target, inv_sigma2, candidates: Iterable[int] = CANDIDATES,
+def tune_batch(thetas, nsides, geom, target, inv_sigma2, candidates: Iterable[int] = BATCH_CANDIDATES,
                reps: int = 3, **kw):
     """Tunes the lane count of the persistent many-set kernels (plans are
     rebuilt per candidate, since a plan fixes its launch shape)."""

@@ -152,6 +152,13 @@ def test_chi2_checks_on_host(sm):
 def test_lane_setting(sm):
     assert sm.syn_set_lanes_per_ray(0, 0, 3) == sm.SYN_EINVAL
     assert sm.syn_set_lanes_per_ray(5, 0, 4) == sm.SYN_EINVAL
+    # 8 lanes: the forward and reverse marches only, not the batch kernels
+    assert sm.syn_set_lanes_per_ray(2, 0, 8) == sm.SYN_EINVAL
+    assert "batch kernels" in sm.syn_last_error().decode()
+    for k in (0, 1):
+        assert sm.syn_set_lanes_per_ray(k, 1, 8) == sm.SYN_OK
+        assert sm.get_lanes_per_ray(k, 1, 49152) == 8
+        assert sm.syn_set_lanes_per_ray(k, 1, 0) == sm.SYN_OK
     assert sm.syn_set_grid_addressing(4) == sm.SYN_EINVAL
     assert sm.syn_set_grid_addressing(3) == sm.SYN_OK and sm.get_grid_addressing() == 3
     assert sm.syn_set_grid_addressing(0) == sm.SYN_OK and sm.get_grid_addressing() == 0
@@ -162,7 +169,7 @@ def test_lane_setting(sm):
     assert sm.get_lanes_per_ray(0, 0, 10 ** 7) == 4
     assert sm.get_lanes_per_ray(0, 1, 786432) == 16
     assert sm.get_lanes_per_ray(0, 1, 3072) == 64
-    assert sm.get_lanes_per_ray(1, 1, 49152) == 4
+    assert sm.get_lanes_per_ray(1, 1, 49152) == 8
     assert sm.get_lanes_per_ray(1, 0, 49152) == 4
     assert sm.get_lanes_per_ray(2, 0, 10 ** 7) == 1
 

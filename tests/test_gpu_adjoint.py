@@ -55,7 +55,7 @@ def assert_theta_close(got, ref, theta, label):
     assert np.all(err <= 1e-3 * scale), (label, err / scale)
 
 
-@pytest.mark.parametrize("S", [1, 4, 16, 64])
+@pytest.mark.parametrize("S", [1, 4, 8, 16, 64])
 def test_theta_gradient_model16(sm, orc, lanes, S):
     g = I.geometry("C0", nside=8, n_steps=96, freqs_hz=(0.8e9, 1.4e9))
     dm = I.cotangents((2, 3, g.npix), seed=21)
@@ -84,7 +84,7 @@ def _grid(orc, n=(17, 17, 9), with_c=True):
 
 # with a grid gradient, S > 1 splits each sightline into S contiguous pieces:
 # 83 steps leave a short last piece at S = 4 and 16, and empty pieces at 16 and 64
-@pytest.mark.parametrize("S", [1, 4, 16, 64])
+@pytest.mark.parametrize("S", [1, 4, 8, 16, 64])
 @pytest.mark.parametrize("with_c", [True, False])
 def test_grid_gradient(sm, orc, lanes, S, with_c):
     import torch

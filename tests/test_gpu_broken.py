@@ -17,7 +17,7 @@ from parity import FP32_TERMS, check_grid_gradient, compare_maps, oracle_geom
 
 pytestmark = pytest.mark.gpu
 
-LANES = [1, 4, 16, 64]
+LANES = [1, 4, 8, 16, 64]
 C0_MAX_FLOOR = 3
 THETA_T = np.array([5.0, -0.25, 0.15, 0.35, 7.0, 1.2, 2.0, 1.4, 9.0,
                     4.2e-5, 7.5, 1.1, 2.3, 0.028, 0.9, 0.02])

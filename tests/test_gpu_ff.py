@@ -49,7 +49,7 @@ def check(gpu, ref, label, floor=0.0, max_floor=0):
     assert ok, (label, rep)
 
 
-@pytest.mark.parametrize("S", [1, 4, 16, 64])
+@pytest.mark.parametrize("S", [1, 4, 8, 16, 64])
 def test_model16_dense_plasma(sm, orc, lanes, S):
     g = I.geometry("C0", nside=8, n_steps=83, freqs_hz=FREQS_FF, r_max=2.0)
     lanes(sm.FIELD_MODEL16, S)

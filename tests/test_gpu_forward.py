@@ -9,7 +9,7 @@ from parity import FP32_TERMS, compare_maps, failing_pixels, oracle_geom
 
 pytestmark = pytest.mark.gpu
 
-LANES = [1, 4, 16, 64]
+LANES = [1, 4, 8, 16, 64]
 
 
 @pytest.fixture(scope="module")

@@ -34,7 +34,7 @@ def paper_geometry(**over):
     return I.geometry("G1", **base)
 
 
-@pytest.mark.parametrize("S", [1, 4, 16, 64])
+@pytest.mark.parametrize("S", [1, 4, 8, 16, 64])
 def test_wmap_maps_match_oracle(sm, orc, lanes, S):
     import torch
     g = paper_geometry()

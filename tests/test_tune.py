@@ -40,8 +40,10 @@ def test_python_cache_reader_falls_back_on_missing_or_corrupt_files(tmp_path):
     bad.write_text(json.dumps([1, 2, 3]))
     assert tune.load_cache(str(bad)) == {}
     mixed = tmp_path / "mixed.json"
-    mixed.write_text(json.dumps({"a": 16, "b": 5, "c": [4, 3], "d": [4, 1], "e": "x", "f": True}))
-    assert tune.load_cache(str(mixed)) == {"a": 16, "c": [4, 3]}
+    mixed.write_text(json.dumps({"a": 16, "b": 5, "c": [4, 3], "d": [4, 1], "e": "x", "f": True,
+                                 "x|k0|y": 8, "x|k1|y": [8, 2], "x|k2|y": 8}))
+    # 8 lanes per sightline: forward and reverse entries only, not batch ones
+    assert tune.load_cache(str(mixed)) == {"a": 16, "c": [4, 3], "x|k0|y": 8, "x|k1|y": [8, 2]}
 
 
 def test_library_loads_entries_of_this_build_and_looks_up_exact_shapes(tmp_path):
@@ -82,6 +84,18 @@ def test_library_loader_rejects_bad_files_and_keeps_its_table(tmp_path, text, ms
         tune.load(str(p))
     assert e.value.status == sm.SYN_EINVAL and msg in str(e.value)
     assert sm.syn_autotune_entries() == 1 and lookup() == (16, 0)
+
+
+def test_eight_lanes_are_accepted_for_marches_and_refused_for_batch_entries(tmp_path):
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps({key(k=1, f=1, p=49152, n=768, q=1): 8}))
+    assert tune.load(str(p)) == 1
+    assert lookup(k=1, f=1, p=49152, n=768, q=1) == (8, 0)
+    p.write_text(json.dumps({key(k=2, f=0, p=100, n=10, q=1): 8}))
+    with pytest.raises(sm.SynError) as e:
+        tune.load(str(p))
+    assert e.value.status == sm.SYN_EINVAL and "batch" in str(e.value)
+    assert lookup(k=1, f=1, p=49152, n=768, q=1) == (8, 0)  # table unchanged
 
 
 def test_grid_flag_and_value_shape_must_agree(tmp_path):
