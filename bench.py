@@ -906,6 +906,10 @@ def cpu_baseline_leg(sm, I, np, torch, g, noise, geom, seconds):
         "cores": 1,
         "sample": f"the first {n1} pixels of the sample above, {dt1:.1f} s",
     }
+    # context only: the paper's GPU-vs-CPU figure is a ratio of minimum ESS/s of
+    # its 4-parameter WMAP inference (NUTS), A100 against a 128-thread EPYC 7763
+    cpu["paper_context"] = "the paper's ~20x GPU (A100) vs CPU (EPYC 7763, 128 threads) speed-up " \
+                           "in minimum ESS/s of its WMAP inference; not the same measurement"
     log("cpu baseline:", cpu)
     # GPU on the same (oracle-built) grids, compared on the sampled pixels
     f = sm.grid(I.THETA0, torch.from_numpy(bn).cuda(), torch.from_numpy(reg_c).cuda(), I.BOX_LO,
