@@ -83,7 +83,7 @@ def _grid(orc, n=(17, 17, 9), with_c=True):
 
 
 # with a grid gradient, S > 1 splits each sightline into S contiguous pieces:
-# 83 steps leave a short last piece at S = 4 and 16, and empty pieces at 16 and 64
+# 83 steps leave a short last piece at S = 4, 8 and 16, and empty pieces at 16 and 64
 @pytest.mark.parametrize("S", [1, 4, 8, 16, 64])
 @pytest.mark.parametrize("with_c", [True, False])
 def test_grid_gradient(sm, orc, lanes, S, with_c):
