@@ -1,8 +1,10 @@
 """Launch-shape autotuner for the march kernels.
 
-The tunables are S, the number of lanes that share a sightline (1, 4, 16 or
-64): larger S gives more parallelism for small maps (few sightlines), smaller
-S fewer scan instructions and more register reuse for large maps; and, for
+The tunables are S, the number of lanes that share a sightline (1, 4, 8, 16
+or 64; the batch kernels 1, 4, 16 or 64): larger S gives more parallelism for
+small maps (few sightlines) and, for the grid adjoint, a wavefront count that
+fills the chip in whole rounds; smaller S fewer scan instructions and more
+register reuse for large maps; and, for
 gridded forwards, the grid read path (per-lane buffer reads or cells shared
 through LDS).  The tuner times each candidate with HIP events on the workload
 at hand and applies the fastest through syn_set_lanes_per_ray.  Results are
