@@ -131,7 +131,6 @@ bool parse_key(const std::string& key, Entry* e, std::string* build_id, bool* gr
          e->steps >= 1 && e->freqs >= 1;
 }
 
-
 // Name of the current device, cached per ordinal; empty without a device.
 std::string current_device_name() {
   static std::mutex mu;
