@@ -195,7 +195,12 @@ syn_status syn_spectrum_table_host(double alpha_lo, double alpha_hi, float* tabl
 /* Bytes of workspace syn_forward needs; with_adjoint != 0 adds what the
    matching syn_adjoint reads (the Faraday sum of every sightline, 8 B per
    pixel, with free-free also its emission measure, 8 B per pixel, plus
-   per-block gradient partials).  Returns 0 for invalid input. */
+   per-block gradient partials) and, for fields with a reverse pass (GRID,
+   MODEL16, WMAP), the piece snapshots: the running sums the forward leaves at
+   the ends of the reverse pass's S contiguous pieces per sightline (S its lane
+   count; 1 + 2 n_freq doubles, with free-free 2 + 4 n_freq, per piece end and
+   pixel), from which the reverse pass starts each piece.  Returns 0 for
+   invalid input. */
 size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t with_adjoint);
 
 /* Forward march: maps (device) float [n_freq][3][npix] in K.  ws (device) may
@@ -349,10 +354,10 @@ enum { SYN_KERNEL_FORWARD = 0, SYN_KERNEL_ADJOINT = 1, SYN_KERNEL_BATCH = 2 };
 /* Lanes per sightline S (1, 4, 8, 16 or 64; the batch kernels take 1, 4, 16
    or 64): consecutive steps of one sightline
    are spread over S lanes and their Faraday sums are combined with a
-   wavefront prefix scan.  An adjoint that returns a grid gradient instead
-   gives each of the S lanes a contiguous piece of ceil(n_steps / S) steps
-   (the pieces are joined by group scans of their Faraday sums and phase
-   cotangents).  0 restores the built-in choice.  Applies to the given
+   wavefront prefix scan.  The adjoint instead gives each of the S lanes a
+   contiguous piece of ceil(n_steps / S) steps (the pieces are joined by
+   group scans of their Faraday sums and phase cotangents); when the forward
+   stored piece snapshots for S pieces, syn_adjoint uses that S.  0 restores the built-in choice.  Applies to the given
    (kernel, field kind) pair on the calling process. */
 syn_status syn_set_lanes_per_ray(int32_t kernel, int32_t field_kind, int32_t lanes);
 int32_t syn_get_lanes_per_ray(int32_t kernel, int32_t field_kind, int64_t npix);

@@ -74,9 +74,11 @@ std::atomic<int> g_grid_addressing{0};  // 0 automatic, 1 64-bit, 2 buffer per l
 int default_lanes(int kernel, int kind, int64_t npix) {
   if (kernel == SYN_KERNEL_BATCH) return 1;
   if (kernel == SYN_KERNEL_ADJOINT) {
-    // grid gradients: eight contiguous pieces per sightline
+    // contiguous pieces per sightline: eight (the fastest for both reverse
+    // passes at N_side 64; with a grid gradient its wavefronts then fill the
+    // chip in whole rounds), or sixteen for small maps
     if (kind == SYN_FIELD_GRID) return 8;
-    return npix < (1 << 14) ? 16 : 4;
+    return npix < (1 << 14) ? 16 : 8;
   }
   if (npix < (1 << 14)) return 64;
   // gridded fields share cell reads across the 16 steps of a sightline chunk
@@ -460,12 +462,30 @@ size_t ws_bytes_for(int64_t npix, bool adjoint, bool ff, bool bp) {
          (size_t)sm::march_blocks(npix, 64) * (sm::kNParam + (bp ? 2 : 0)) * sizeof(double);
 }
 
-// Piece snapshots for a grid-gradient reverse pass of `pieces` pieces (see
-// GridArgs): quantities per piece end, and their bytes (0 when there are no
-// pieces or they would take more than kMaxSnapBytes; the reverse pass then
-// recomputes its pieces' sums itself).
+// Piece snapshots for a reverse pass of `pieces` pieces (see GridArgs):
+// quantities per piece end, and their bytes (0 when there are no pieces or they
+// would take more than kMaxSnapBytes; the reverse pass then recomputes its
+// pieces' sums itself).  Grid, spiral-disk and WMAP fields have reverse passes.
 constexpr size_t kMaxSnapBytes = (size_t)1 << 31;
 int snap_quantities(int n_freq, bool ff) { return 1 + 2 * n_freq + (ff ? 1 + 2 * n_freq : 0); }
+
+bool has_snapshots(int kind) {
+  return kind == SYN_FIELD_GRID || kind == SYN_FIELD_MODEL16 || kind == SYN_FIELD_WMAP;
+}
+
+// Points the field's argument block at the snapshots (nullptr: none).
+void set_snapshots(sm::FieldPack* fp, int kind, double* snap, int pieces, int n_steps, int nq) {
+  const int len = pieces > 0 ? (n_steps + pieces - 1) / pieces : 0;
+  auto put = [&](auto& a) {
+    a.snap = snap;
+    a.pieces = pieces;
+    a.piece_len = len;
+    a.snap_nq = nq;
+  };
+  if (kind == SYN_FIELD_GRID) put(fp->grid);
+  if (kind == SYN_FIELD_MODEL16) put(fp->m16);
+  if (kind == SYN_FIELD_WMAP) put(fp->wmap);
+}
 
 size_t snap_bytes(int64_t npix, int pieces, int n_freq, bool ff) {
   if (pieces < 2) return 0;
@@ -592,7 +612,7 @@ size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t
   if (check_field(field, &fp, false) != SYN_OK) return 0;
   if (with_adjoint == 0) return 0;
   size_t b = ws_bytes_for(ga.npix, true, fp.ff, fp.spec == sm::kSpecBroken);
-  if (field->kind == SYN_FIELD_GRID) {
+  if (has_snapshots(field->kind)) {
     int tm = 0;
     const int pieces = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps,
                                        geom->n_freq, &tm);
@@ -635,24 +655,22 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
   if (maps == nullptr || ((uintptr_t)maps & 3) != 0) return fail(SYN_EINVAL, "maps must be a 4-byte aligned device pointer");
   double* phi_end = nullptr;
   double* em_end = nullptr;
-  int pieces = 0;  // snapshots stored for a grid-gradient reverse pass of this many pieces
+  int pieces = 0;  // snapshots stored for a reverse pass of this many pieces
   if (ws != nullptr) {
     const size_t base = ws_bytes_for(ga.npix, true, fp.ff, fp.spec == sm::kSpecBroken);
     if (ws_bytes < base || ((uintptr_t)ws & 7) != 0)
       return fail(SYN_EWORKSPACE, "workspace smaller than syn_workspace_bytes(...,1) or misaligned");
     phi_end = static_cast<double*>(ws);
     if (fp.ff) em_end = reinterpret_cast<double*>(static_cast<char*>(ws) + ws_phi_bytes(ga.npix));
-    if (field->kind == SYN_FIELD_GRID) {
+    if (has_snapshots(field->kind)) {
       int tm = 0;
       const int p = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps,
                                     geom->n_freq, &tm);
       const size_t sb = snap_bytes(ga.npix, p, geom->n_freq, fp.ff);
       if (sb > 0 && ws_bytes >= base + sb) {
         pieces = p;
-        fp.grid.snap = reinterpret_cast<double*>(static_cast<char*>(ws) + base);
-        fp.grid.pieces = p;
-        fp.grid.piece_len = (ga.n_steps + p - 1) / p;
-        fp.grid.snap_nq = snap_quantities(geom->n_freq, fp.ff);
+        set_snapshots(&fp, field->kind, reinterpret_cast<double*>(static_cast<char*>(ws) + base), p,
+                      ga.n_steps, snap_quantities(geom->n_freq, fp.ff));
       }
     }
   }
@@ -729,14 +747,13 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   double* phi_end = reinterpret_cast<double*>(w);
   double* em_end = fp.ff ? reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix)) : nullptr;
   double* partials = reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix) * (fp.ff ? 2 : 1));
-  if (pieces >= 2 && (dgrid_bn != nullptr || dgrid_c != nullptr)) {
+  if (pieces >= 2 && has_snapshots(field->kind)) {
     // the forward stored the sums at the ends of `pieces` pieces: split the
     // sightlines the same way and skip the pre-pass over each piece
     S = pieces;
-    fp.grid.snap = reinterpret_cast<double*>(w + ws_bytes_for(ga.npix, true, fp.ff, bp));
-    fp.grid.pieces = pieces;
-    fp.grid.piece_len = (ga.n_steps + pieces - 1) / pieces;
-    fp.grid.snap_nq = snap_quantities(geom->n_freq, fp.ff);
+    set_snapshots(&fp, field->kind,
+                  reinterpret_cast<double*>(w + ws_bytes_for(ga.npix, true, fp.ff, bp)), pieces,
+                  ga.n_steps, snap_quantities(geom->n_freq, fp.ff));
   }
   hipError_t e = sm::launch_adjoint(ga, fa, ea, fp, S, dmaps, phi_end, em_end, partials, dtheta,
                                     dgrid_bn, dgrid_c, stream);

@@ -105,7 +105,9 @@ __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitAr
     box = workgroup_box(g, fld, q, lds_dyn, box_cap);
     stage = lds_dyn + 5 * box_cap + (threadIdx.x >> 6) * (kStageRecs * kStageFloats);
   }
-  adj_lane<F, S, MF, THETA, GRID, FF, SP>(g, fa, ea, fld, q, sub, valid, dmaps,
+  // a theta-only pass walks contiguous pieces too (from the forward's piece
+  // snapshots, or a pre-pass without them)
+  adj_lane<F, S, MF, THETA, GRID, FF, SP, THETA>(g, fa, ea, fld, q, sub, valid, dmaps,
                                           MapAddr{g.npix, 0}, phi_end, tb, gbn, gc, &box, stage,
                                           em_end);
   if constexpr (GRID) {

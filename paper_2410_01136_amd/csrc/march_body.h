@@ -62,9 +62,13 @@ constexpr bool exact_freqs(int MF) { return MF == 1 || MF == 3; }
 // multipliers of bp_mult (interpolated moment shares), so the I sum is per
 // frequency as well.
 //
-// PC (gridded fields only): also store the piece snapshots of fld.p (the
-// running sums at the piece ends of the grid-gradient reverse pass), so that
-// pass needs no pre-pass over its pieces.
+// PC (grid, spiral-disk and WMAP fields): also store the piece snapshots of
+// fld.p (the running sums at the piece ends of a reverse pass in pieces), so
+// that pass needs no pre-pass over its pieces.
+template <class F>
+constexpr bool kHasSnapshots = std::is_base_of_v<Grid, F> || std::is_base_of_v<Model16, F> ||
+                               std::is_base_of_v<Wmap, F>;
+
 template <class F, int S, int MF, bool FF = false, int SP = kSpecPower, bool PC = false, class FA>
 __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, float* __restrict__ maps,
@@ -91,6 +95,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 
   constexpr int MPC = PC ? MF : 1;
   double tq[MPC], tu[MPC], ti[PC && PF ? MF : 1], tf[PC && FF ? MF : 1];  // PC: this step's terms
+  int pc_k = 1;  // PC: the next piece end to store, k piece_len
   for (int c0 = 0; c0 < g.n_steps; c0 += S) {
     const int n = c0 + sub;
     const bool act = n < g.n_steps;
@@ -189,9 +194,10 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     if constexpr (PC) {
       // piece ends inside this chunk (those at or beyond the last step are
       // written after the loop, from the totals): sums over the steps before b
-      for (int k = c0 / fld.p.piece_len + 1;
-           k <= fld.p.pieces && k * fld.p.piece_len <= c0 + S && k * fld.p.piece_len < g.n_steps;
-           ++k) {
+      for (; pc_k <= fld.p.pieces && pc_k * fld.p.piece_len <= c0 + S &&
+             pc_k * fld.p.piece_len < g.n_steps;
+           ++pc_k) {
+        const int k = pc_k;
         const int b = k * fld.p.piece_len;
         const bool before = n < b;
         double* out = fld.p.snap + (int64_t)(k - 1) * fld.p.snap_nq * ma.stride + ma.off + ray.ring;
@@ -299,10 +305,11 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 // lane's share of dL/dtheta into tb (THETA) and scatters grid gradients
 // (GRID).  FA additionally provides dlnsI[], dlnsP[].
 //
-// With a grid gradient and S > 1 the S lanes of a sightline do not interleave
-// steps: lane k walks its own contiguous piece of ceil(N / S) steps, so that it
-// stays in one cell for as many steps as a single lane would and its register
-// accumulator flushes as rarely.  The piece needs two numbers from the pieces
+// With a grid gradient, or PIECES (the theta-only reverse pass of the march
+// kernels), and S > 1 the S lanes of a sightline do not interleave steps: lane
+// k walks its own contiguous piece of ceil(N / S) steps, so that it stays in
+// one cell for as many steps as a single lane would and its register
+// accumulator flushes as rarely, and no step needs a lane exchange.  The piece needs two numbers from the pieces
 // beyond it: the Faraday sum before its end, and the sum of the phase
 // cotangents after it.  A pre-pass over the piece gets both with one march:
 // the Faraday sum of the piece, and per frequency the sum of z_n e^{2 pi i t_n}
@@ -311,7 +318,7 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
 // into the piece's phase-cotangent total, and a suffix scan gives each piece
 // those of the pieces after it.
 template <class F, int S, int MF, bool THETA, bool GRID, bool FF = false, int SP = kSpecPower,
-          class FA>
+          bool PIECES = false, class FA>
 __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
                                 int64_t q, int sub, bool valid, const float* __restrict__ dmaps,
                                 MapAddr ma, const double* __restrict__ phi_end, double* tb,
@@ -361,7 +368,7 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
   }
   // each lane walks a contiguous run [n_lo, n_hi) of steps (one lane per
   // sightline, or one piece of it) rather than every S-th step
-  constexpr bool SPLIT = GRID && S > 1;
+  constexpr bool SPLIT = (GRID || PIECES) && S > 1;
   constexpr bool SERIAL = S == 1 || SPLIT;
   int n_lo = 0, n_hi = g.n_steps;
   double E = 0.0;     // Faraday sum over the steps before the current chunk's end

@@ -10,7 +10,7 @@
 
 namespace sm {
 
-// PC: gridded fields only, also store the piece snapshots (fld.p.snap).
+// PC: also store the piece snapshots (fld.p.snap; grid, spiral-disk and WMAP fields).
 template <class F, int S, int MF, bool FF, int SP, bool PC = false>
 __global__ __launch_bounds__(256) void k_forward(GeomArgs g, FreqArgs fa, EmitArgs ea, F fld,
                                                  float* __restrict__ maps,
@@ -42,11 +42,12 @@ static hipError_t fwd_mf_pc(const GeomArgs& g, const FreqArgs& fa, const EmitArg
   return hipGetLastError();
 }
 
-// gridded fields write piece snapshots when asked to (fld.p.snap set)
+// grid, spiral-disk and WMAP fields write piece snapshots when asked to
+// (fld.p.snap set)
 template <bool FF, int SP, class F, int S>
 static hipError_t fwd_mf(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
                          float* maps, double* phi_end, double* em_end, hipStream_t st) {
-  if constexpr (std::is_base_of_v<Grid, F>) {
+  if constexpr (kHasSnapshots<F>) {
     if (f.p.snap != nullptr) return fwd_mf_pc<FF, SP, true, F, S>(g, fa, ea, f, maps, phi_end, em_end, st);
   }
   return fwd_mf_pc<FF, SP, false, F, S>(g, fa, ea, f, maps, phi_end, em_end, st);

@@ -1408,11 +1408,25 @@ __device__ inline double group_suffix_scan(double v, int sub) {
   }
 }
 
+// Sum over the group, to every lane of it.  Within a 16-lane row by DPP: a
+// mirror pairs each lane with one of the other half (16), a half-row mirror
+// with one of the other quad (8), after which the four lanes of a quad hold
+// disjoint partial sums that two quad permutations add up.
+constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadSwap1 = 0xb1, kDppQuadSwap2 = 0x4e;  // quad_perm [1,0,3,2], [2,3,0,1]
 template <int S>
 __device__ inline double group_sum(double v) {
+  if constexpr (S == 4 || S == 8 || S == 16) {
+    if constexpr (S == 16) v += dpp_f64<kDppRowMirror>(v);
+    if constexpr (S >= 8) v += dpp_f64<kDppRowHalfMirror>(v);
+    v += dpp_f64<kDppQuadSwap1>(v);
+    v += dpp_f64<kDppQuadSwap2>(v);
+    return v;
+  } else {
 #pragma unroll
-  for (int d = S / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, S);
-  return v;
+    for (int d = S / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, S);
+    return v;
+  }
 }
 
 template <int S>

@@ -25,6 +25,10 @@ struct M16Args {
   float C0, invhr, invhz, l2_invhr, l2_invhz;
   float n0, invhne, l2_invhne, l2_kappa;
   float log2_rsun;
+  // piece snapshots of a forward that a reverse pass will follow (as in
+  // GridArgs; snap nullptr: none)
+  double* snap;
+  int32_t pieces, piece_len, snap_nq;
 };
 
 // WMAP field of Sec. 3.1 (FP32 constants derived on the host).
@@ -33,6 +37,9 @@ struct WmapArgs {
   float rin, rout;
   float C0, invhr, invhz;
   float n0, invhne, l2_invhne, l2_kappa;
+  // piece snapshots (as in GridArgs; snap nullptr: none)
+  double* snap;
+  int32_t pieces, piece_len, snap_nq;
 };
 
 struct GridArgs {
@@ -45,8 +52,8 @@ struct GridArgs {
   // strides of one y row and one z plane in the float4 grid and in the N0 grid
   uint32_t bn_bytes, c_bytes;
   uint32_t sy16, sz16, sy4, sz4;
-  // Piece snapshots of a forward that a grid-gradient reverse pass will follow
-  // (nullptr: none).  The reverse pass cuts each sightline into `pieces`
+  // Piece snapshots of a forward that a reverse pass in pieces will follow
+  // (nullptr: none).  The analytic and WMAP argument blocks carry the same.  The reverse pass cuts each sightline into `pieces`
   // contiguous pieces of `piece_len` steps; at each piece end b_k = k piece_len
   // (k = 1 .. pieces, capped at n_steps) the forward stores, per pixel, the
   // running sums over the steps before b_k: the Faraday sum, per frequency the

@@ -177,15 +177,13 @@ def tune_forward(geom, field, maps=None, ws=None, **kw):
 
 
 def tune_adjoint(geom, field, dmaps, ws, want_theta=True, dgrid_bn=None, dgrid_c=None, **kw):
-    """Tunes the reverse pass.  With a grid gradient the pass reads the sums the
-    forward stored at the ends of its pieces, laid out for the lane count in
-    force when the forward ran: each candidate then gets its own workspace and
-    forward (untimed), and the forward is rerun into `ws` for the winner."""
+    """Tunes the reverse pass.  The pass reads the sums the forward stored at the
+    ends of its pieces, laid out for the lane count in force when the forward
+    ran: each candidate gets its own workspace and forward (untimed), and the
+    forward is rerun into `ws` for the winner when `ws` has room for its
+    pieces (else the caller allocates a new workspace and reruns it)."""
     npix = 12 * geom.nside ** 2
     shape = (npix, geom.n_steps, geom.n_freq)
-    if dgrid_bn is None and dgrid_c is None:
-        return tune(sm.KERNEL_ADJOINT, field.s.kind, shape,
-                    lambda: sm.adjoint(geom, field, dmaps, ws, want_theta=want_theta), **kw)
     state = {}
 
     def prepare():

@@ -103,13 +103,28 @@ def test_grid_descriptor_rejected_on_host(sm):
     assert st == sm.SYN_EINVAL and "grid_n" in sm.syn_last_error().decode()
 
 
+def base_ws_bytes(sm, g, f):
+    """The workspace without piece snapshots (those are optional: a forward
+    without room for them stores none and the reverse pass recomputes its
+    pieces' sums): its size with a one-lane reverse pass in force."""
+    sm.set_lanes_per_ray(1, f.s.kind, 1)
+    try:
+        return sm.workspace_bytes(g, f, True)
+    finally:
+        sm.set_lanes_per_ray(1, f.s.kind, 0)
+
+
 def test_workspace_checks_on_host(sm):
     g = _geom(sm)
     f = sm.model16(I.THETA0)
     need = sm.workspace_bytes(g, f, True)
-    assert need >= 8 * 12 * 16 * 16
+    base = base_ws_bytes(sm, g, f)
+    assert need >= base >= 8 * 12 * 16 * 16
+    # the snapshots: the Faraday, Q and U sums at each piece end of every pixel
+    S = sm.get_lanes_per_ray(1, f.s.kind, 12 * g.nside ** 2)
+    assert need - base >= S * 3 * 8 * 12 * 16 * 16
     assert sm.workspace_bytes(g, f, False) == 0
-    st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, 0x2000, need - 8, None)
+    st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, 0x2000, base - 8, None)
     assert st == sm.SYN_EWORKSPACE
     st = sm.syn_adjoint(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, 0x3000, None,
                         None, None)
@@ -170,7 +185,7 @@ def test_lane_setting(sm):
     assert sm.get_lanes_per_ray(0, 1, 786432) == 16
     assert sm.get_lanes_per_ray(0, 1, 3072) == 64
     assert sm.get_lanes_per_ray(1, 1, 49152) == 8
-    assert sm.get_lanes_per_ray(1, 0, 49152) == 4
+    assert sm.get_lanes_per_ray(1, 0, 49152) == 8
     assert sm.get_lanes_per_ray(2, 0, 10 ** 7) == 1
 
 
@@ -253,7 +268,7 @@ def test_free_free_arguments_checked_on_host(sm):
         st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(f.s), 0x1000, None, 0, None)
         assert st == sm.SYN_EINVAL and "te_k" in sm.syn_last_error().decode()
     plain, ff = sm.model16(I.THETA0), sm.model16(I.THETA0).with_te(8000.0)
-    need_plain, need_ff = sm.workspace_bytes(g, plain, True), sm.workspace_bytes(g, ff, True)
+    need_plain, need_ff = base_ws_bytes(sm, g, plain), base_ws_bytes(sm, g, ff)
     assert need_ff > need_plain  # the emission-measure sums of the sightlines
     st = sm.syn_forward(sm.ctypes.byref(g), sm.ctypes.byref(ff.s), 0x1000, 0x2000, need_plain, None)
     assert st == sm.SYN_EWORKSPACE

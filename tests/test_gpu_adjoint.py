@@ -66,6 +66,25 @@ def test_theta_gradient_model16(sm, orc, lanes, S):
     assert_theta_close(got, ref, THETA_T, f"model16 S={S}")
 
 
+def test_theta_gradient_without_piece_snapshots(sm, orc, lanes):
+    # the forward ran with a one-lane reverse pass in force (no pieces, so no
+    # piece snapshots); the reverse pass then splits each sightline into 8
+    # pieces and finds their starting sums with a pre-pass of its own
+    import torch
+    g = I.geometry("C0", nside=8, n_steps=96, freqs_hz=(0.8e9, 1.4e9))
+    dm = I.cotangents((2, 3, g.npix), seed=25)
+    field = sm.model16(THETA_T)
+    geom = sm.geom_from(g)
+    lanes(sm.FIELD_MODEL16, 1)
+    ws = sm.alloc_workspace(geom, field)
+    sm.forward(geom, field, ws=ws)
+    lanes(sm.FIELD_MODEL16, 8)
+    got = sm.adjoint(geom, field, torch.from_numpy(dm).cuda(), ws).cpu().numpy()
+    ref, _, _ = orc.adjoint(oracle_geom(orc, g), orc.Field(orc.MODEL16, THETA_T),
+                            dm.astype(np.float64))
+    assert_theta_close(got, ref, THETA_T, "model16, 8 pieces without snapshots")
+
+
 def test_theta_gradient_alpha3_theta0(sm, orc):
     g = I.geometry("C2", nside=16, n_steps=128)
     dm = I.cotangents((1, 3, g.npix), seed=22)
