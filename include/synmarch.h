@@ -195,12 +195,13 @@ syn_status syn_spectrum_table_host(double alpha_lo, double alpha_hi, float* tabl
 /* Bytes of workspace syn_forward needs; with_adjoint != 0 adds what the
    matching syn_adjoint reads (the Faraday sum of every sightline, 8 B per
    pixel, with free-free also its emission measure, 8 B per pixel, plus
-   per-block gradient partials) and, for fields with a reverse pass (GRID,
-   MODEL16, WMAP), the piece snapshots: the running sums the forward leaves at
-   the ends of the reverse pass's S contiguous pieces per sightline (S its lane
-   count; 1 + 2 n_freq doubles, with free-free 2 + 4 n_freq, per piece end and
-   pixel), from which the reverse pass starts each piece.  Returns 0 for
-   invalid input. */
+   per-block gradient partials) and, for fields with a reverse pass (GRID;
+   MODEL16 and WMAP unless under a broken power law, whose theta-only reverse
+   pass interleaves steps instead), the piece snapshots: the running sums the
+   forward leaves at the ends of the reverse pass's S contiguous pieces per
+   sightline (S its lane count; 1 + 2 n_freq doubles, with free-free
+   2 + 4 n_freq, per piece end and pixel), from which the reverse pass starts
+   each piece.  Returns 0 for invalid input. */
 size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t with_adjoint);
 
 /* Forward march: maps (device) float [n_freq][3][npix] in K.  ws (device) may

@@ -469,8 +469,11 @@ size_t ws_bytes_for(int64_t npix, bool adjoint, bool ff, bool bp) {
 constexpr size_t kMaxSnapBytes = (size_t)1 << 31;
 int snap_quantities(int n_freq, bool ff) { return 1 + 2 * n_freq + (ff ? 1 + 2 * n_freq : 0); }
 
-bool has_snapshots(int kind) {
-  return kind == SYN_FIELD_GRID || kind == SYN_FIELD_MODEL16 || kind == SYN_FIELD_WMAP;
+// (a theta-only reverse pass under a broken power law interleaves steps
+// instead, so its analytic and WMAP forwards store none)
+bool has_snapshots(int kind, int spec) {
+  return kind == SYN_FIELD_GRID ||
+         ((kind == SYN_FIELD_MODEL16 || kind == SYN_FIELD_WMAP) && spec != sm::kSpecBroken);
 }
 
 // Points the field's argument block at the snapshots (nullptr: none).
@@ -612,7 +615,7 @@ size_t syn_workspace_bytes(const syn_geom* geom, const syn_field* field, int32_t
   if (check_field(field, &fp, false) != SYN_OK) return 0;
   if (with_adjoint == 0) return 0;
   size_t b = ws_bytes_for(ga.npix, true, fp.ff, fp.spec == sm::kSpecBroken);
-  if (has_snapshots(field->kind)) {
+  if (has_snapshots(field->kind, fp.spec)) {
     int tm = 0;
     const int pieces = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps,
                                        geom->n_freq, &tm);
@@ -662,7 +665,7 @@ syn_status syn_forward(const syn_geom* geom, const syn_field* field, float* maps
       return fail(SYN_EWORKSPACE, "workspace smaller than syn_workspace_bytes(...,1) or misaligned");
     phi_end = static_cast<double*>(ws);
     if (fp.ff) em_end = reinterpret_cast<double*>(static_cast<char*>(ws) + ws_phi_bytes(ga.npix));
-    if (has_snapshots(field->kind)) {
+    if (has_snapshots(field->kind, fp.spec)) {
       int tm = 0;
       const int p = lanes_for_shape(SYN_KERNEL_ADJOINT, field->kind, ga.npix, ga.n_steps,
                                     geom->n_freq, &tm);
@@ -747,7 +750,7 @@ syn_status syn_adjoint(const syn_geom* geom, const syn_field* field, const float
   double* phi_end = reinterpret_cast<double*>(w);
   double* em_end = fp.ff ? reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix)) : nullptr;
   double* partials = reinterpret_cast<double*>(w + ws_phi_bytes(ga.npix) * (fp.ff ? 2 : 1));
-  if (pieces >= 2 && has_snapshots(field->kind)) {
+  if (pieces >= 2 && has_snapshots(field->kind, fp.spec)) {
     // the forward stored the sums at the ends of `pieces` pieces: split the
     // sightlines the same way and skip the pre-pass over each piece
     S = pieces;

@@ -106,8 +106,10 @@ __global__ __launch_bounds__(256) void k_adjoint(GeomArgs g, FreqArgs fa, EmitAr
     stage = lds_dyn + 5 * box_cap + (threadIdx.x >> 6) * (kStageRecs * kStageFloats);
   }
   // a theta-only pass walks contiguous pieces too (from the forward's piece
-  // snapshots, or a pre-pass without them)
-  adj_lane<F, S, MF, THETA, GRID, FF, SP, THETA>(g, fa, ea, fld, q, sub, valid, dmaps,
+  // snapshots, or a pre-pass without them), except under a broken power law,
+  // whose reverse pass measured faster with interleaved steps
+  constexpr bool PIECES = THETA && SP != kSpecBroken;
+  adj_lane<F, S, MF, THETA, GRID, FF, SP, PIECES>(g, fa, ea, fld, q, sub, valid, dmaps,
                                           MapAddr{g.npix, 0}, phi_end, tb, gbn, gc, &box, stage,
                                           em_end);
   if constexpr (GRID) {
