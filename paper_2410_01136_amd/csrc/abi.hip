@@ -486,8 +486,7 @@ void set_snapshots(sm::FieldPack* fp, int kind, double* snap, int pieces, int n_
     a.snap_nq = nq;
   };
   if (kind == SYN_FIELD_GRID) put(fp->grid);
-  if (kind == SYN_FIELD_MODEL16) put(fp->m16);
-  if (kind == SYN_FIELD_WMAP) put(fp->wmap);
+  if (kind == SYN_FIELD_MODEL16 || kind == SYN_FIELD_WMAP) put(fp->snap);
 }
 
 size_t snap_bytes(int64_t npix, int pieces, int n_freq, bool ff) {

@@ -258,10 +258,10 @@ static hipError_t launch_adjoint_t(const GeomArgs& g, const FreqArgs& fa, const 
   if constexpr (SP != kSpecGridAlpha) {
     switch (fp.kind) {
       case kModel16:
-        return adj_s<FF, SP>(g, fa, ea, Model16NoGrid{Model16{fp.m16}}, S, dmaps, phi_end, em_end,
+        return adj_s<FF, SP>(g, fa, ea, Model16NoGrid{Model16{fp.m16, fp.snap}}, S, dmaps, phi_end, em_end,
                              partials, dtheta, nullptr, nullptr, st);
       case kWmap:
-        return adj_s<FF, SP>(g, fa, ea, WmapNoGrid{Wmap{fp.wmap}}, S, dmaps, phi_end, em_end,
+        return adj_s<FF, SP>(g, fa, ea, WmapNoGrid{Wmap{fp.wmap, fp.snap}}, S, dmaps, phi_end, em_end,
                              partials, dtheta, nullptr, nullptr, st);
       default: break;
     }

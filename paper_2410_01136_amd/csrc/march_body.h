@@ -63,11 +63,18 @@ constexpr bool exact_freqs(int MF) { return MF == 1 || MF == 3; }
 // frequency as well.
 //
 // PC (grid, spiral-disk and WMAP fields): also store the piece snapshots of
-// fld.p (the running sums at the piece ends of a reverse pass in pieces), so
+// the field (the running sums at the piece ends of a reverse pass in pieces), so
 // that pass needs no pre-pass over its pieces.
 template <class F>
 constexpr bool kHasSnapshots = std::is_base_of_v<Grid, F> || std::is_base_of_v<Model16, F> ||
                                std::is_base_of_v<Wmap, F>;
+// The snapshot fields of a field: in GridArgs for grids, beside the arguments
+// (SnapArgs) for the analytic and WMAP fields.
+template <class F>
+__host__ __device__ inline const auto& snap_args(const F& f) {
+  if constexpr (std::is_base_of_v<Grid, F>) return f.p;
+  else return f.sn;
+}
 
 template <class F, int S, int MF, bool FF = false, int SP = kSpecPower, bool PC = false, class FA>
 __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs& ea, const F& fld,
@@ -194,13 +201,13 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     if constexpr (PC) {
       // piece ends inside this chunk (those at or beyond the last step are
       // written after the loop, from the totals): sums over the steps before b
-      for (; pc_k <= fld.p.pieces && pc_k * fld.p.piece_len <= c0 + S &&
-             pc_k * fld.p.piece_len < g.n_steps;
+      const auto& sa = snap_args(fld);
+      for (; pc_k <= sa.pieces && pc_k * sa.piece_len <= c0 + S && pc_k * sa.piece_len < g.n_steps;
            ++pc_k) {
         const int k = pc_k;
-        const int b = k * fld.p.piece_len;
+        const int b = k * sa.piece_len;
         const bool before = n < b;
-        double* out = fld.p.snap + (int64_t)(k - 1) * fld.p.snap_nq * ma.stride + ma.off + ray.ring;
+        double* out = sa.snap + (int64_t)(k - 1) * sa.snap_nq * ma.stride + ma.off + ray.ring;
         const int64_t st = ma.stride;
         const double phib = S == 1 ? carry : carry0 + group_bcast<S>(fincl, b - 1 - c0);
         if (valid && sub == 0) out[0] = phib;
@@ -275,9 +282,9 @@ __device__ inline void fwd_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     if (valid && sub == 0) {
       const int nf = fa.n_freq;
       const int64_t st = ma.stride;
-      for (int k = max(1, (g.n_steps + fld.p.piece_len - 1) / fld.p.piece_len); k <= fld.p.pieces;
-           ++k) {
-        double* out = fld.p.snap + (int64_t)(k - 1) * fld.p.snap_nq * st + ma.off + ray.ring;
+      const auto& sa = snap_args(fld);
+      for (int k = max(1, (g.n_steps + sa.piece_len - 1) / sa.piece_len); k <= sa.pieces; ++k) {
+        double* out = sa.snap + (int64_t)(k - 1) * sa.snap_nq * st + ma.off + ray.ring;
         out[0] = carry;
 #pragma unroll
         for (int f = 0; f < MF; ++f) {
@@ -379,15 +386,16 @@ __device__ inline void adj_lane(const GeomArgs& g, const FA& fa, const EmitArgs&
     const int len = (g.n_steps + S - 1) / S;
     n_lo = min(sub * len, g.n_steps);
     n_hi = min(n_lo + len, g.n_steps);
-    if (fld.p.snap != nullptr) {
+    const auto& sa = snap_args(fld);
+    if (sa.snap != nullptr) {
       // The forward stored the running sums at every piece end (S pieces of this
       // length): the piece's own sums are differences of those at its two ends,
       // with the absolute phase and attenuation already applied, so
       //   B_k = Im(sum_f k_f dP_f),  X_k = -sum_f kd_f (gi_f dU_f + cf_f dV_f + Re(h_f dP_f)).
       const int nf = fa.n_freq;
       const int64_t st = g.npix;
-      const double* hi_end = fld.p.snap + (int64_t)sub * fld.p.snap_nq * st + ray.ring;
-      const double* lo_end = fld.p.snap + (int64_t)(sub > 0 ? sub - 1 : 0) * fld.p.snap_nq * st + ray.ring;
+      const double* hi_end = sa.snap + (int64_t)sub * sa.snap_nq * st + ray.ring;
+      const double* lo_end = sa.snap + (int64_t)(sub > 0 ? sub - 1 : 0) * sa.snap_nq * st + ray.ring;
       auto lo_at = [&](int j) { return sub > 0 ? lo_end[j * st] : 0.0; };
       double Bk = 0.0, Xk = 0.0;
 #pragma unroll

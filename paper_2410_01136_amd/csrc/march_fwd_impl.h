@@ -10,7 +10,7 @@
 
 namespace sm {
 
-// PC: also store the piece snapshots (fld.p.snap; grid, spiral-disk and WMAP fields).
+// PC: also store the piece snapshots (snap_args; grid, spiral-disk and WMAP fields).
 template <class F, int S, int MF, bool FF, int SP, bool PC = false>
 __global__ __launch_bounds__(256) void k_forward(GeomArgs g, FreqArgs fa, EmitArgs ea, F fld,
                                                  float* __restrict__ maps,
@@ -43,12 +43,12 @@ static hipError_t fwd_mf_pc(const GeomArgs& g, const FreqArgs& fa, const EmitArg
 }
 
 // grid, spiral-disk and WMAP fields write piece snapshots when asked to
-// (fld.p.snap set)
+// (snap_args(fld).snap set)
 template <bool FF, int SP, class F, int S>
 static hipError_t fwd_mf(const GeomArgs& g, const FreqArgs& fa, const EmitArgs& ea, const F& f,
                          float* maps, double* phi_end, double* em_end, hipStream_t st) {
   if constexpr (kHasSnapshots<F>) {
-    if (f.p.snap != nullptr) return fwd_mf_pc<FF, SP, true, F, S>(g, fa, ea, f, maps, phi_end, em_end, st);
+    if (snap_args(f).snap != nullptr) return fwd_mf_pc<FF, SP, true, F, S>(g, fa, ea, f, maps, phi_end, em_end, st);
   }
   return fwd_mf_pc<FF, SP, false, F, S>(g, fa, ea, f, maps, phi_end, em_end, st);
 }
@@ -81,9 +81,9 @@ static hipError_t launch_forward_t(const GeomArgs& g, const FreqArgs& fa, const 
   }
   if constexpr (SP != kSpecGridAlpha) {
     switch (fp.kind) {
-      case kModel16: return fwd_s<FF, SP>(g, fa, ea, Model16{fp.m16}, S, maps, phi_end, em_end, st);
+      case kModel16: return fwd_s<FF, SP>(g, fa, ea, Model16{fp.m16, fp.snap}, S, maps, phi_end, em_end, st);
       case kSphere: return fwd_s<FF, SP>(g, fa, ea, Sphere{fp.sph}, S, maps, phi_end, em_end, st);
-      case kWmap: return fwd_s<FF, SP>(g, fa, ea, Wmap{fp.wmap}, S, maps, phi_end, em_end, st);
+      case kWmap: return fwd_s<FF, SP>(g, fa, ea, Wmap{fp.wmap, fp.snap}, S, maps, phi_end, em_end, st);
       default: break;
     }
   }

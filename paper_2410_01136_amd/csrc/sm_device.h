@@ -170,6 +170,7 @@ __device__ inline float smooth_x(const GeomArgs& g, const Ray& r, double s, int 
 // (reciprocal scale lengths pre-multiplied by log2(e)).
 struct Model16 {
   M16Args p;
+  SnapArgs sn;  // piece snapshots of a forward (snap nullptr: none)
 
   __device__ inline FV eval(float x, float y, float z) const {
     const float rho = fsqrt(x * x + y * y);
@@ -977,6 +978,7 @@ struct GridL : GridB {
 // disk.  tanh and sech^2 come from one exp2 each.
 struct Wmap {
   WmapArgs p;
+  SnapArgs sn;  // piece snapshots of a forward (snap nullptr: none)
 
   __device__ inline FV eval(float x, float y, float z) const {
     const float rho = fsqrt(x * x + y * y);

@@ -63,6 +63,7 @@ struct FieldPack {
   SphereArgs sph;
   MlpArgs mlp;
   WmapArgs wmap;
+  SnapArgs snap;  // piece snapshots of the analytic and WMAP fields (grids: in grid)
   bool ff = false;  // free-free emission and absorption (constants in FreqArgs)
   int spec = kSpecPower;  // kSpecBroken: broken power law (table and constants in EmitArgs, FreqArgs)
 };

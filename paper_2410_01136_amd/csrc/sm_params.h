@@ -25,10 +25,6 @@ struct M16Args {
   float C0, invhr, invhz, l2_invhr, l2_invhz;
   float n0, invhne, l2_invhne, l2_kappa;
   float log2_rsun;
-  // piece snapshots of a forward that a reverse pass will follow (as in
-  // GridArgs; snap nullptr: none)
-  double* snap;
-  int32_t pieces, piece_len, snap_nq;
 };
 
 // WMAP field of Sec. 3.1 (FP32 constants derived on the host).
@@ -37,7 +33,12 @@ struct WmapArgs {
   float rin, rout;
   float C0, invhr, invhz;
   float n0, invhne, l2_invhne, l2_kappa;
-  // piece snapshots (as in GridArgs; snap nullptr: none)
+};
+
+// Piece snapshots of the analytic and WMAP fields (as in GridArgs; snap
+// nullptr: none).  Kept beside their argument blocks, not in them, so that the
+// batch kernels' per-set descriptors do not carry them.
+struct SnapArgs {
   double* snap;
   int32_t pieces, piece_len, snap_nq;
 };
@@ -53,7 +54,7 @@ struct GridArgs {
   uint32_t bn_bytes, c_bytes;
   uint32_t sy16, sz16, sy4, sz4;
   // Piece snapshots of a forward that a reverse pass in pieces will follow
-  // (nullptr: none).  The analytic and WMAP argument blocks carry the same.  The reverse pass cuts each sightline into `pieces`
+  // (nullptr: none).  The analytic and WMAP fields carry the same (SnapArgs).  The reverse pass cuts each sightline into `pieces`
   // contiguous pieces of `piece_len` steps; at each piece end b_k = k piece_len
   // (k = 1 .. pieces, capped at n_steps) the forward stores, per pixel, the
   // running sums over the steps before b_k: the Faraday sum, per frequency the
