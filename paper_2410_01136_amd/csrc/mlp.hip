@@ -51,15 +51,6 @@ __device__ inline f32x16 mfma(f16x8 a, f16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-// Cubic-gated linear unit on a pair of FP16 values: x S(s), s = clamp(x / 4 +
-// 1/2, 0, 1), S = s^2 (3 - 2 s); each operation rounds to FP16 (x / 4 and 2 s
-// are exact, so the fused forms round once like the separate ones).
-__device__ inline h2v act_cubic2(h2v x) {
-  h2v s = x * (h2v)(0.25f16) + (h2v)(0.5f16);
-  s = __builtin_elementwise_min(__builtin_elementwise_max(s, (h2v)(0.0f16)), (h2v)(1.0f16));
-  return x * (s * s * ((h2v)(3.0f16) - (h2v)(2.0f16) * s));
-}
-
 // sin and cos of 2 pi t in FP32: reduced to [-1/2, 1/2] turn, then the
 // hardware sine and cosine (argument in turns).
 __device__ inline void sincos_turns_f(float t, float* sn, float* cs) {
@@ -94,40 +85,68 @@ __device__ inline void fourier_operand(const float* fq, float x, float y, float 
 
 // Activation of a 32-row accumulator block (bias included), converted into the
 // next layer's B operands (two k-steps per row block): the accumulator rounded
-// to FP16 and the gate applied on packed pairs.
+// to FP16 and the gate applied on packed pairs.  The gate runs stage by stage
+// over the block's 8 pairs, so that consecutive instructions are independent;
+// pair by pair, each packed FP16 instruction would read the one before it, a
+// dependence this chip makes wait a cycle.
 __device__ inline void activate(const f32x16& acc, f16x8* op2) {
+  h2v x[8], s[8], t[8];
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
+  for (int p = 0; p < 8; ++p) {
+    x[p].x = (_Float16)acc[2 * p];
+    x[p].y = (_Float16)acc[2 * p + 1];
+  }
+  // cubic-gated linear unit x S(s), s = clamp(x / 4 + 1/2, 0, 1), S = s^2 (3 - 2 s);
+  // each operation rounds to FP16 (x / 4 and 2 s are exact, so the fused forms
+  // round once like the separate ones)
 #pragma unroll
-    for (int i = 0; i < 8; i += 2) {
-      h2v x;
-      x.x = (_Float16)acc[8 * j + i];
-      x.y = (_Float16)acc[8 * j + i + 1];
-      const h2v y = act_cubic2(x);
-      op2[j][i] = y.x;
-      op2[j][i + 1] = y.y;
-    }
+  for (int p = 0; p < 8; ++p)
+    s[p] = __builtin_elementwise_min(
+        __builtin_elementwise_max(x[p] * (h2v)(0.25f16) + (h2v)(0.5f16), (h2v)(0.0f16)),
+        (h2v)(1.0f16));
+#pragma unroll
+  for (int p = 0; p < 8; ++p) t[p] = (h2v)(3.0f16) - (h2v)(2.0f16) * s[p];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) s[p] = s[p] * s[p];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) t[p] = s[p] * t[p];
+  // pair p holds accumulator rows 2p, 2p + 1: elements 2 (p % 4), +1 of k-step p / 4
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const h2v y = x[p] * t[p];
+    op2[p >> 2][2 * (p & 3)] = y.x;
+    op2[p >> 2][2 * (p & 3) + 1] = y.y;
+  }
 }
 
 // One layer for both point blocks: X (block A) and XB (block B) in, YA and YB
-// out, one 32-row block at a time; each weight fragment feeds both blocks.  The
-// scheduling barrier keeps the compiler from hoisting the next row block's
-// fragment loads above the activation (which would need more registers than
-// two wavefronts per SIMD have).
+// out, one 32-row block at a time; each weight fragment feeds both blocks.
+// Fragments are loaded kPrefetch k-steps ahead of their products; the
+// scheduling barriers hold that order (at its register limit the compiler
+// would otherwise load each fragment just before its products and wait out
+// the LDS latency) and keep the next row block's loads below the activation.
+constexpr int kPrefetch = 2;
+
 template <int KS>
 __device__ inline void pair_layer(const f16x8* W, const f32x16* bias, int lane, int h,
                                   const f16x8* XA, const f16x8* XB, f16x8* YA, f16x8* YB) {
+  constexpr int D = KS < kPrefetch ? KS : kPrefetch;
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
+    const f16x8* Wr = W + rb * KS * 64 + lane;
     // the bias enters as the first product's addend (FP32, no vector instruction)
     const f32x16 c = bias[rb * 2 + h];
-    const f16x8 w0 = W[rb * KS * 64 + lane];
-    f32x16 a = mfma(w0, XA[0], c), b = mfma(w0, XB[0], c);
+    f16x8 w[KS];
+#pragma unroll
+    for (int t = 0; t <= D && t < KS; ++t) w[t] = Wr[t * 64];
+    f32x16 a = mfma(w[0], XA[0], c), b = mfma(w[0], XB[0], c);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 1; t < KS; ++t) {
-      const f16x8 w = W[(rb * KS + t) * 64 + lane];
-      a = mfma(w, XA[t], a);
-      b = mfma(w, XB[t], b);
+      if (t + D < KS) w[t + D] = Wr[(t + D) * 64];
+      a = mfma(w[t], XA[t], a);
+      b = mfma(w[t], XB[t], b);
+      __builtin_amdgcn_sched_barrier(0);
     }
     activate(a, &YA[2 * rb]);
     activate(b, &YB[2 * rb]);
