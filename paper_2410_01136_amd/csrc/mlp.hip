@@ -110,7 +110,7 @@ __device__ inline void activate(const f32x16& acc, f16x8* op2) {
   for (int p = 0; p < 8; ++p) s[p] = s[p] * s[p];
 #pragma unroll
   for (int p = 0; p < 8; ++p) t[p] = s[p] * t[p];
-  // pair p holds accumulator rows 2p, 2p + 1: elements 2 (p % 4), +1 of k-step p / 4
+  // pair p is accumulator registers 2p, 2p + 1: elements 2 (p % 4), +1 of k-step p / 4
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     const h2v y = x[p] * t[p];
